@@ -1,0 +1,207 @@
+/*
+ * slpic.h -- C ABI of the MI355X speed-limited PIC / Monte Carlo collision
+ * particle step for a 1D3V electron / Ar+ cascade across a gas-filled gap.
+ *
+ * Method: Theis, Werner, Jenkins & Cary, "Computing the Paschen curve for
+ * argon with speed-limited particle-in-cell simulation".  One call to
+ * slpic_step advances every marker of every instance by one time step:
+ *   - speed-limited motion, Eqs. (8)-(9) with beta(v) of Eq. (11), integrated
+ *     exactly for the field gathered at the start of the step;
+ *   - null-collision Monte Carlo collisions with the SLPIC rate of
+ *     Eqs. (15)-(16) (elastic, excitation, ionization with new electron and
+ *     ion markers; constant cross-section Ar+ charge exchange);
+ *   - ion-induced secondary electron emission at the cathode (Sec. IV);
+ *   - linear-weighting charge deposit with density weight w_p = beta w_j
+ *     (Sec. III) and a 1D Poisson solve in FP64.
+ *
+ * Conventions for every entry point:
+ *   - return value: SLPIC_OK (0) or a negative slpic_status; no exception
+ *     crosses the ABI; slpic_last_error() gives a readable message;
+ *   - "host" pointers are read (or written) before the call returns and are
+ *     not retained; "device" pointers are borrowed for the handle's lifetime;
+ *   - the handle is bound to one HIP stream given at create time, launches
+ *     all work on it, and is not thread-safe;
+ *   - units are SI except the pressure (Torr) and energies (eV);
+ *   - the cathode is at x = 0 (potential 0), the anode at x = d (potential V).
+ */
+#ifndef SLPIC_H
+#define SLPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SLPIC_ABI_VERSION 1
+
+typedef enum slpic_status {
+  SLPIC_OK = 0,
+  SLPIC_INVALID_ARG = -1,        /* a parameter is out of range */
+  SLPIC_WORKSPACE_TOO_SMALL = -2,
+  SLPIC_CAPACITY_EXCEEDED = -3,  /* a species outgrew its capacity; the
+                                    excess markers were dropped */
+  SLPIC_NONFINITE_STATE = -4,    /* a marker reached a non-finite state and
+                                    was dropped */
+  SLPIC_HIP_ERROR = -5,
+  SLPIC_NU_BOUND_EXCEEDED = -6,  /* a collision rate exceeded the
+                                    null-collision bound */
+  SLPIC_NOT_BUILT = -7
+} slpic_status;
+
+/* channel kinds, seed modes, species, flags */
+enum { SLPIC_ELASTIC = 0, SLPIC_EXCITATION = 1, SLPIC_IONIZATION = 2 };
+enum { SLPIC_SEED_NONE = 0, SLPIC_SEED_CATHODE = 1, SLPIC_SEED_MAXWELL_CELL0 = 2 };
+enum { SLPIC_ELECTRON = 0, SLPIC_ION = 1 };
+/* SLPIC_FLAG_PRODUCTS_AT_REST: both electrons of an ionization leave at rest
+ * (a closed-form Townsend test gas, not physical argon) */
+enum { SLPIC_FLAG_PRODUCTS_AT_REST = 1 };
+
+/* Settings shared by all instances of a handle. */
+typedef struct slpic_config {
+  int32_t precision;     /* 32: FP32 particles, FP64 field and totals;
+                            64: FP64 throughout */
+  uint32_t seed;         /* Philox key word 0 (word 1 = instance index) */
+  uint32_t flags;        /* SLPIC_FLAG_* */
+  int32_t resort_period; /* steps between cell sorts of the markers, 0 = off */
+  double T_gas;          /* neutral temperature [K], > 0 */
+  double area;           /* electrode area [m^2], > 0 */
+  double w_j0;           /* initial flux weight w_j of every marker, > 0 */
+  double cfl;            /* v0 dt / dx in (0, 1] when dt is derived */
+  double ion_B_eV;       /* ionization energy-sharing parameter [eV] */
+  double kTe_seed_eV;    /* temperature of Maxwellian seed electrons [eV] */
+} slpic_config;
+
+/* One independent gap (p, d, V). */
+typedef struct slpic_instance {
+  double d;          /* gap [m], > 0 */
+  double p_torr;     /* neutral pressure [Torr], >= 0 */
+  double V;          /* anode potential [V] */
+  double gamma_se;   /* secondary electrons per ion reaching the cathode,
+                        in [0, 1] */
+  double v_limit;    /* speed limit v0 [m/s]; <= 0: sqrt(2 e |V| / m_Ar)
+                        (Sec. IV); +INFINITY: beta == 1, plain PIC */
+  double dt;         /* time step [s]; <= 0: cfl dx / v0, or for plain PIC
+                        cfl dx / sqrt(2 e |V| / m_e) (Sec. IV) */
+  int32_t cells;     /* >= 2 */
+  int32_t seed_mode; /* SLPIC_SEED_* */
+  int64_t n_seed;    /* seed electrons (ids 0 .. n_seed-1) */
+  int64_t n_target;  /* population-control target; 0 = off.  Before each
+                        step with N markers: N > 2 n_target keeps each output
+                        marker with probability 1/2 and doubles w_j;
+                        0 < N < n_target/2 clones each and halves w_j */
+  int64_t capacity;  /* marker slots per species, >= n_seed */
+} slpic_instance;
+
+/* Electron-neutral cross sections: piecewise linear in energy between
+ * log-uniform nodes e_j = e_min (e_max/e_min)^(j/(n_grid-1)), constant
+ * beyond either end, zero below the channel threshold. */
+typedef struct slpic_xs {
+  int32_t n_chan;               /* 0 .. 8 */
+  int32_t n_grid;               /* >= 2 */
+  const double* energies;       /* host [n_grid] eV, log-uniform, increasing */
+  const double* sigma;          /* host [n_chan][n_grid] m^2, >= 0 */
+  const double* threshold_eV;   /* host [n_chan] */
+  const int32_t* kind;          /* host [n_chan] SLPIC_ELASTIC/EXCITATION/IONIZATION */
+  const double* fixed_prob;     /* host [n_chan] or NULL.  If given, channel k
+                                   happens with this constant per-step
+                                   probability (fixed-event test mode) */
+  double fixed_prob_cx;         /* fixed-event mode: per-step Ar+ charge
+                                   exchange probability */
+  double sigma_cx;              /* Ar+ charge exchange cross section [m^2] */
+} slpic_xs;
+
+/* Per-step statistics of one instance (one row per step). */
+typedef struct slpic_stats {
+  int64_t step;            /* steps completed */
+  int64_t n_e, n_i;        /* markers after the step */
+  int64_t n_in;            /* markers entering the step */
+  double w_e, w_i;         /* sum of density weights beta w_j per species */
+  double w_j;              /* flux weight after the step */
+  int64_t elastic, excitation, ionization, cx;
+  int64_t abs_e_cathode, abs_e_anode, abs_i_cathode, abs_i_anode;
+  int64_t see;             /* secondary electrons emitted */
+  int64_t roulette;        /* markers removed by population control */
+  int64_t split;           /* markers cloned by population control */
+  int64_t err;             /* error bits raised during the step */
+} slpic_stats;
+
+typedef struct slpic_handle slpic_t;
+
+/* Device workspace size in bytes for the given setup, or 0 if invalid. */
+size_t slpic_workspace_bytes(const slpic_config* cfg, const slpic_instance* inst,
+                             int n_inst, const slpic_xs* xs);
+
+/* Create a handle for n_inst instances (1 .. 1024).  All host arrays are
+ * copied.  dev_workspace (device, >= slpic_workspace_bytes, 256-byte
+ * aligned) and hip_stream (a hipStream_t, NULL = default stream) are
+ * borrowed until slpic_destroy.  Seeds each instance, solves its initial
+ * field and synchronizes the stream.  On failure *out is NULL. */
+int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
+                 const slpic_xs* xs, void* dev_workspace, size_t ws_bytes,
+                 void* hip_stream, slpic_t** out);
+
+/* Enqueue n_steps steps of every instance on the handle's stream and return
+ * without waiting.  Errors raised on the device are reported by slpic_sync. */
+int slpic_step(slpic_t* h, int n_steps);
+
+/* Wait for the stream; return the first device error raised since the last
+ * call (SLPIC_CAPACITY_EXCEEDED, SLPIC_NONFINITE_STATE,
+ * SLPIC_NU_BOUND_EXCEEDED) or SLPIC_OK. */
+int slpic_sync(slpic_t* h);
+
+/* Use a captured HIP graph of period_steps steps for slpic_step (1) or plain
+ * launches (0).  Default 0. */
+int slpic_use_graph(slpic_t* h, int enable);
+
+/* Replace the markers of one species of one instance with n host-side
+ * markers (x = (cell + off) dx, cell in [0, cells), off in [0, 1)), then
+ * rebuild that handle's fields.  Synchronizes. */
+int slpic_load_markers(slpic_t* h, int inst, int species, int64_t n,
+                       const int32_t* cell, const double* off, const double* vx,
+                       const double* vy, const double* vz, const uint64_t* id);
+
+/* Number of markers of one species of one instance.  Synchronizes. */
+int slpic_count(slpic_t* h, int inst, int species, int64_t* n);
+
+/* Copy one species of one instance to host arrays of at least max_n
+ * entries (NULL to skip an array); *n receives the count.  Synchronizes. */
+int slpic_read_markers(slpic_t* h, int inst, int species, int64_t max_n,
+                       int64_t* n, int32_t* cell, double* off, double* vx,
+                       double* vy, double* vz, uint64_t* id);
+
+/* Node arrays (cells + 1 each, host, NULL to skip) of one instance: charge
+ * density [C/m^3], potential [V] and field [V/m].  Synchronizes. */
+int slpic_read_fields(slpic_t* h, int inst, double* rho, double* phi, double* E);
+
+/* Statistics rows of one instance for steps first_step+1 .. first_step+n
+ * (row k describes step first_step+k+1), from a ring of the last 4096 steps.
+ * Synchronizes. */
+int slpic_read_stats(slpic_t* h, int inst, int64_t first_step, int n,
+                     slpic_stats* rows);
+
+/* Derived scalars of one instance: dx, dt, v0, n_g, nu_max_e, nu_max_cx,
+ * w_j, step (8 doubles, host).  Synchronizes. */
+int slpic_scalars(slpic_t* h, int inst, double* out8);
+
+/* Steps completed by the handle (host-side count, no synchronization). */
+int64_t slpic_steps_done(const slpic_t* h);
+
+/* Message describing the last failure on this handle (or of the last
+ * create when h is NULL). */
+const char* slpic_last_error(const slpic_t* h);
+
+/* Wait for the stream and release host-side resources; the workspace stays
+ * owned by the caller. */
+void slpic_destroy(slpic_t* h);
+
+/* Test hook: Philox4x32-10 on the device.  ctr is device [n][4] uint32, out
+ * device [n][4]; key (key0, key1).  Enqueued on stream, not waited for. */
+int slpic_philox_device(const uint32_t* ctr, uint32_t key0, uint32_t key1,
+                        int64_t n, uint32_t* out, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLPIC_H */

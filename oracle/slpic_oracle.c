@@ -235,7 +235,12 @@ double or_free_flight(double vx, double vperp, double a, double dt, double v0,
         double s = s0 + delta;
         double hp = sqrt(s * s + c * c) / v0;
         if (hp < 1.0) hp = 1.0;
-        double dn = delta - f / hp;
+        double step = -f / hp;
+        if (fabs(step) <= 1e-16 * delta) { /* Newton has converged */
+          if (delta + step > lo && delta + step < hi) delta += step;
+          break;
+        }
+        double dn = delta + step;
         if (!(dn > lo && dn < hi)) dn = 0.5 * (lo + hi);
         if (dn == delta) break;
         delta = dn;
@@ -271,10 +276,13 @@ double or_sigma(const or_sim* s, int k, double eps) {
 
 /* ------------------------------------------------------------------ */
 /* Scatter laws.  Vahedi & Surendra elastic/ionization angle:
- * cos chi = (2 + eps - 2 (1+eps)^u) / eps  (eps in eV; isotropic as eps->0). */
+ * cos chi = (2 + eps - 2 (1+eps)^u) / eps  (eps in eV; isotropic as eps->0),
+ * evaluated as 1 - 2 [(1+eps)^u - 1] / eps with the exact identity
+ * (1+eps)^u - 1 = expm1(u log1p(eps)): the printed form loses all its digits
+ * to cancellation for energies far below 1 eV. */
 double or_vs_cos_chi(double eps, double u) {
   if (eps <= 0.0) return 1.0 - 2.0 * u;
-  return (2.0 + eps - 2.0 * pow(1.0 + eps, u)) / eps;
+  return 1.0 - 2.0 * expm1(u * log1p(eps)) / eps;
 }
 
 /* Vahedi & Surendra ejected-electron energy for available energy eps_av */
@@ -357,18 +365,18 @@ static void note_margin(or_sim* s, marker* m, double margin) {
 /* Field: charge deposit with linear weights, density weight w_p = beta w_j
  * (Sec. III), and the Dirichlet Poisson problem phi(0) = 0, phi(d) = V. */
 void or_poisson(int N, double dx, double V, const double* rho, double* phi, double* E) {
-  /* interior nodes 1..N-1:  -phi[i-1] + 2 phi[i] - phi[i+1] = rho[i] dx^2 / eps0,
-   * solved by the Thomas algorithm */
+  /* By linearity phi = V i/N + psi, where psi solves the same difference
+   * equation with psi[0] = psi[N] = 0 and the space charge as its source:
+   *   -psi[i-1] + 2 psi[i] - psi[i+1] = rho[i] dx^2 / eps0,  i = 1..N-1,
+   * solved by the Thomas algorithm.  Differencing only psi keeps the
+   * vacuum field -V/d exact instead of recovering it from differences of
+   * a potential of size V. */
   int m = N - 1;
+  double* psi = (double*)calloc((size_t)N + 1, sizeof(double));
   double* cp = (double*)malloc(sizeof(double) * (m > 0 ? m : 1));
   double* dp = (double*)malloc(sizeof(double) * (m > 0 ? m : 1));
-  phi[0] = 0.0;
-  phi[N] = V;
   for (int k = 0; k < m; ++k) {
-    int i = k + 1;
-    double b = rho[i] * dx * dx / EPS0;
-    if (i == 1) b += phi[0];
-    if (i == N - 1) b += phi[N];
+    double b = rho[k + 1] * dx * dx / EPS0;
     double diag = 2.0, off = -1.0;
     if (k == 0) {
       cp[k] = off / diag;
@@ -379,15 +387,20 @@ void or_poisson(int N, double dx, double V, const double* rho, double* phi, doub
       dp[k] = (b - off * dp[k - 1]) / den;
     }
   }
-  if (m > 0) phi[m] = dp[m - 1];
-  for (int k = m - 2; k >= 0; --k) phi[k + 1] = dp[k] - cp[k] * phi[k + 2];
+  if (m > 0) psi[m] = dp[m - 1];
+  for (int k = m - 2; k >= 0; --k) psi[k + 1] = dp[k] - cp[k] * psi[k + 2];
   free(cp);
   free(dp);
+  for (int i = 0; i <= N; ++i) phi[i] = V * (double)i / (double)N + psi[i];
+  phi[0] = 0.0;
+  phi[N] = V;
   /* E = -dphi/dx: central differences inside, Gauss's law over the half
    * cell at each electrode */
-  for (int i = 1; i < N; ++i) E[i] = (phi[i - 1] - phi[i + 1]) / (2.0 * dx);
-  E[0] = (phi[0] - phi[1]) / dx - rho[0] * dx / (2.0 * EPS0);
-  E[N] = (phi[N - 1] - phi[N]) / dx + rho[N] * dx / (2.0 * EPS0);
+  double Ev = -V / ((double)N * dx);
+  for (int i = 1; i < N; ++i) E[i] = Ev + (psi[i - 1] - psi[i + 1]) / (2.0 * dx);
+  E[0] = Ev + (psi[0] - psi[1]) / dx - rho[0] * dx / (2.0 * EPS0);
+  E[N] = Ev + (psi[N - 1] - psi[N]) / dx + rho[N] * dx / (2.0 * EPS0);
+  free(psi);
 }
 
 static void locate(const or_sim* s, double x, int* ci, double* f) {

@@ -1,0 +1,771 @@
+// Host side of the slpic C ABI (include/slpic.h): validation, the derived
+// per-instance constants, the device workspace layout, launches and graph
+// capture, and the host readers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/slpic.h"
+#include "slpic_internal.hpp"
+
+namespace slpic {
+template <typename R> hipError_t launch_gen(const Ctx<R>&, int, hipStream_t);
+template <typename R>
+hipError_t launch_seed(const Ctx<R>&, int, int, int64_t, double, uint32_t, hipStream_t);
+template <typename R> hipError_t occupancy_gen(int*);
+hipError_t launch_philox_test(const uint32_t*, uint32_t, uint32_t, int64_t, uint32_t*,
+                              hipStream_t);
+}  // namespace slpic
+
+using namespace slpic;
+
+namespace {
+
+constexpr double kQE = 1.602176634e-19;
+constexpr double kKB = 1.380649e-23;
+constexpr double kME = 9.1093837015e-31;
+constexpr double kMAR = 39.948 * 1.66053906660e-27;
+constexpr double kTorr = 101325.0 / 760.0;
+
+thread_local std::string g_create_error;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Integer form of a per-step probability: with u = (2m + 1) 2^-24 for the
+// 23-bit integer m = r >> 9, u < P holds exactly for m < ceil((P 2^24 - 1)/2).
+uint32_t prob_threshold(double P) {
+  if (!(P > 0.0)) return 0u;
+  if (P >= 1.0) return 1u << 23;
+  double t = std::ceil((P * 16777216.0 - 1.0) * 0.5);
+  if (t < 0) t = 0;
+  if (t > 8388608.0) t = 8388608.0;
+  return (uint32_t)t;
+}
+
+struct Layout {
+  size_t ip, st, counts, tile_start, tile_ev, acc, E, E64, phi, rho, scratch, ring, inst_err,
+      glob, xs_e, xs_sig, xs_thr, xs_kind;
+  size_t part[2][2][6];  // [buffer][species][array]
+  size_t total;
+  int total_nodes, max_tiles;
+  int64_t total_cap;
+  std::vector<int> node, parts;
+  std::vector<int64_t> seg, cap_p;
+};
+
+// Output partitions of an instance: enough that the per-tile compaction
+// counters are spread over several addresses for large instances, one for
+// small ones.  Each partition gets an equal share of the capacity plus one
+// tile of slack for uneven growth.
+int partitions_for(int64_t cap) {
+  int p = 1;
+  while (p < MAX_PART && (int64_t)p * 2 * 4 * BLOCK <= cap) p *= 2;
+  return p;
+}
+
+bool make_layout(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
+                 const slpic_xs* xs, Layout& L) {
+  const size_t rs = cfg->precision == 64 ? 8 : 4;
+  L.node.resize(n_inst);
+  L.seg.resize(n_inst);
+  L.parts.resize(n_inst);
+  L.cap_p.resize(n_inst);
+  int nodes = 0;
+  int64_t cap = 0, tiles = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    L.node[i] = nodes;
+    nodes += inst[i].cells + 1;
+    const int P = partitions_for(inst[i].capacity);
+    const int64_t cp = (inst[i].capacity + P - 1) / P + (P > 1 ? BLOCK : 0);
+    L.parts[i] = P;
+    L.cap_p[i] = cp;
+    L.seg[i] = cap;
+    cap += (int64_t)P * cp;
+    tiles += 2 * (int64_t)P * ((cp + BLOCK - 1) / BLOCK);
+  }
+  if (tiles > 0x7fffffff) return false;
+  L.total_nodes = nodes;
+  L.total_cap = cap;
+  L.max_tiles = (int)tiles;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  L.ip = take(sizeof(InstParams) * n_inst);
+  L.st = take(sizeof(InstState) * 2 * n_inst);
+  L.counts = take(sizeof(uint32_t) * 3 * 2 * MAX_PART * (size_t)n_inst);
+  L.tile_start = take(sizeof(uint32_t) * (2 * (size_t)n_inst + 1));
+  L.tile_ev = take(sizeof(uint32_t) * NEV * (size_t)L.max_tiles);
+  L.acc = take(sizeof(unsigned long long) * 2 * NSLOT * (size_t)nodes);
+  L.E = take(rs * 2 * nodes);
+  L.E64 = take(8 * 2 * (size_t)nodes);
+  L.phi = take(8 * 2 * (size_t)nodes);
+  L.rho = take(8 * 2 * (size_t)nodes);
+  L.scratch = take(8 * (size_t)nodes);
+  L.ring = take(sizeof(StatsRow) * RING * (size_t)n_inst);
+  L.inst_err = take(sizeof(uint32_t) * n_inst);
+  L.glob = take(sizeof(Global));
+  const int ng = xs->n_grid, nc = std::max(xs->n_chan, 1);
+  L.xs_e = take(rs * ng);
+  L.xs_sig = take(rs * (size_t)ng * nc);
+  L.xs_thr = take(rs * nc);
+  L.xs_kind = take(sizeof(int32_t) * nc);
+  const size_t sizes[6] = {4, rs, rs, rs, rs, 8};
+  for (int b = 0; b < 2; ++b)
+    for (int s = 0; s < 2; ++s)
+      for (int a = 0; a < 6; ++a) L.part[b][s][a] = take(sizes[a] * (size_t)cap);
+  L.total = o;
+  return true;
+}
+
+std::string validate(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
+                     const slpic_xs* xs) {
+  if (!cfg || !inst || !xs) return "null argument";
+  if (cfg->precision != 32 && cfg->precision != 64) return "precision must be 32 or 64";
+  if (n_inst < 1 || n_inst > MAX_INST) return "n_inst must be in 1..1024";
+  if (!(cfg->T_gas > 0) || !(cfg->area > 0) || !(cfg->w_j0 > 0)) return "T_gas, area, w_j0 must be > 0";
+  if (!(cfg->cfl > 0 && cfg->cfl <= 1)) return "cfl must be in (0, 1]";
+  if (!(cfg->ion_B_eV > 0)) return "ion_B_eV must be > 0";
+  if (cfg->resort_period < 0) return "resort_period must be >= 0";
+  if (xs->n_chan < 0 || xs->n_chan > MAX_CHAN) return "n_chan must be in 0..8";
+  if (xs->n_grid < 2 || !xs->energies) return "n_grid must be >= 2";
+  if (xs->n_chan > 0 && (!xs->sigma || !xs->threshold_eV || !xs->kind)) return "missing tables";
+  const double e0 = xs->energies[0], e1 = xs->energies[xs->n_grid - 1];
+  if (!(e0 > 0) || !(e1 > e0)) return "energy grid must be positive and increasing";
+  for (int j = 0; j < xs->n_grid; ++j) {
+    const double want = e0 * std::exp(j * (std::log(e1 / e0) / (xs->n_grid - 1)));
+    if (!(std::fabs(xs->energies[j] - want) <= 1e-9 * want)) return "energy grid is not log-uniform";
+  }
+  for (int k = 0; k < xs->n_chan; ++k) {
+    if (xs->kind[k] < 0 || xs->kind[k] > 2) return "unknown channel kind";
+    if (!(xs->threshold_eV[k] >= 0)) return "thresholds must be >= 0";
+    for (int j = 0; j < xs->n_grid; ++j)
+      if (!(xs->sigma[(size_t)k * xs->n_grid + j] >= 0)) return "cross sections must be >= 0";
+  }
+  if (xs->fixed_prob) {
+    double s = 0;
+    for (int k = 0; k < xs->n_chan; ++k) {
+      if (!(xs->fixed_prob[k] >= 0)) return "fixed probabilities must be >= 0";
+      s += xs->fixed_prob[k];
+    }
+    if (s > 1.0) return "fixed probabilities sum above 1";
+    if (!(xs->fixed_prob_cx >= 0 && xs->fixed_prob_cx <= 1)) return "fixed_prob_cx outside [0,1]";
+  }
+  if (!(xs->sigma_cx >= 0)) return "sigma_cx must be >= 0";
+  for (int i = 0; i < n_inst; ++i) {
+    const slpic_instance& I = inst[i];
+    if (!(I.d > 0) || I.cells < 2 || !(I.p_torr >= 0)) return "instance needs d > 0, cells >= 2, p >= 0";
+    if (!(I.gamma_se >= 0 && I.gamma_se <= 1)) return "gamma_se must be in [0, 1]";
+    if (I.seed_mode < 0 || I.seed_mode > 2) return "unknown seed mode";
+    if (I.n_seed < 0 || I.n_target < 0) return "n_seed and n_target must be >= 0";
+    if (I.capacity < I.n_seed || I.capacity < 1 || I.capacity > 0x7fffffff)
+      return "capacity must be in [max(1, n_seed), 2^31)";
+    if (!(I.v_limit > 0) && !(std::fabs(I.V) > 0)) return "derived speed limit needs V != 0";
+    if (I.v_limit == INFINITY && !(I.dt > 0) && !(std::fabs(I.V) > 0)) return "plain PIC needs dt or V";
+  }
+  return "";
+}
+
+// Null-collision bound for electrons: nu'(eps) = n_g sigma_T(eps) min(v, v0)
+// (Eq. 16 with beta_n = 1).  On each table segment the interpolated total is
+// below the larger node value and min(v, v0) grows with energy, so
+// max(node totals) * min(v(right node), v0) bounds the segment; above the
+// table the cross section is constant up to the cap energy 2|V| + 100 eV.
+double electron_bound(const slpic_xs* xs, double n_g, double v0, double ecap) {
+  const int n = xs->n_grid, nc = xs->n_chan;
+  double best = 0.0;
+  for (int j = 0; j + 1 < n; ++j) {
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < nc; ++k) {
+      a += xs->sigma[(size_t)k * n + j];
+      b += xs->sigma[(size_t)k * n + j + 1];
+    }
+    const double v = std::sqrt(2.0 * kQE * xs->energies[j + 1] / kME);
+    best = std::max(best, std::max(a, b) * std::min(v, v0));
+  }
+  double tail = 0.0;
+  for (int k = 0; k < nc; ++k) tail += xs->sigma[(size_t)k * n + n - 1];
+  best = std::max(best, tail * std::min(std::sqrt(2.0 * kQE * ecap / kME), v0));
+  return n_g * best;
+}
+
+InstParams derive(const slpic_config* cfg, const slpic_instance& I, const slpic_xs* xs,
+                  const Layout& L, int i) {
+  InstParams P;
+  std::memset(&P, 0, sizeof(P));
+  P.d = I.d;
+  P.cells = I.cells;
+  P.dx = I.d / I.cells;
+  P.inv_dx = 1.0 / P.dx;
+  P.V = I.V;
+  P.area = cfg->area;
+  P.gamma_se = I.gamma_se;
+  if (I.v_limit == INFINITY) P.v0 = INFINITY;
+  else if (I.v_limit > 0) P.v0 = I.v_limit;
+  else P.v0 = std::sqrt(2.0 * kQE * std::fabs(I.V) / kMAR);  // Sec. IV speed limit
+  P.limited = std::isfinite(P.v0) ? 1 : 0;
+  if (I.dt > 0) P.dt = I.dt;
+  else if (P.limited) P.dt = cfg->cfl * P.dx / P.v0;
+  else P.dt = cfg->cfl * P.dx / std::sqrt(2.0 * kQE * std::fabs(I.V) / kME);
+  P.n_g = I.p_torr * kTorr / (kKB * cfg->T_gas);
+  const double ecap = std::max(xs->energies[xs->n_grid - 1], 2.0 * std::fabs(I.V) + 100.0);
+  P.nu_max_e = electron_bound(xs, P.n_g, P.v0, ecap);
+  P.sigma_cx = xs->sigma_cx;
+  P.nu_max_cx = P.n_g * xs->sigma_cx * std::min(P.v0, std::sqrt(2.0 * kQE * ecap / kMAR));
+  P.qm_e = -kQE / kME;
+  P.qm_i = kQE / kMAR;
+  P.vth_i = std::sqrt(kKB * cfg->T_gas / kMAR);
+  P.w_j0 = cfg->w_j0;
+  P.seg = L.seg[i];
+  P.cap = I.capacity;
+  P.cap_p = L.cap_p[i];
+  P.parts = L.parts[i];
+  P.n_target = I.n_target;
+  P.node = L.node[i];
+  P.t_null_e = prob_threshold(-std::expm1(-P.nu_max_e * P.dt));
+  P.t_null_cx = prob_threshold(-std::expm1(-P.nu_max_cx * P.dt));
+  P.t_see = prob_threshold(I.gamma_se);
+  if (xs->fixed_prob) {
+    double cum = 0.0;
+    for (int k = 0; k < xs->n_chan; ++k) {
+      cum += xs->fixed_prob[k];
+      P.t_fixed[k] = prob_threshold(cum);
+    }
+    P.t_fixed_cx = prob_threshold(xs->fixed_prob_cx);
+  }
+  return P;
+}
+
+}  // namespace
+
+struct slpic_handle {
+  slpic_config cfg;
+  std::vector<slpic_instance> inst;
+  std::vector<InstParams> ip;
+  int n_inst = 0;
+  Layout L;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  Ctx<float> c32;
+  Ctx<double> c64;
+  int grid = 0;
+  uint64_t gen = 0;      // generation launches issued
+  int64_t steps = 0;
+  bool use_graph = false;
+  int graph_period = 16;
+  hipGraphExec_t graph = nullptr;
+  std::string err;
+};
+
+namespace {
+
+int fail(slpic_t* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+int hip_fail(slpic_t* h, hipError_t e, const char* where) {
+  return fail(h, SLPIC_HIP_ERROR, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(h, call)                                  \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_fail(h, e_, #call); \
+  } while (0)
+
+template <typename R>
+void fill_ctx(slpic_t* h, Ctx<R>& C) {
+  const Layout& L = h->L;
+  char* w = h->ws;
+  C.ip = reinterpret_cast<const InstParams*>(w + L.ip);
+  for (int b = 0; b < 2; ++b)
+    for (int s = 0; s < 2; ++s) {
+      C.buf[b][s].cell = reinterpret_cast<int32_t*>(w + L.part[b][s][0]);
+      C.buf[b][s].off = reinterpret_cast<R*>(w + L.part[b][s][1]);
+      C.buf[b][s].vx = reinterpret_cast<R*>(w + L.part[b][s][2]);
+      C.buf[b][s].vy = reinterpret_cast<R*>(w + L.part[b][s][3]);
+      C.buf[b][s].vz = reinterpret_cast<R*>(w + L.part[b][s][4]);
+      C.buf[b][s].id = reinterpret_cast<uint64_t*>(w + L.part[b][s][5]);
+    }
+  C.st = reinterpret_cast<InstState*>(w + L.st);
+  C.counts = reinterpret_cast<uint32_t*>(w + L.counts);
+  C.tile_start = reinterpret_cast<uint32_t*>(w + L.tile_start);
+  C.tile_ev = reinterpret_cast<uint32_t*>(w + L.tile_ev);
+  C.acc = reinterpret_cast<unsigned long long*>(w + L.acc);
+  C.E = reinterpret_cast<R*>(w + L.E);
+  C.E64 = reinterpret_cast<double*>(w + L.E64);
+  C.phi = reinterpret_cast<double*>(w + L.phi);
+  C.rho = reinterpret_cast<double*>(w + L.rho);
+  C.scratch = reinterpret_cast<double*>(w + L.scratch);
+  C.ring = reinterpret_cast<StatsRow*>(w + L.ring);
+  C.inst_err = reinterpret_cast<uint32_t*>(w + L.inst_err);
+  C.g = reinterpret_cast<Global*>(w + L.glob);
+  C.xs_e = reinterpret_cast<const R*>(w + L.xs_e);
+  C.xs_sig = reinterpret_cast<const R*>(w + L.xs_sig);
+  C.xs_thr = reinterpret_cast<const R*>(w + L.xs_thr);
+  C.xs_kind = reinterpret_cast<const int32_t*>(w + L.xs_kind);
+  C.n_inst = h->n_inst;
+  C.total_nodes = L.total_nodes;
+  C.max_tiles = L.max_tiles;
+  C.grid = h->grid;
+  C.flags = h->cfg.flags;
+  C.seed = h->cfg.seed;
+  C.ion_B = h->cfg.ion_B_eV;
+  int64_t capmax = 1;
+  for (auto& I : h->inst) capmax = std::max<int64_t>(capmax, I.capacity);
+  int bits = 0;
+  while ((1ll << bits) <= capmax) ++bits;
+  // a node sums at most one unit per marker; markers produced beyond the
+  // capacity (up to 4x with ionization and splitting) still deposit
+  const int want = h->cfg.precision == 64 ? 44 : 32;
+  C.dep_shift = std::min(want, 60 - bits);
+}
+
+template <typename R>
+int upload_tables(slpic_t* h, Ctx<R>& C, const slpic_xs* xs) {
+  const int ng = xs->n_grid, nc = xs->n_chan;
+  std::vector<R> e(ng), sig((size_t)ng * std::max(nc, 1)), thr(std::max(nc, 1));
+  std::vector<int32_t> kind(std::max(nc, 1), 0);
+  for (int j = 0; j < ng; ++j) e[j] = (R)xs->energies[j];
+  for (int j = 0; j < ng; ++j)
+    for (int k = 0; k < nc; ++k) sig[(size_t)j * nc + k] = (R)xs->sigma[(size_t)k * ng + j];
+  for (int k = 0; k < nc; ++k) {
+    thr[k] = (R)xs->threshold_eV[k];
+    kind[k] = xs->kind[k];
+  }
+  C.n_chan = nc;
+  C.n_grid = ng;
+  C.fixed = xs->fixed_prob ? 1 : 0;
+  C.log_emin = (R)std::log(xs->energies[0]);
+  C.inv_dlog = (R)((ng - 1) / std::log(xs->energies[ng - 1] / xs->energies[0]));
+  HIPCHK(h, hipMemcpyAsync((void*)C.xs_e, e.data(), sizeof(R) * ng, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync((void*)C.xs_sig, sig.data(), sizeof(R) * sig.size(), hipMemcpyHostToDevice,
+                           h->stream));
+  HIPCHK(h, hipMemcpyAsync((void*)C.xs_thr, thr.data(), sizeof(R) * thr.size(), hipMemcpyHostToDevice,
+                           h->stream));
+  HIPCHK(h, hipMemcpyAsync((void*)C.xs_kind, kind.data(), sizeof(int32_t) * kind.size(),
+                           hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return SLPIC_OK;
+}
+
+int launch_gen_any(slpic_t* h, int mode) {
+  hipError_t e = h->cfg.precision == 64 ? launch_gen<double>(h->c64, mode, h->stream)
+                                        : launch_gen<float>(h->c32, mode, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "generation kernel launch");
+  h->gen += 1;
+  return SLPIC_OK;
+}
+
+Global read_global(slpic_t* h, hipError_t* e) {
+  Global G;
+  *e = hipMemcpy(&G, h->ws + h->L.glob, sizeof(Global), hipMemcpyDeviceToHost);
+  return G;
+}
+
+}  // namespace
+
+namespace {
+
+int current(slpic_t* h, Global& G, uint32_t& slot3, uint32_t& bsel) {
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  hipError_t e;
+  G = read_global(h, &e);
+  if (e != hipSuccess) return hip_fail(h, e, "read state");
+  if ((uint64_t)G.cur_gen != (h->gen & 0xffffffffull))
+    return fail(h, SLPIC_HIP_ERROR, "device generation out of step with the host");
+  slot3 = G.cur_gen % 3u;
+  bsel = G.bufsel[G.cur_gen % 2u];
+  return SLPIC_OK;
+}
+
+template <typename R>
+Soa<R> buffer_of(slpic_t* h, uint32_t bsel, int sp);
+template <>
+Soa<float> buffer_of<float>(slpic_t* h, uint32_t bsel, int sp) { return h->c32.buf[bsel][sp]; }
+template <>
+Soa<double> buffer_of<double>(slpic_t* h, uint32_t bsel, int sp) { return h->c64.buf[bsel][sp]; }
+
+size_t count_offset(slpic_t* h, uint32_t slot3, int inst, int sp, int p) {
+  return h->L.counts + sizeof(uint32_t) * ((((size_t)slot3 * h->n_inst + inst) * 2 + sp) * MAX_PART + p);
+}
+
+// Markers are spread over the instance's P partitions: marker k of a loaded
+// population goes to partition k mod P at slot k / P.
+template <typename R>
+int load_impl(slpic_t* h, int inst, int sp, int64_t n, const int32_t* cell, const double* off,
+              const double* vx, const double* vy, const double* vz, const uint64_t* id) {
+  Global G;
+  uint32_t slot3, bsel;
+  int rc = current(h, G, slot3, bsel);
+  if (rc) return rc;
+  const InstParams& P = h->ip[inst];
+  for (int64_t k = 0; k < n; ++k)
+    if (cell[k] < 0 || cell[k] >= P.cells || !(off[k] >= 0.0 && off[k] < 1.0) ||
+        !std::isfinite(vx[k]) || !std::isfinite(vy[k]) || !std::isfinite(vz[k]))
+      return fail(h, SLPIC_INVALID_ARG, "marker outside the gap or non-finite");
+  if ((n + P.parts - 1) / P.parts > P.cap_p) return fail(h, SLPIC_CAPACITY_EXCEEDED, "load exceeds capacity");
+  const Soa<R> B = buffer_of<R>(h, bsel, sp);
+  for (int p = 0; p < P.parts; ++p) {
+    const int64_t m = n / P.parts + (p < n % P.parts ? 1 : 0);
+    std::vector<int32_t> c(m);
+    std::vector<R> o(m), x(m), y(m), z(m);
+    std::vector<uint64_t> d(m);
+    for (int64_t q = 0; q < m; ++q) {
+      const int64_t k = q * P.parts + p;
+      c[q] = cell[k];
+      R f = (R)off[k];
+      o[q] = f < R(1) ? f : std::nextafter(R(1), R(0));
+      x[q] = (R)vx[k];
+      y[q] = (R)vy[k];
+      z[q] = (R)vz[k];
+      d[q] = id[k];
+    }
+    const int64_t at = P.seg + (int64_t)p * P.cap_p;
+    if (m) {
+      HIPCHK(h, hipMemcpy(B.cell + at, c.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice));
+      HIPCHK(h, hipMemcpy(B.off + at, o.data(), sizeof(R) * m, hipMemcpyHostToDevice));
+      HIPCHK(h, hipMemcpy(B.vx + at, x.data(), sizeof(R) * m, hipMemcpyHostToDevice));
+      HIPCHK(h, hipMemcpy(B.vy + at, y.data(), sizeof(R) * m, hipMemcpyHostToDevice));
+      HIPCHK(h, hipMemcpy(B.vz + at, z.data(), sizeof(R) * m, hipMemcpyHostToDevice));
+      HIPCHK(h, hipMemcpy(B.id + at, d.data(), sizeof(uint64_t) * m, hipMemcpyHostToDevice));
+    }
+    const uint32_t cnt = (uint32_t)m;
+    HIPCHK(h, hipMemcpy(h->ws + count_offset(h, slot3, inst, sp, p), &cnt, sizeof(uint32_t),
+                        hipMemcpyHostToDevice));
+  }
+  rc = launch_gen_any(h, MODE_REFRESH);
+  if (rc) return rc;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return SLPIC_OK;
+}
+
+int part_counts(slpic_t* h, uint32_t slot3, int inst, int sp, std::vector<uint32_t>& c) {
+  c.assign(MAX_PART, 0u);
+  HIPCHK(h, hipMemcpy(c.data(), h->ws + count_offset(h, slot3, inst, sp, 0), sizeof(uint32_t) * MAX_PART,
+                      hipMemcpyDeviceToHost));
+  c.resize(h->ip[inst].parts);
+  return SLPIC_OK;
+}
+
+template <typename R>
+int read_impl(slpic_t* h, int inst, int sp, int64_t max_n, int64_t* n_out, int32_t* cell,
+              double* off, double* vx, double* vy, double* vz, uint64_t* id) {
+  Global G;
+  uint32_t slot3, bsel;
+  int rc = current(h, G, slot3, bsel);
+  if (rc) return rc;
+  std::vector<uint32_t> cnt;
+  rc = part_counts(h, slot3, inst, sp, cnt);
+  if (rc) return rc;
+  int64_t n = 0;
+  for (uint32_t c : cnt) n += c;
+  *n_out = n;
+  if (n > max_n) return fail(h, SLPIC_INVALID_ARG, "output arrays too small");
+  const InstParams& P = h->ip[inst];
+  const Soa<R> B = buffer_of<R>(h, bsel, sp);
+  int64_t done = 0;
+  for (int p = 0; p < P.parts; ++p) {
+    const int64_t m = cnt[p], at = P.seg + (int64_t)p * P.cap_p;
+    if (!m) continue;
+    std::vector<R> a(m);
+    auto get = [&](double* dst, const R* src) -> hipError_t {
+      if (!dst) return hipSuccess;
+      hipError_t e = hipMemcpy(a.data(), src + at, sizeof(R) * m, hipMemcpyDeviceToHost);
+      for (int64_t k = 0; k < m; ++k) dst[done + k] = (double)a[k];
+      return e;
+    };
+    if (cell) HIPCHK(h, hipMemcpy(cell + done, B.cell + at, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+    HIPCHK(h, get(off, B.off));
+    HIPCHK(h, get(vx, B.vx));
+    HIPCHK(h, get(vy, B.vy));
+    HIPCHK(h, get(vz, B.vz));
+    if (id) HIPCHK(h, hipMemcpy(id + done, B.id + at, sizeof(uint64_t) * m, hipMemcpyDeviceToHost));
+    done += m;
+  }
+  return SLPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t slpic_workspace_bytes(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
+                             const slpic_xs* xs) {
+  if (!validate(cfg, inst, n_inst, xs).empty()) return 0;
+  Layout L;
+  if (!make_layout(cfg, inst, n_inst, xs, L)) return 0;
+  return L.total;
+}
+
+int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
+                 const slpic_xs* xs, void* dev_workspace, size_t ws_bytes, void* hip_stream,
+                 slpic_t** out) {
+  if (!out) return fail(nullptr, SLPIC_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  const std::string v = validate(cfg, inst, n_inst, xs);
+  if (!v.empty()) return fail(nullptr, SLPIC_INVALID_ARG, v);
+  slpic_t* h = new slpic_handle();
+  h->cfg = *cfg;
+  h->inst.assign(inst, inst + n_inst);
+  h->n_inst = n_inst;
+  if (!make_layout(cfg, inst, n_inst, xs, h->L)) {
+    delete h;
+    return fail(nullptr, SLPIC_INVALID_ARG, "too many tiles");
+  }
+  if (!dev_workspace || ws_bytes < h->L.total || ((uintptr_t)dev_workspace & 255)) {
+    delete h;
+    return fail(nullptr, SLPIC_WORKSPACE_TOO_SMALL, "workspace missing, too small or misaligned");
+  }
+  h->ws = static_cast<char*>(dev_workspace);
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  for (int i = 0; i < n_inst; ++i) h->ip.push_back(derive(cfg, inst[i], xs, h->L, i));
+  for (int i = 0; i < n_inst; ++i)
+    if (inst[i].n_seed > (int64_t)h->L.parts[i] * h->L.cap_p[i]) {
+      delete h;
+      return fail(nullptr, SLPIC_INVALID_ARG, "seeds exceed the capacity");
+    }
+  // grid: enough workgroups to fill the device, never more than tiles exist
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = cfg->precision == 64 ? occupancy_gen<double>(&per_cu) : occupancy_gen<float>(&per_cu);
+  if (e != hipSuccess) {
+    int rc = hip_fail(nullptr, e, "device query");
+    delete h;
+    return rc;
+  }
+  h->grid = std::max(1, std::min(cus * std::max(per_cu, 1), h->L.max_tiles));
+  fill_ctx(h, h->c32);
+  fill_ctx(h, h->c64);
+  int rc = cfg->precision == 64 ? upload_tables(h, h->c64, xs) : upload_tables(h, h->c32, xs);
+  if (rc) {
+    g_create_error = h->err;
+    delete h;
+    return rc;
+  }
+  const Layout& L = h->L;
+  // constant and initial state: generation 0, buffer 0, seeds in counts[0]
+  std::vector<InstState> st(2 * n_inst);
+  std::vector<uint32_t> counts(3 * 2 * MAX_PART * (size_t)n_inst, 0u);
+  for (int i = 0; i < n_inst; ++i) {
+    st[i] = InstState{cfg->w_j0, 0u, POP_NONE};
+    st[n_inst + i] = st[i];
+    const int64_t ns = inst[i].seed_mode != SLPIC_SEED_NONE ? inst[i].n_seed : 0;
+    const int P = L.parts[i];
+    for (int p = 0; p < P; ++p)  // seed k sits in partition k mod P
+      counts[(size_t)i * 2 * MAX_PART + p] = (uint32_t)(ns / P + (p < ns % P ? 1 : 0));
+  }
+  Global G;
+  std::memset(&G, 0, sizeof(G));
+  auto up = [&](size_t off, const void* src, size_t n) {
+    return hipMemcpyAsync(h->ws + off, src, n, hipMemcpyHostToDevice, h->stream);
+  };
+  e = up(L.ip, h->ip.data(), sizeof(InstParams) * n_inst);
+  if (e == hipSuccess) e = up(L.st, st.data(), sizeof(InstState) * st.size());
+  if (e == hipSuccess) e = up(L.counts, counts.data(), sizeof(uint32_t) * counts.size());
+  if (e == hipSuccess) e = up(L.glob, &G, sizeof(G));
+  if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.tile_start, 0, sizeof(uint32_t) * (2 * n_inst + 1), h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.acc, 0, sizeof(unsigned long long) * 2 * NSLOT * L.total_nodes, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.inst_err, 0, sizeof(uint32_t) * n_inst, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.ring, 0, sizeof(StatsRow) * RING * n_inst, h->stream);
+  for (int i = 0; i < n_inst && e == hipSuccess; ++i) {
+    if (inst[i].seed_mode == SLPIC_SEED_NONE) continue;
+    const double sv = std::sqrt(kQE * cfg->kTe_seed_eV / kME);
+    e = cfg->precision == 64
+            ? launch_seed<double>(h->c64, i, inst[i].seed_mode, inst[i].n_seed, sv, 0u, h->stream)
+            : launch_seed<float>(h->c32, i, inst[i].seed_mode, inst[i].n_seed, sv, 0u, h->stream);
+  }
+  if (e != hipSuccess) {
+    int r2 = hip_fail(nullptr, e, "create upload/seed");
+    delete h;
+    return r2;
+  }
+  rc = launch_gen_any(h, MODE_REFRESH);
+  if (rc == SLPIC_OK) {
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) rc = hip_fail(h, e, "create sync");
+  }
+  if (rc) {
+    g_create_error = h->err;
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return SLPIC_OK;
+}
+
+int slpic_use_graph(slpic_t* h, int enable) {
+  if (!h) return SLPIC_INVALID_ARG;
+  h->use_graph = enable != 0;
+  return SLPIC_OK;
+}
+
+int slpic_step(slpic_t* h, int n_steps) {
+  if (!h || n_steps < 0) return fail(h, SLPIC_INVALID_ARG, "bad step arguments");
+  int done = 0;
+  if (h->use_graph && n_steps >= h->graph_period) {
+    if (!h->graph) {
+      hipGraph_t gr;
+      HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      for (int k = 0; k < h->graph_period; ++k) {
+        hipError_t e = h->cfg.precision == 64 ? launch_gen<double>(h->c64, MODE_STEP, h->stream)
+                                              : launch_gen<float>(h->c32, MODE_STEP, h->stream);
+        if (e != hipSuccess) {
+          (void)hipStreamEndCapture(h->stream, &gr);
+          return hip_fail(h, e, "graph capture");
+        }
+      }
+      HIPCHK(h, hipStreamEndCapture(h->stream, &gr));
+      HIPCHK(h, hipGraphInstantiate(&h->graph, gr, nullptr, nullptr, 0));
+      (void)hipGraphDestroy(gr);
+    }
+    while (n_steps - done >= h->graph_period) {
+      HIPCHK(h, hipGraphLaunch(h->graph, h->stream));
+      h->gen += h->graph_period;
+      h->steps += h->graph_period;
+      done += h->graph_period;
+    }
+  }
+  for (; done < n_steps; ++done) {
+    int rc = launch_gen_any(h, MODE_STEP);
+    if (rc) return rc;
+    h->steps += 1;
+  }
+  return SLPIC_OK;
+}
+
+int slpic_sync(slpic_t* h) {
+  if (!h) return SLPIC_INVALID_ARG;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  std::vector<uint32_t> err(h->n_inst);
+  HIPCHK(h, hipMemcpy(err.data(), h->ws + h->L.inst_err, sizeof(uint32_t) * h->n_inst,
+                      hipMemcpyDeviceToHost));
+  uint32_t all = 0;
+  for (uint32_t v : err) all |= v;
+  if (all) HIPCHK(h, hipMemset(h->ws + h->L.inst_err, 0, sizeof(uint32_t) * h->n_inst));
+  if (all & ERR_CAPACITY) return fail(h, SLPIC_CAPACITY_EXCEEDED, "marker capacity exceeded");
+  if (all & ERR_NONFINITE) return fail(h, SLPIC_NONFINITE_STATE, "non-finite marker state");
+  if (all & ERR_NU_BOUND) return fail(h, SLPIC_NU_BOUND_EXCEEDED, "collision rate above bound");
+  return SLPIC_OK;
+}
+
+int slpic_load_markers(slpic_t* h, int inst, int species, int64_t n, const int32_t* cell,
+                       const double* off, const double* vx, const double* vy, const double* vz,
+                       const uint64_t* id) {
+  if (!h || inst < 0 || inst >= h->n_inst || (species != 0 && species != 1) || n < 0)
+    return fail(h, SLPIC_INVALID_ARG, "bad load arguments");
+  if (n > h->inst[inst].capacity) return fail(h, SLPIC_CAPACITY_EXCEEDED, "more markers than capacity");
+  if (n > 0 && (!cell || !off || !vx || !vy || !vz || !id))
+    return fail(h, SLPIC_INVALID_ARG, "null marker array");
+  return h->cfg.precision == 64 ? load_impl<double>(h, inst, species, n, cell, off, vx, vy, vz, id)
+                                : load_impl<float>(h, inst, species, n, cell, off, vx, vy, vz, id);
+}
+
+int slpic_count(slpic_t* h, int inst, int species, int64_t* n) {
+  if (!h || !n || inst < 0 || inst >= h->n_inst || (species != 0 && species != 1))
+    return fail(h, SLPIC_INVALID_ARG, "bad count arguments");
+  Global G;
+  uint32_t slot3, bsel;
+  int rc = current(h, G, slot3, bsel);
+  if (rc) return rc;
+  std::vector<uint32_t> c;
+  rc = part_counts(h, slot3, inst, species, c);
+  if (rc) return rc;
+  int64_t t = 0;
+  for (uint32_t v : c) t += v;
+  *n = t;
+  return SLPIC_OK;
+}
+
+int slpic_read_markers(slpic_t* h, int inst, int species, int64_t max_n, int64_t* n,
+                       int32_t* cell, double* off, double* vx, double* vy, double* vz,
+                       uint64_t* id) {
+  if (!h || !n || inst < 0 || inst >= h->n_inst || (species != 0 && species != 1))
+    return fail(h, SLPIC_INVALID_ARG, "bad read arguments");
+  return h->cfg.precision == 64
+             ? read_impl<double>(h, inst, species, max_n, n, cell, off, vx, vy, vz, id)
+             : read_impl<float>(h, inst, species, max_n, n, cell, off, vx, vy, vz, id);
+}
+
+int slpic_read_fields(slpic_t* h, int inst, double* rho, double* phi, double* E) {
+  if (!h || inst < 0 || inst >= h->n_inst) return fail(h, SLPIC_INVALID_ARG, "bad instance");
+  Global G;
+  uint32_t slot3, bsel;
+  int rc = current(h, G, slot3, bsel);
+  if (rc) return rc;
+  const size_t base = (size_t)(G.cur_gen % 2u) * h->L.total_nodes + h->ip[inst].node;
+  const size_t n = (size_t)h->ip[inst].cells + 1;
+  if (rho) HIPCHK(h, hipMemcpy(rho, h->ws + h->L.rho + 8 * base, 8 * n, hipMemcpyDeviceToHost));
+  if (phi) HIPCHK(h, hipMemcpy(phi, h->ws + h->L.phi + 8 * base, 8 * n, hipMemcpyDeviceToHost));
+  if (E) HIPCHK(h, hipMemcpy(E, h->ws + h->L.E64 + 8 * base, 8 * n, hipMemcpyDeviceToHost));
+  return SLPIC_OK;
+}
+
+int slpic_read_stats(slpic_t* h, int inst, int64_t first_step, int n, slpic_stats* rows) {
+  if (!h || inst < 0 || inst >= h->n_inst || n < 0 || (n > 0 && !rows) || first_step < 0)
+    return fail(h, SLPIC_INVALID_ARG, "bad stats arguments");
+  static_assert(sizeof(StatsRow) == sizeof(slpic_stats), "stats row layout");
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (first_step + n > h->steps || first_step + RING < h->steps)
+    return fail(h, SLPIC_INVALID_ARG, "requested steps are not in the statistics ring");
+  for (int k = 0; k < n; ++k) {
+    const int64_t slot = (first_step + k) % RING;
+    HIPCHK(h, hipMemcpy(rows + k, h->ws + h->L.ring + sizeof(StatsRow) * ((size_t)inst * RING + slot),
+                        sizeof(StatsRow), hipMemcpyDeviceToHost));
+  }
+  return SLPIC_OK;
+}
+
+int slpic_scalars(slpic_t* h, int inst, double* out8) {
+  if (!h || !out8 || inst < 0 || inst >= h->n_inst) return fail(h, SLPIC_INVALID_ARG, "bad scalars arguments");
+  Global G;
+  uint32_t slot3, bsel;
+  int rc = current(h, G, slot3, bsel);
+  if (rc) return rc;
+  InstState st;
+  HIPCHK(h, hipMemcpy(&st, h->ws + h->L.st + sizeof(InstState) * ((size_t)(G.cur_gen % 2u) * h->n_inst + inst),
+                      sizeof(st), hipMemcpyDeviceToHost));
+  const InstParams& P = h->ip[inst];
+  out8[0] = P.dx;
+  out8[1] = P.dt;
+  out8[2] = P.v0;
+  out8[3] = P.n_g;
+  out8[4] = P.nu_max_e;
+  out8[5] = P.nu_max_cx;
+  out8[6] = st.w_j;
+  out8[7] = st.step;
+  return SLPIC_OK;
+}
+
+int64_t slpic_steps_done(const slpic_t* h) { return h ? h->steps : -1; }
+
+const char* slpic_last_error(const slpic_t* h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+void slpic_destroy(slpic_t* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  delete h;
+}
+
+int slpic_philox_device(const uint32_t* ctr, uint32_t key0, uint32_t key1, int64_t n,
+                        uint32_t* out, void* hip_stream) {
+  if (n < 0 || (n > 0 && (!ctr || !out))) return SLPIC_INVALID_ARG;
+  hipError_t e = launch_philox_test(ctr, key0, key1, n, out, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? SLPIC_OK : SLPIC_HIP_ERROR;
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// Internal layout shared by the host side (slpic_capi.cpp) and the kernels
+// (slpic_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace slpic {
+
+constexpr int BLOCK = 256;        // threads per workgroup = markers per tile
+constexpr int WAVE = 64;
+constexpr int MAX_INST = 1024;
+constexpr int MAX_CHAN = 8;
+constexpr int NEV = 11;           // event counters per tile
+constexpr int RING = 4096;        // statistics rows kept per instance
+constexpr int MAX_PART = 16;      // output partitions per (instance, species)
+constexpr int NSLOT = 16;         // copies of each global deposit node
+constexpr int HWIN = 1024;        // nodes in a workgroup's LDS deposit window
+
+// event counter slots (order of the public slpic_stats fields)
+enum Ev {
+  EV_ELASTIC = 0, EV_EXCIT, EV_IONIZ, EV_CX, EV_ABS_E_CATH, EV_ABS_E_ANODE,
+  EV_ABS_I_CATH, EV_ABS_I_ANODE, EV_SEE, EV_ROULETTE, EV_SPLIT
+};
+
+// device error bits
+enum Err { ERR_CAPACITY = 1, ERR_NONFINITE = 2, ERR_NU_BOUND = 4 };
+
+// Philox stream channels: the fourth counter word is channel | sub << 8
+enum Chan {
+  CH_COLL = 1, CH_IONIZ = 2, CH_IONBIRTH = 3, CH_CX = 4, CH_SEE = 5,
+  CH_ROULETTE = 6, CH_CHILD = 7, CH_SEED = 8
+};
+
+enum PopMode { POP_NONE = 0, POP_ROULETTE = 1, POP_SPLIT = 2 };
+
+// kernel modes of the generation kernel
+enum Mode { MODE_STEP = 0, MODE_REFRESH = 1 };
+
+// Per-instance constants.  Integer thresholds t_* turn a probability P into
+// the test (r >> 9) < t on a raw 32-bit Philox word, which equals
+// u < P for u = (2 (r >> 9) + 1) 2^-24.
+struct InstParams {
+  double d, dx, inv_dx, dt, V, n_g, v0, area, gamma_se;
+  double nu_max_e, nu_max_cx, sigma_cx;
+  double qm_e, qm_i;        // signed charge over mass [C/kg]
+  double vth_i;             // sqrt(k_B T / m_Ar)
+  double w_j0;
+  int64_t seg;              // first slot of the instance in each species array
+  int64_t cap;              // markers per species (sum over partitions)
+  int64_t cap_p;            // slots per partition: partition p of the instance
+                            // holds slots [seg + p cap_p, seg + (p+1) cap_p)
+  int64_t n_target;
+  int32_t cells, node;      // node: first node of the instance in node arrays
+  int32_t limited;          // 0: plain PIC (beta == 1)
+  int32_t parts;            // output partitions P (tile j serves j mod P)
+  uint32_t t_null_e, t_null_cx, t_see;
+  uint32_t t_fixed[MAX_CHAN];
+  uint32_t t_fixed_cx;
+};
+
+template <typename R>
+struct Soa {
+  int32_t* cell;
+  R* off;
+  R* vx;
+  R* vy;
+  R* vz;
+  uint64_t* id;
+};
+
+// identical layout to the public slpic_stats
+struct StatsRow {
+  int64_t step, n_e, n_i, n_in;
+  double w_e, w_i, w_j;
+  int64_t ev[NEV];
+  int64_t err;
+};
+
+struct InstState {
+  double w_j;
+  uint32_t step;
+  int32_t popmode;
+};
+
+// Handle-wide device words.  wgc counts workgroup starts of the particle
+// kernel: every launch has exactly `grid` workgroups, so a workgroup's
+// generation is its ticket / grid, and the tail kernel that follows reads
+// the generation as wgc / grid - 1.  Per-step state is buffered by
+// generation: a launch reads generation g and writes g + 1.
+struct Global {
+  unsigned long long wgc;
+  uint32_t cur_gen;     // generation of the current state (set by tails)
+  uint32_t bufsel[2];   // particle buffer holding generation g's markers
+  uint32_t err;
+};
+
+template <typename R>
+struct Ctx {
+  const InstParams* ip;
+  Soa<R> buf[2][2];          // [buffer][species]
+  InstState* st;             // [2][n_inst]
+  uint32_t* counts;          // [3][n_inst][2][MAX_PART]
+  uint32_t* tile_start;      // [2 n_inst + 1] tile prefix of the last launch
+  uint32_t* tile_ev;         // [max_tiles][NEV]
+  unsigned long long* acc;   // [2 species][total_nodes][NSLOT] fixed-point deposit
+  R* E;                      // [2][total_nodes] field in kernel precision
+  double* E64;               // [2][total_nodes]
+  double* phi;               // [2][total_nodes]
+  double* rho;               // [2][total_nodes]
+  double* scratch;           // [total_nodes]
+  StatsRow* ring;            // [n_inst][RING]
+  uint32_t* inst_err;        // [n_inst], sticky
+  Global* g;
+  const R* xs_e;             // [n_grid] node energies
+  const R* xs_sig;           // [n_grid][n_chan]
+  const R* xs_thr;           // [n_chan]
+  const int32_t* xs_kind;    // [n_chan]
+  R log_emin, inv_dlog;      // log-uniform grid index
+  double ion_B;
+  int n_chan, n_grid;
+  int n_inst, total_nodes, grid, max_tiles;
+  int fixed;
+  uint32_t flags, seed;
+  int dep_shift;             // fraction bits of the fixed-point deposit
+};
+
+}  // namespace slpic

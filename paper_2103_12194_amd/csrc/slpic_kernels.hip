@@ -1,0 +1,1074 @@
+// HIP kernels (gfx950) of the speed-limited PIC / Monte Carlo collision step.
+//
+// One launch of k_gen<R, MODE_STEP> advances every marker of every instance
+// by one step: gather, speed-limited free flight (Eqs. 8-9 with beta of
+// Eq. 11, solved exactly for the gathered field), wall absorption and
+// ion-induced secondary emission, null-collision MCC with the SLPIC rate of
+// Eqs. (15)-(16), population control, stream compaction of survivors and new
+// markers, and the linear charge deposit.  The workgroup that completes the
+// last tile of an instance then solves that instance's Poisson problem in
+// FP64 and writes its statistics row.
+//
+// Memory layout: structure-of-arrays markers (int32 cell, R offset in the
+// cell, R v_x, v_y, v_z, uint64 id) in two ping-pong buffers per species;
+// each instance owns a fixed segment [seg, seg + cap) of every array.
+// Work unit: a tile of 256 consecutive markers of one (instance, species);
+// tiles are dealt round-robin to the workgroups of the launch.
+#include <hip/hip_runtime.h>
+
+#include "slpic_internal.hpp"
+
+namespace slpic {
+
+// ---------------------------------------------------------------- math
+__device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float m_log(float x) { return logf(x); }
+__device__ __forceinline__ double m_log(double x) { return log(x); }
+__device__ __forceinline__ float m_log1p(float x) { return log1pf(x); }
+__device__ __forceinline__ double m_log1p(double x) { return log1p(x); }
+__device__ __forceinline__ float m_expm1(float x) { return expm1f(x); }
+__device__ __forceinline__ double m_expm1(double x) { return expm1(x); }
+__device__ __forceinline__ float m_asinh(float x) { return asinhf(x); }
+__device__ __forceinline__ double m_asinh(double x) { return asinh(x); }
+__device__ __forceinline__ float m_atan(float x) { return atanf(x); }
+__device__ __forceinline__ double m_atan(double x) { return atan(x); }
+__device__ __forceinline__ float m_tan(float x) { return tanf(x); }
+__device__ __forceinline__ double m_tan(double x) { return tan(x); }
+__device__ __forceinline__ float m_floor(float x) { return floorf(x); }
+__device__ __forceinline__ double m_floor(double x) { return floor(x); }
+__device__ __forceinline__ void m_sincospi(float x, float* s, float* c) { sincospif(x, s, c); }
+__device__ __forceinline__ void m_sincospi(double x, double* s, double* c) { sincospi(x, s, c); }
+__device__ __forceinline__ bool m_finite(float x) { return isfinite(x); }
+__device__ __forceinline__ bool m_finite(double x) { return isfinite(x); }
+template <typename R> __device__ __forceinline__ R one_below();
+template <> __device__ __forceinline__ float one_below<float>() { return 0x1.fffffep-1f; }
+template <> __device__ __forceinline__ double one_below<double>() { return 0x1.fffffffffffffp-1; }
+
+// physical constants (SI)
+constexpr double QE = 1.602176634e-19;
+constexpr double ME = 9.1093837015e-31;
+constexpr double MAR = 39.948 * 1.66053906660e-27;
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
+// multiplies on words 0 and 2, with the Weyl-sequence key schedule.
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    c0 = hi1 ^ c1 ^ k0;
+    c2 = hi0 ^ c3 ^ k1;
+    c1 = lo1;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+// stream of one marker: key (seed, instance), counter (id, step, channel)
+__device__ __forceinline__ U4 draw(uint64_t id, uint32_t step, uint32_t ch, uint32_t seed,
+                                   uint32_t inst) {
+  return philox((uint32_t)id, (uint32_t)(id >> 32), step, ch, seed, inst);
+}
+
+// u = (2 (r >> 9) + 1) 2^-24: exact in FP32 and FP64, never 0 or 1
+template <typename R>
+__device__ __forceinline__ R unif(uint32_t r) {
+  return (R)(((r >> 9) << 1) | 1u) * (R)5.9604644775390625e-08;
+}
+
+__device__ __forceinline__ uint64_t child(uint32_t lo, uint32_t hi) {
+  return ((uint64_t)hi << 32 | lo) | 0x8000000000000000ull;
+}
+
+// three normals (Box-Muller on two pairs) scaled by sigma
+template <typename R>
+__device__ __forceinline__ void normals3(U4 r, R sigma, R& a, R& b, R& c) {
+  R s0, c0, s1, c1;
+  const R r0 = m_sqrt(R(-2) * m_log(unif<R>(r.x)));
+  const R r1 = m_sqrt(R(-2) * m_log(unif<R>(r.z)));
+  m_sincospi(R(2) * unif<R>(r.y), &s0, &c0);
+  m_sincospi(R(2) * unif<R>(r.w), &s1, &c1);
+  a = sigma * r0 * c0;
+  b = sigma * r0 * s0;
+  c = sigma * r1 * c1;
+}
+
+// ---------------------------------------------------------------- flight
+// Integral of sqrt(u^2 + c^2) over [p, p + len], p >= 0, in a form without
+// cancellation for short intervals (q = p + len, W(u) = sqrt(u^2 + c^2)):
+//   q W(q) - p W(p) = len (q + p)(q^2 + p^2 + c^2) / (q W(q) + p W(p)),
+//   asinh(q/c) - asinh(p/c) = asinh(len (q + p) / (q W(p) + p W(q))).
+template <typename R>
+__device__ R sqrt_span(R p, R len, R c) {
+  if (!(len > R(0))) return R(0);
+  const R q = p + len, sq = p + q;
+  if (c == R(0)) return R(0.5) * len * sq;
+  const R c2 = c * c;
+  const R Wp = m_sqrt(p * p + c2), Wq = m_sqrt(q * q + c2);
+  const R t1 = len * sq * (q * q + p * p + c2) / (q * Wq + p * Wp);
+  const R t2 = c2 * m_asinh(len * sq / (q * Wp + p * Wq));
+  return R(0.5) * (t1 + t2);
+}
+
+// Wall-clock time (times |a|) to move s from a to a + len:
+// integral of max(1, sqrt(u^2 + c^2) / v0), split where |v| = v0 and at 0.
+template <typename R>
+__device__ R time_span(R a, R len, R c, R v0) {
+  const R ss = c < v0 ? m_sqrt(v0 * v0 - c * c) : R(0);
+  const R b = a + len;
+  R start = a, total = R(0);
+  const R brk[3] = {-ss, R(0), ss};
+#pragma unroll
+  for (int k = 0; k <= 3; ++k) {
+    R p = start, piece;
+    if (k < 3) {
+      if (!(brk[k] > start && brk[k] < b)) continue;
+      piece = brk[k] - start;
+      start = brk[k];
+    } else {
+      piece = (p == a) ? len : b - p;
+    }
+    const R mid = p + R(0.5) * piece;
+    if (c < v0 && (mid < ss && mid > -ss)) total += piece;
+    else if (mid < R(0)) total += sqrt_span(-(p + piece), piece, c) / v0;
+    else total += sqrt_span(p, piece, c) / v0;
+  }
+  return total;
+}
+
+template <typename R>
+__device__ __forceinline__ R c0_time(R s, R v0) {  // time integral from 0 to s for c = 0
+  const R as = s < R(0) ? -s : s;
+  const R t = as <= v0 ? as : (as * as + v0 * v0) / (R(2) * v0);
+  return s < R(0) ? -t : t;
+}
+
+template <typename R>
+__device__ __forceinline__ R c0_inverse(R y, R v0) {
+  const R ay = y < R(0) ? -y : y;
+  const R s = ay <= v0 ? ay : m_sqrt(R(2) * v0 * ay - v0 * v0);
+  return y < R(0) ? -s : s;
+}
+
+struct FlightOut {
+  bool turns;
+};
+
+// Exact speed-limited flight over dt in the uniform acceleration a along x.
+// Returns the displacement, the new v_x and, when v_x changes sign inside the
+// flight, the displacement of the turning point.
+template <typename R>
+__device__ void flight(R vx, R c, R a, R dt, R v0, int limited, R& disp, R& vx1,
+                       bool& turns, R& turn_disp) {
+  R dv;  // change of v_x (= a tau)
+  R tau;
+  const R w0sq = vx * vx + c * c;
+  const R ve = vx + a * dt;
+  if (!limited || (w0sq <= v0 * v0 && ve * ve + c * c <= v0 * v0)) {
+    tau = dt;  // beta == 1 along the whole flight
+    dv = a * dt;
+  } else if (a == R(0)) {
+    tau = dt * v0 / m_sqrt(w0sq);
+    dv = R(0);
+  } else {
+    const R sg = a > R(0) ? R(1) : R(-1);
+    const R at = a * sg, s0 = sg * vx;
+    const R rhs = at * dt;
+    R lo = R(0), hi = rhs;
+    R delta = c0_inverse(c0_time(s0, v0) + rhs, v0) - s0;
+    if (!(delta > lo && delta < hi)) {
+      const R h0 = m_sqrt(w0sq) / v0;
+      delta = rhs / (h0 > R(1) ? h0 : R(1));
+    }
+    const R tol = sizeof(R) == 4 ? R(2e-7) : R(4e-16);
+    for (int it = 0; it < 40; ++it) {
+      const R f = time_span(s0, delta, c, v0) - rhs;
+      if (f > R(0)) hi = delta;
+      else if (f < R(0)) lo = delta;
+      else break;
+      const R s = s0 + delta;
+      R hp = m_sqrt(s * s + c * c) / v0;
+      hp = hp > R(1) ? hp : R(1);
+      const R step = -f / hp;
+      // converged: the Newton step is below the tolerance (and may be below
+      // the resolution of delta, where the bracket test would reject it)
+      if ((step < R(0) ? -step : step) <= tol * delta) {
+        const R dn = delta + step;
+        if (dn > lo && dn < hi) delta = dn;
+        break;
+      }
+      R dn = delta + step;
+      if (!(dn > lo && dn < hi)) dn = R(0.5) * (lo + hi);
+      delta = dn;
+      if (hi - lo <= tol * hi) break;
+    }
+    tau = delta / at;
+    dv = sg * delta;
+  }
+  disp = tau * (vx + R(0.5) * dv);
+  vx1 = vx + dv;
+  turns = (vx * dv < R(0)) && ((vx < R(0) ? -vx : vx) < (dv < R(0) ? -dv : dv));
+  turn_disp = turns ? -vx * vx / (R(2) * a) : R(0);
+}
+
+// beta of Eq. (11) as min(1, v0/|v|)
+template <typename R>
+__device__ __forceinline__ R beta_of(R v2, R v0, int limited) {
+  if (!limited) return R(1);
+  const R v = m_sqrt(v2);
+  return v > v0 ? v0 / v : R(1);
+}
+
+// ---------------------------------------------------------------- collisions
+template <typename R>
+__device__ __forceinline__ R vs_cos(R eps, R u) {
+  // Vahedi-Surendra: cos chi = (2 + eps - 2 (1 + eps)^u) / eps
+  //                          = 1 - 2 expm1(u log1p(eps)) / eps
+  if (!(eps > R(0))) return R(1) - R(2) * u;
+  return R(1) - R(2) * m_expm1(u * m_log1p(eps)) / eps;
+}
+
+// Turn unit vector (hx, hy, hz) by chi (cos given) and azimuth 2 pi u; the
+// azimuth is measured from e1 = normalize(h x a), a the axis of the smallest
+// |component| of h (ties to the lower index), e2 = h x e1.
+template <typename R>
+__device__ __forceinline__ void turn(R hx, R hy, R hz, R cosx, R u, R& ox, R& oy, R& oz) {
+  const R ax = hx < R(0) ? -hx : hx, ay = hy < R(0) ? -hy : hy, az = hz < R(0) ? -hz : hz;
+  R e1x, e1y, e1z;
+  if (ay < ax && ay <= az) { e1x = -hz; e1y = R(0); e1z = hx; }       // axis y
+  else if (az < ax && az < ay) { e1x = hy; e1y = -hx; e1z = R(0); }  // axis z
+  else { e1x = R(0); e1y = hz; e1z = -hy; }                          // axis x
+  const R n = m_sqrt(e1x * e1x + e1y * e1y + e1z * e1z);
+  e1x /= n; e1y /= n; e1z /= n;
+  const R e2x = hy * e1z - hz * e1y, e2y = hz * e1x - hx * e1z, e2z = hx * e1y - hy * e1x;
+  R sn = R(1) - cosx * cosx;
+  sn = sn > R(0) ? m_sqrt(sn) : R(0);
+  R sp, cp;
+  m_sincospi(R(2) * u, &sp, &cp);
+  ox = cosx * hx + sn * (cp * e1x + sp * e2x);
+  oy = cosx * hy + sn * (cp * e1y + sp * e2y);
+  oz = cosx * hz + sn * (cp * e1z + sp * e2z);
+}
+
+template <typename R>
+__device__ __forceinline__ void unit3(R vx, R vy, R vz, R& hx, R& hy, R& hz) {
+  const R s = m_sqrt(vx * vx + vy * vy + vz * vz);
+  if (s > R(0)) { hx = vx / s; hy = vy / s; hz = vz / s; }
+  else { hx = R(1); hy = R(0); hz = R(0); }
+}
+
+// Channel choice of a collision candidate: the first channel k with
+// target < sum_{q<=k} n_g sigma_q(eps) slow, where sigma_q is interpolated
+// linearly between log-uniform nodes and is zero below the channel's
+// threshold.  Returns -1 for a null collision; cum receives the full sum.
+template <typename R>
+__device__ __forceinline__ int select_channel(const Ctx<R>& C, R eps, R scale, R target, R& cum) {
+  const int n = C.n_grid;
+  int i;
+  R t;
+  if (!(eps > C.xs_e[0])) { i = 0; t = R(0); }
+  else if (!(eps < C.xs_e[n - 1])) { i = n - 2; t = R(1); }
+  else {
+    i = (int)((m_log(eps) - C.log_emin) * C.inv_dlog);
+    i = i < 0 ? 0 : (i > n - 2 ? n - 2 : i);
+    if (eps < C.xs_e[i] && i > 0) --i;
+    else if (!(eps < C.xs_e[i + 1]) && i < n - 2) ++i;
+    t = (eps - C.xs_e[i]) / (C.xs_e[i + 1] - C.xs_e[i]);
+  }
+  const R* a = C.xs_sig + (size_t)i * C.n_chan;
+  const R* b = a + C.n_chan;
+  int ch = -1;
+  R sum = R(0);
+  for (int k = 0; k < C.n_chan; ++k) {
+    const R v = eps < C.xs_thr[k] ? R(0) : a[k] + t * (b[k] - a[k]);
+    sum += scale * v;
+    if (ch < 0 && target < sum) ch = k;
+  }
+  cum = sum;
+  return ch;
+}
+
+template <typename R>
+struct Mk {  // one marker's state
+  int32_t cell;
+  R off, vx, vy, vz;
+  uint64_t id;
+};
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ uint32_t gen_slot3(uint32_t g, uint32_t k) { return (g + k) % 3u; }
+
+template <typename R>
+__device__ __forceinline__ unsigned long long fixed_pt(R w, int shift) {
+  // w in [0, 1] -> round(w 2^shift)
+  return (unsigned long long)((double)w * (double)(1ull << shift) + 0.5);
+}
+
+// inclusive segmented sum over lanes with equal key in runs; returns true in
+// the last lane of each run
+__device__ __forceinline__ bool seg_reduce(int key, unsigned long long& lo,
+                                           unsigned long long& hi) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int prev = __shfl_up(key, 1);
+  int head = (lane == 0 || prev != key) ? 1 : 0;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const unsigned long long lo_u = __shfl_up(lo, d);
+    const unsigned long long hi_u = __shfl_up(hi, d);
+    const int head_u = __shfl_up(head, d);
+    if (lane >= d) {
+      if (!head) { lo += lo_u; hi += hi_u; }
+      head |= head_u;
+    }
+  }
+  const int next = __shfl_down(key, 1);
+  return lane == WAVE - 1 || next != key;
+}
+
+// ---------------------------------------------------------------- tail
+// Poisson problem of one instance on its N+1 nodes (phi_0 = 0, phi_N = V),
+// solved as two prefix sums:
+//   E_{k+1/2} = E_{1/2} + (dx/eps0) S_k,   S_k = sum_{j=1..k} rho_j,
+//   E_{1/2} fixed by sum_k E_{k+1/2} dx = -V,
+//   phi_i = -dx (i E_{1/2} + (dx/eps0) U_i),  U_i = sum_{k<i} S_k,
+// with node fields E_i = (E_{i-1/2} + E_{i+1/2}) / 2 inside and Gauss's law
+// over the half cell at each electrode.
+constexpr double EPS0 = 8.8541878128e-12;
+
+__device__ double block_exclusive_scan(double v, double* sh, double& total) {
+  // 256 threads, returns the exclusive prefix of v; total receives the sum
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int d = 1; d < BLOCK; d <<= 1) {
+    const double add = t >= d ? sh[t - d] : 0.0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  const double incl = sh[t];
+  total = sh[BLOCK - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__device__ __forceinline__ size_t cidx(int n_inst, uint32_t slot, int inst, int sp, int p) {
+  return (((size_t)slot * n_inst + inst) * 2 + sp) * MAX_PART + p;
+}
+
+// One workgroup per instance, launched after the particle kernel: charge
+// density from the fixed-point deposit, Poisson solve, statistics row,
+// population-control decision for the next step and the generation switch.
+template <typename R, int MODE>
+__global__ void __launch_bounds__(BLOCK) k_tail(Ctx<R> C) {
+  __shared__ double sh[BLOCK];
+  const int inst = blockIdx.x, t = threadIdx.x;
+  const uint32_t g = (uint32_t)(C.g->wgc / (unsigned long long)C.grid) - 1u;
+  const InstParams& P = C.ip[inst];
+  const int N = P.cells, node = P.node;
+  const uint32_t sc = g % 2u, sn = (g + 1) % 2u;
+  const InstState cur = C.st[sc * C.n_inst + inst];
+  const double factor = MODE == MODE_STEP
+                            ? (cur.popmode == POP_ROULETTE ? 2.0 : (cur.popmode == POP_SPLIT ? 0.5 : 1.0))
+                            : 1.0;
+  const double wj = cur.w_j * factor;
+  const double unit = 1.0 / (double)(1ull << C.dep_shift);
+  const double qvol = QE * wj * unit / (P.area * P.dx);
+  unsigned long long* acc_e = C.acc + (size_t)node * NSLOT;
+  unsigned long long* acc_i = C.acc + ((size_t)C.total_nodes + node) * NSLOT;
+  double* rho = C.rho + (size_t)sn * C.total_nodes + node;
+  double* S = C.scratch + node;
+  const int chunk = (N + 1 + BLOCK - 1) / BLOCK;
+  const int i0 = t * chunk, i1 = min(i0 + chunk, N + 1);
+
+  // pass 1: charge density, species totals, interior prefix S
+  double se = 0.0, si = 0.0, loc = 0.0;
+  for (int i = i0; i < i1; ++i) {
+    unsigned long long ae = 0ull, ai = 0ull;
+    for (int q = 0; q < NSLOT; ++q) {
+      ae += acc_e[(size_t)i * NSLOT + q];
+      ai += acc_i[(size_t)i * NSLOT + q];
+      acc_e[(size_t)i * NSLOT + q] = 0ull;
+      acc_i[(size_t)i * NSLOT + q] = 0ull;
+    }
+    se += (double)ae;
+    si += (double)ai;
+    double r = ((double)ai - (double)ae) * qvol;
+    if (i == 0 || i == N) r *= 2.0;  // half cells at the electrodes
+    rho[i] = r;
+    if (i >= 1 && i <= N - 1) loc += r;
+  }
+  double tot;
+  const double off1 = block_exclusive_scan(loc, sh, tot);
+  double se_tot, si_tot;
+  block_exclusive_scan(se, sh, se_tot);
+  block_exclusive_scan(si, sh, si_tot);
+  // pass 2: S_i = sum_{j=1..i} rho_j (S_0 = 0), U = sum over k < N of S_k
+  double run = off1, usum = 0.0;
+  for (int i = i0; i < i1; ++i) {
+    if (i >= 1 && i <= N - 1) run += rho[i];
+    const double s = (i == 0) ? 0.0 : (i <= N - 1 ? run : 0.0);
+    S[i] = s;
+    if (i <= N - 1) usum += s;
+  }
+  double T;
+  const double off2 = block_exclusive_scan(usum, sh, T);
+  const double dx = P.dx, k = dx / EPS0;
+  const double Ehalf = (-P.V / dx - k * T) / (double)N;
+  double* phi = C.phi + (size_t)sn * C.total_nodes + node;
+  double* E64 = C.E64 + (size_t)sn * C.total_nodes + node;
+  R* ER = C.E + (size_t)sn * C.total_nodes + node;
+  double U = off2;
+  for (int i = i0; i < i1; ++i) {
+    double e;
+    if (i == 0) e = Ehalf - rho[0] * dx / (2.0 * EPS0);
+    else if (i == N) e = Ehalf + k * S[N - 1] + rho[N] * dx / (2.0 * EPS0);
+    else e = Ehalf + k * 0.5 * (S[i - 1] + S[i]);
+    phi[i] = (i == N) ? P.V : -dx * ((double)i * Ehalf + k * U);
+    E64[i] = e;
+    ER[i] = (R)e;
+    if (i <= N - 1) U += S[i];
+  }
+  // events of the instance's tiles
+  uint32_t ev[NEV];
+  for (int q = 0; q < NEV; ++q) ev[q] = 0;
+  if (MODE == MODE_STEP) {
+    const uint32_t t0 = C.tile_start[2 * inst], t1 = C.tile_start[2 * inst + 2];
+    for (uint32_t tt = t0 + t; tt < t1; tt += BLOCK)
+      for (int q = 0; q < NEV; ++q) ev[q] += C.tile_ev[(size_t)tt * NEV + q];
+  }
+  __syncthreads();
+  int64_t evsum[NEV];
+  for (int q = 0; q < NEV; ++q) {
+    double tq;
+    block_exclusive_scan((double)ev[q], sh, tq);
+    evsum[q] = (int64_t)tq;
+  }
+  if (t == 0) {
+    int64_t n[2] = {0, 0}, nin = 0;
+    for (int sp = 0; sp < 2; ++sp)
+      for (int p = 0; p < P.parts; ++p) {
+        uint32_t* ci = C.counts + cidx(C.n_inst, g % 3u, inst, sp, p);
+        uint32_t* co = C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, sp, p);
+        uint32_t* cf = C.counts + cidx(C.n_inst, (g + 2) % 3u, inst, sp, p);
+        nin += *ci;
+        uint32_t c = MODE == MODE_STEP ? *co : *ci;
+        if (c > (uint32_t)P.cap_p) {
+          atomicOr(C.inst_err + inst, (uint32_t)ERR_CAPACITY);
+          c = (uint32_t)P.cap_p;
+        }
+        *co = c;
+        *cf = 0u;
+        n[sp] += c;
+      }
+    const int64_t nout = n[0] + n[1];
+    int32_t pm = POP_NONE;
+    if (P.n_target > 0) {
+      if (nout > 2 * P.n_target) pm = POP_ROULETTE;
+      else if (nout > 0 && 2 * nout < P.n_target) pm = POP_SPLIT;
+    }
+    InstState nx;
+    nx.w_j = wj;
+    nx.step = cur.step + (MODE == MODE_STEP ? 1u : 0u);
+    nx.popmode = pm;
+    C.st[sn * C.n_inst + inst] = nx;
+    if (MODE == MODE_STEP) {
+      StatsRow row;
+      row.step = nx.step;
+      row.n_e = n[0];
+      row.n_i = n[1];
+      row.n_in = nin;
+      row.w_e = se_tot * unit * wj;
+      row.w_i = si_tot * unit * wj;
+      row.w_j = wj;
+      for (int q = 0; q < NEV; ++q) row.ev[q] = evsum[q];
+      row.err = C.inst_err[inst];
+      C.ring[(size_t)inst * RING + (nx.step - 1) % RING] = row;
+    }
+    const uint32_t bs = C.g->bufsel[g % 2u];
+    C.g->bufsel[(g + 1) % 2u] = MODE == MODE_STEP ? 1u - bs : bs;
+    C.g->cur_gen = g + 1;
+  }
+}
+
+// ---------------------------------------------------------------- deposit
+// A workgroup accumulates its markers' fixed-point weights in an LDS window
+// of HWIN nodes per species (the whole grid when it fits), and adds the
+// window to global memory once per instance it worked on, into one of NSLOT
+// copies of each node picked by the workgroup index: the tail kernel sums
+// the copies.  Nodes outside the window go to global memory directly.
+struct DepWin {
+  int inst, anchor;
+};
+
+__device__ __forceinline__ void dep_add(const unsigned long long* acc_base, unsigned long long* acc,
+                                        unsigned long long (*hist)[HWIN], const DepWin& w,
+                                        int sp, int node0, int total_nodes, int cell,
+                                        unsigned long long lo, unsigned long long hi) {
+  (void)acc_base;
+  const int r = cell - w.anchor;
+  if (r >= 0 && r + 1 < HWIN) {
+    if (lo) atomicAdd(&hist[sp][r], lo);
+    if (hi) atomicAdd(&hist[sp][r + 1], hi);
+  } else {
+    const int slot = blockIdx.x % NSLOT;
+    unsigned long long* a = acc + ((size_t)sp * total_nodes + node0 + cell) * NSLOT + slot;
+    if (lo) atomicAdd(a, lo);
+    if (hi) atomicAdd(a + NSLOT, hi);
+  }
+}
+
+template <typename R>
+__device__ void dep_flush(const Ctx<R>& C, unsigned long long (*hist)[HWIN], const DepWin& w) {
+  __syncthreads();
+  const InstParams& P = C.ip[w.inst];
+  const int nn = min(HWIN, P.cells + 1 - w.anchor);
+  const int slot = blockIdx.x % NSLOT;
+  for (int sp = 0; sp < 2; ++sp)
+    for (int i = threadIdx.x; i < nn; i += BLOCK) {
+      const unsigned long long v = hist[sp][i];
+      if (v) {
+        atomicAdd(C.acc + ((size_t)sp * C.total_nodes + P.node + w.anchor + i) * NSLOT + slot, v);
+        hist[sp][i] = 0ull;
+      }
+    }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- main kernel
+template <typename R>
+struct LaneOut {
+  Mk<R> e[2];   // electrons produced by this lane (before population control)
+  Mk<R> i1;     // ion produced by this lane
+  int ne, ni;   // how many of e[] / i1 are set
+};
+
+template <typename R, int MODE>
+__global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
+  __shared__ uint32_t s_prefix[2 * MAX_INST + 1];
+  __shared__ unsigned long long s_hist[2][HWIN];
+  __shared__ uint32_t s_gen;
+  __shared__ uint32_t s_wave[BLOCK / WAVE][2];
+  __shared__ uint32_t s_base[2];
+  __shared__ uint32_t s_ev[NEV];
+  __shared__ double s_scan[BLOCK];
+
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
+  if (tid == 0) {
+    const unsigned long long ticket = atomicAdd(&C.g->wgc, 1ull);
+    s_gen = (uint32_t)(ticket / (unsigned long long)C.grid);
+  }
+  if (tid < NEV) s_ev[tid] = 0;
+  for (int i = tid; i < 2 * HWIN; i += BLOCK) s_hist[i / HWIN][i % HWIN] = 0ull;
+  __syncthreads();
+  const uint32_t g = s_gen;
+
+  // tile space of this generation: electrons of instance 0, ions of
+  // instance 0, electrons of instance 1, ...; an (instance, species) with P
+  // partitions gets P * max_p ceil(n_p / BLOCK) tiles, tile j serving
+  // partition j mod P
+  const int nk = 2 * C.n_inst;
+  {
+    const int per = (nk + BLOCK - 1) / BLOCK;
+    uint32_t loc = 0;
+    for (int k = tid * per; k < min(nk, (tid + 1) * per); ++k) {
+      const int parts = C.ip[k >> 1].parts;
+      uint32_t mx = 0;
+      for (int p = 0; p < parts; ++p) {
+        const uint32_t n = C.counts[cidx(C.n_inst, g % 3u, k >> 1, k & 1, p)];
+        mx = n > mx ? n : mx;
+      }
+      const uint32_t tl = ((mx + BLOCK - 1) / BLOCK) * (uint32_t)parts;
+      s_prefix[k + 1] = tl;
+      loc += tl;
+    }
+    double tot;
+    const double ex = block_exclusive_scan((double)loc, s_scan, tot);
+    uint32_t run = (uint32_t)ex;
+    if (tid == 0) s_prefix[0] = 0;
+    __syncthreads();
+    for (int k = tid * per; k < min(nk, (tid + 1) * per); ++k) {
+      run += s_prefix[k + 1];
+      s_prefix[k + 1] = run;
+    }
+    __syncthreads();
+  }
+  const uint32_t n_tiles = s_prefix[nk];
+  const uint32_t bsel = C.g->bufsel[g % 2u];
+  if (blockIdx.x == 0)
+    for (int k = tid; k <= nk; k += BLOCK) C.tile_start[k] = s_prefix[k];
+
+  // each workgroup takes a contiguous run of tiles, so that (for markers in
+  // cell order) its deposits stay inside one LDS window
+  const uint32_t per = (n_tiles + (uint32_t)C.grid - 1) / (uint32_t)C.grid;
+  const uint32_t t_begin = blockIdx.x * per, t_end = min(n_tiles, t_begin + per);
+  DepWin win{-1, 0};
+  for (uint32_t t = t_begin; t < t_end; ++t) {
+    // (instance, species) of the tile
+    int lo = 0, hi = nk;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_prefix[mid] <= t) lo = mid;
+      else hi = mid;
+    }
+    const int k = lo, inst = k >> 1, sp = k & 1;
+    const InstParams& P = C.ip[inst];
+    const uint32_t j = t - s_prefix[k];
+    const int part = (int)(j % (uint32_t)P.parts);
+    const uint32_t n_in = C.counts[cidx(C.n_inst, g % 3u, inst, sp, part)];
+    const uint32_t idx = (j / (uint32_t)P.parts) * BLOCK + tid;
+    const bool valid = idx < n_in;
+    const int64_t pbase = P.seg + (int64_t)part * P.cap_p;
+    if (inst != win.inst) {
+      // new instance for this workgroup: flush the old window, anchor the
+      // new one a quarter window below the tile's first marker
+      if (win.inst >= 0) dep_flush(C, s_hist, win);
+      const uint32_t first = (j / (uint32_t)P.parts) * BLOCK;
+      int c0 = first < n_in ? C.buf[bsel][sp].cell[pbase + first] : 0;
+      int anchor = c0 - HWIN / 4;
+      const int top = P.cells + 1 - HWIN;
+      anchor = anchor > top ? top : anchor;
+      win.anchor = anchor < 0 ? 0 : anchor;
+      win.inst = inst;
+    }
+    const InstState S0 = C.st[(g % 2u) * C.n_inst + inst];
+    const uint32_t step = S0.step;
+    const int pop = MODE == MODE_STEP ? S0.popmode : POP_NONE;
+    const Soa<R> in = C.buf[bsel][sp];
+    const R v0 = (R)P.v0;
+    const int limited = P.limited;
+
+    Mk<R> m;
+    if (valid) {
+      const int64_t s = pbase + idx;
+      m.cell = in.cell[s];
+      m.off = in.off[s];
+      m.vx = in.vx[s];
+      m.vy = in.vy[s];
+      m.vz = in.vz[s];
+      m.id = in.id[s];
+    }
+    LaneOut<R> o;
+    o.ne = o.ni = 0;
+    uint32_t ev = 0;    // bit per event slot
+    uint32_t err = 0;
+    bool see = false;
+
+    if (valid && MODE == MODE_REFRESH) {
+      if (sp == 0) { o.e[0] = m; o.ne = 1; }
+      else { o.i1 = m; o.ni = 1; }
+    } else if (valid) {
+      // gather at x^n and fly
+      const R* E = C.E + (size_t)(g % 2u) * C.total_nodes + P.node;
+      const R e0 = E[m.cell], e1 = E[m.cell + 1];
+      const R Ep = e0 + m.off * (e1 - e0);
+      const R a = (R)(sp == 0 ? P.qm_e : P.qm_i) * Ep;
+      const R c = m_sqrt(m.vy * m.vy + m.vz * m.vz);
+      R disp, vx1, tdisp;
+      bool turns;
+      flight<R>(m.vx, c, a, (R)P.dt, v0, limited, disp, vx1, turns, tdisp);
+      const R inv_dx = (R)P.inv_dx;
+      R f = m.off + disp * inv_dx;
+      const R fl = m_floor(f);
+      int cell = m.cell + (int)fl;
+      f -= fl;
+      if (f >= R(1)) f = one_below<R>();
+      bool out_lo = cell < 0, out_hi = cell >= P.cells;
+      if (turns) {
+        const R ft = m.off + tdisp * inv_dx;
+        const int ct = m.cell + (int)m_floor(ft);
+        out_lo = out_lo || ct < 0;
+        out_hi = out_hi || ct >= P.cells;
+      }
+      if (!m_finite(f) || !m_finite(vx1)) {
+        err |= ERR_NONFINITE;
+      } else if (out_lo) {
+        ev |= 1u << (sp == 0 ? EV_ABS_E_CATH : EV_ABS_I_CATH);
+        if (sp == 1) {
+          // ion-induced secondary emission (Sec. IV): an electron at rest at
+          // the cathode with probability gamma_se
+          const U4 r = draw(m.id, step, CH_SEE, C.seed, inst);
+          if ((r.x >> 9) < P.t_see) {
+            see = true;
+            ev |= 1u << EV_SEE;
+            Mk<R> e;
+            e.cell = 0;
+            e.off = R(0);
+            e.vx = e.vy = e.vz = R(0);
+            e.id = child(r.z, r.w);
+            o.e[0] = e;
+            o.ne = 1;
+          }
+        }
+      } else if (out_hi) {
+        ev |= 1u << (sp == 0 ? EV_ABS_E_ANODE : EV_ABS_I_ANODE);
+      } else {
+        m.cell = cell;
+        m.off = f;
+        m.vx = vx1;
+        if (sp == 0) {
+          // ---------------- electron-neutral collision
+          const U4 r = draw(m.id, step, CH_COLL, C.seed, inst);
+          const R v2 = m.vx * m.vx + m.vy * m.vy + m.vz * m.vz;
+          const R eps = v2 * (R)(0.5 * ME / QE);
+          int ch = -1;
+          if (C.fixed) {
+            const uint32_t u = r.x >> 9;
+            for (int q = 0; q < C.n_chan; ++q)
+              if (ch < 0 && u < P.t_fixed[q]) ch = q;
+          } else if ((r.x >> 9) < P.t_null_e) {
+            const R sp0 = m_sqrt(v2);
+            const R slow = limited ? (sp0 < v0 ? sp0 : v0) : sp0;
+            const R numax = (R)P.nu_max_e;
+            R cum;
+            ch = select_channel(C, eps, (R)P.n_g * slow, unif<R>(r.y) * numax, cum);
+            if (cum > numax * R(1.000001)) err |= ERR_NU_BOUND;
+          }
+          if (ch >= 0) {
+            const int kind = C.xs_kind[ch];
+            const R thr = C.xs_thr[ch];
+            R hx, hy, hz, ox, oy, oz;
+            unit3(m.vx, m.vy, m.vz, hx, hy, hz);
+            if (kind == 0) {  // elastic, Vahedi-Surendra angle
+              const R cx = vs_cos(eps, unif<R>(r.z));
+              const R e1 = eps * (R(1) - R(2.0 * ME / MAR) * (R(1) - cx));
+              turn(hx, hy, hz, cx, unif<R>(r.w), ox, oy, oz);
+              const R sp1 = m_sqrt(e1 * (R)(2.0 * QE / ME));
+              m.vx = sp1 * ox; m.vy = sp1 * oy; m.vz = sp1 * oz;
+              ev |= 1u << EV_ELASTIC;
+            } else if (kind == 1) {  // excitation, isotropic
+              R e1 = eps - thr;
+              e1 = e1 > R(0) ? e1 : R(0);
+              turn(hx, hy, hz, R(1) - R(2) * unif<R>(r.z), unif<R>(r.w), ox, oy, oz);
+              const R sp1 = m_sqrt(e1 * (R)(2.0 * QE / ME));
+              m.vx = sp1 * ox; m.vy = sp1 * oy; m.vz = sp1 * oz;
+              ev |= 1u << EV_EXCIT;
+            } else {  // ionization: share eps - I, spawn e- and Ar+
+              const U4 q = draw(m.id, step, CH_IONIZ, C.seed, inst);
+              const U4 b = draw(m.id, step, CH_IONBIRTH, C.seed, inst);
+              const U4 cid = draw(m.id, step, CH_CHILD, C.seed, inst);
+              R eav = eps - thr;
+              eav = eav > R(0) ? eav : R(0);
+              const R B = (R)C.ion_B;
+              R eej = B * m_tan(unif<R>(q.x) * m_atan(eav / (R(2) * B)));
+              R esc = eav - eej;
+              if (C.flags & 1u) { eej = R(0); esc = R(0); }
+              turn(hx, hy, hz, vs_cos(esc, unif<R>(r.z)), unif<R>(r.w), ox, oy, oz);
+              const R sps = m_sqrt(esc * (R)(2.0 * QE / ME));
+              R jx, jy, jz;
+              turn(hx, hy, hz, vs_cos(eej, unif<R>(q.y)), unif<R>(q.z), jx, jy, jz);
+              const R spj = m_sqrt(eej * (R)(2.0 * QE / ME));
+              m.vx = sps * ox; m.vy = sps * oy; m.vz = sps * oz;
+              Mk<R> e2 = m;
+              e2.vx = spj * jx; e2.vy = spj * jy; e2.vz = spj * jz;
+              e2.id = child(cid.x, cid.y);
+              Mk<R> i2 = m;
+              normals3<R>(b, (R)P.vth_i, i2.vx, i2.vy, i2.vz);
+              i2.id = child(cid.z, cid.w);
+              o.e[1] = e2;
+              o.i1 = i2;
+              o.ni = 1;
+              ev |= 1u << EV_IONIZ;
+            }
+          }
+          o.e[0] = m;
+          o.ne = (o.ni == 1) ? 2 : 1;
+        } else {
+          // ---------------- Ar+ charge exchange
+          const U4 r = draw(m.id, step, CH_CX, C.seed, inst);
+          bool hit = false;
+          if (C.fixed) {
+            hit = (r.x >> 9) < P.t_fixed_cx;
+          } else if ((r.x >> 9) < P.t_null_cx) {
+            const R v2 = m.vx * m.vx + m.vy * m.vy + m.vz * m.vz;
+            const R sp1 = m_sqrt(v2);
+            const R slow = limited ? (sp1 < v0 ? sp1 : v0) : sp1;
+            const R nu = (R)P.n_g * (R)P.sigma_cx * slow;
+            const R numax = (R)P.nu_max_cx;
+            if (nu > numax * R(1.000001)) err |= ERR_NU_BOUND;
+            hit = unif<R>(r.y) * numax < nu;
+          }
+          if (hit) {
+            const U4 b = draw(m.id, step, CH_CX | (1u << 8), C.seed, inst);
+            normals3<R>(b, (R)P.vth_i, m.vx, m.vy, m.vz);
+            ev |= 1u << EV_CX;
+          }
+          o.i1 = m;
+          o.ni = 1;
+        }
+      }
+    }
+
+    // ------------- population control on this lane's outputs
+    // electrons: o.e[0..ne), ions: o.i1 if ni; each kept (roulette) or
+    // doubled (split); clones are written right after the original
+    uint32_t keep_e = 0, keep_i = 0;  // bit j: output j survives roulette
+    uint64_t clone_e[2] = {0, 0}, clone_i = 0;
+    int cnt_e = 0, cnt_i = 0;
+    for (int j = 0; j < 2; ++j) {
+      if (j >= o.ne) break;
+      if (pop == POP_ROULETTE) {
+        const U4 r = draw(o.e[j].id, step, CH_ROULETTE, C.seed, inst);
+        if ((r.x >> 9) < (1u << 22)) { keep_e |= 1u << j; ++cnt_e; }
+      } else {
+        keep_e |= 1u << j;
+        ++cnt_e;
+        if (pop == POP_SPLIT) {
+          const U4 r = draw(o.e[j].id, step, CH_CHILD | (1u << 8), C.seed, inst);
+          clone_e[j] = child(r.x, r.y);
+          ++cnt_e;
+        }
+      }
+    }
+    if (o.ni) {
+      if (pop == POP_ROULETTE) {
+        const U4 r = draw(o.i1.id, step, CH_ROULETTE, C.seed, inst);
+        if ((r.x >> 9) < (1u << 22)) { keep_i = 1; ++cnt_i; }
+      } else {
+        keep_i = 1;
+        ++cnt_i;
+        if (pop == POP_SPLIT) {
+          const U4 r = draw(o.i1.id, step, CH_CHILD | (1u << 8), C.seed, inst);
+          clone_i = child(r.x, r.y);
+          ++cnt_i;
+        }
+      }
+    }
+    const int removed = pop == POP_ROULETTE ? (o.ne + o.ni) - (cnt_e + cnt_i) : 0;
+    const int split_added = pop == POP_SPLIT ? (o.ne + o.ni) : 0;
+
+    // ------------- deposit (fixed point, units of q w_j)
+    {
+      unsigned long long own_lo = 0, own_hi = 0;
+      int key = -1;
+      const int shift = C.dep_shift;
+      // markers of the tile's own species go through the wave reduction,
+      // the other species (new ions, secondary electrons) straight to LDS
+      for (int q = 0; q < o.ne; ++q) {
+        if (!(keep_e >> q & 1u)) continue;
+        const Mk<R>& e = o.e[q];
+        const R b = beta_of(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
+        const unsigned long long mul = clone_e[q] ? 2ull : 1ull;
+        const unsigned long long wl = fixed_pt<R>(b * (R(1) - e.off), shift) * mul;
+        const unsigned long long wh = fixed_pt<R>(b * e.off, shift) * mul;
+        if (sp == 0) {
+          key = e.cell;
+          own_lo += wl;
+          own_hi += wh;
+        } else {
+          dep_add(C.acc, C.acc, s_hist, win, 0, P.node, C.total_nodes, e.cell, wl, wh);
+        }
+      }
+      if (o.ni && keep_i) {
+        const Mk<R>& e = o.i1;
+        const R b = beta_of(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
+        const unsigned long long mul = clone_i ? 2ull : 1ull;
+        const unsigned long long wl = fixed_pt<R>(b * (R(1) - e.off), shift) * mul;
+        const unsigned long long wh = fixed_pt<R>(b * e.off, shift) * mul;
+        if (sp == 1) {
+          key = e.cell;
+          own_lo += wl;
+          own_hi += wh;
+        } else {
+          dep_add(C.acc, C.acc, s_hist, win, 1, P.node, C.total_nodes, e.cell, wl, wh);
+        }
+      }
+      const bool last = seg_reduce(key, own_lo, own_hi);
+      if (last && key >= 0)
+        dep_add(C.acc, C.acc, s_hist, win, sp, P.node, C.total_nodes, key, own_lo, own_hi);
+    }
+
+    // ------------- events (per tile, no global atomics)
+    {
+      uint32_t add[NEV];
+#pragma unroll
+      for (int q = 0; q < NEV; ++q) add[q] = (uint32_t)__popcll(__ballot((ev >> q) & 1u));
+      // roulette / split counts are not 0/1 per lane: reduce them in the wave
+      int rem = removed, spl = split_added;
+      for (int d = WAVE / 2; d > 0; d >>= 1) {
+        rem += __shfl_xor(rem, d);
+        spl += __shfl_xor(spl, d);
+      }
+      add[EV_ROULETTE] = (uint32_t)rem;
+      add[EV_SPLIT] = (uint32_t)spl;
+      if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NEV; ++q)
+          if (add[q]) atomicAdd(&s_ev[q], add[q]);
+      }
+      if (err) atomicOr(C.inst_err + inst, err);
+    }
+
+    if (MODE == MODE_STEP) {
+      // ------------- compaction: wave prefix by bit-sliced ballots
+      const unsigned long long lt = (1ull << lane) - 1ull;
+      const unsigned long long be0 = __ballot(cnt_e & 1), be1 = __ballot(cnt_e & 2),
+                               be2 = __ballot(cnt_e & 4);
+      const unsigned long long bi0 = __ballot(cnt_i & 1), bi1 = __ballot(cnt_i & 2);
+      const uint32_t pre_e = __popcll(be0 & lt) + 2 * __popcll(be1 & lt) + 4 * __popcll(be2 & lt);
+      const uint32_t pre_i = __popcll(bi0 & lt) + 2 * __popcll(bi1 & lt);
+      if (lane == 0) {
+        s_wave[wave][0] = __popcll(be0) + 2 * __popcll(be1) + 4 * __popcll(be2);
+        s_wave[wave][1] = __popcll(bi0) + 2 * __popcll(bi1);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t te = 0, ti = 0;
+        for (int w = 0; w < BLOCK / WAVE; ++w) {
+          const uint32_t a = s_wave[w][0], b = s_wave[w][1];
+          s_wave[w][0] = te;
+          s_wave[w][1] = ti;
+          te += a;
+          ti += b;
+        }
+        s_base[0] = te ? atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 0, part), te) : 0u;
+        s_base[1] = ti ? atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 1, part), ti) : 0u;
+      }
+      __syncthreads();
+      const Soa<R> oe = C.buf[1 - bsel][0], oi = C.buf[1 - bsel][1];
+      uint32_t pe = s_base[0] + s_wave[wave][0] + pre_e;
+      uint32_t pi = s_base[1] + s_wave[wave][1] + pre_i;
+      uint32_t werr = 0;
+      for (int j = 0; j < o.ne; ++j) {
+        if (!(keep_e >> j & 1u)) continue;
+        for (int rep = 0; rep < (clone_e[j] ? 2 : 1); ++rep) {
+          if (pe < (uint32_t)P.cap_p) {
+            const int64_t s = pbase + pe;
+            oe.cell[s] = o.e[j].cell;
+            oe.off[s] = o.e[j].off;
+            oe.vx[s] = o.e[j].vx;
+            oe.vy[s] = o.e[j].vy;
+            oe.vz[s] = o.e[j].vz;
+            oe.id[s] = rep ? clone_e[j] : o.e[j].id;
+          } else {
+            werr |= ERR_CAPACITY;
+          }
+          ++pe;
+        }
+      }
+      if (o.ni && keep_i) {
+        for (int rep = 0; rep < (clone_i ? 2 : 1); ++rep) {
+          if (pi < (uint32_t)P.cap_p) {
+            const int64_t s = pbase + pi;
+            oi.cell[s] = o.i1.cell;
+            oi.off[s] = o.i1.off;
+            oi.vx[s] = o.i1.vx;
+            oi.vy[s] = o.i1.vy;
+            oi.vz[s] = o.i1.vz;
+            oi.id[s] = rep ? clone_i : o.i1.id;
+          } else {
+            werr |= ERR_CAPACITY;
+          }
+          ++pi;
+        }
+      }
+      if (werr) atomicOr(C.inst_err + inst, werr);
+      (void)see;
+    }
+
+    // ------------- per-tile event counts for the tail kernel
+    __syncthreads();
+    if (tid == 0 && MODE == MODE_STEP)
+      for (int q = 0; q < NEV; ++q) C.tile_ev[(size_t)t * NEV + q] = s_ev[q];
+    __syncthreads();
+    if (tid < NEV) s_ev[tid] = 0;
+  }
+  if (win.inst >= 0) dep_flush(C, s_hist, win);
+}
+
+// ---------------------------------------------------------------- seeding
+template <typename R>
+__global__ void k_seed(Ctx<R> C, int inst, int mode, int64_t n, double sigma_v, uint32_t bsel) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const InstParams& P = C.ip[inst];
+  const Soa<R> o = C.buf[bsel][0];
+  // seed k goes to partition k mod P, slot k / P
+  const int64_t s = P.seg + (k % P.parts) * P.cap_p + k / P.parts;
+  o.id[s] = (uint64_t)k;
+  o.cell[s] = 0;
+  if (mode == 2) {
+    const U4 r0 = draw((uint64_t)k, 0u, CH_SEED, C.seed, inst);
+    const U4 r1 = draw((uint64_t)k, 0u, CH_SEED | (1u << 8), C.seed, inst);
+    o.off[s] = unif<R>(r0.x);
+    R a, b, c;
+    normals3<R>(r1, (R)sigma_v, a, b, c);
+    o.vx[s] = a;
+    o.vy[s] = b;
+    o.vz[s] = c;
+  } else {
+    o.off[s] = R(0);
+    o.vx[s] = R(0);
+    o.vy[s] = R(0);
+    o.vz[s] = R(0);
+  }
+}
+
+__global__ void k_philox_test(const uint32_t* ctr, uint32_t k0, uint32_t k1, int64_t n,
+                              uint32_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const U4 r = philox(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], k0, k1);
+  out[4 * i] = r.x;
+  out[4 * i + 1] = r.y;
+  out[4 * i + 2] = r.z;
+  out[4 * i + 3] = r.w;
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename R>
+hipError_t launch_gen(const Ctx<R>& C, int mode, hipStream_t s) {
+  if (mode == MODE_STEP) {
+    hipLaunchKernelGGL((k_gen<R, MODE_STEP>), dim3(C.grid), dim3(BLOCK), 0, s, C);
+    hipLaunchKernelGGL((k_tail<R, MODE_STEP>), dim3(C.n_inst), dim3(BLOCK), 0, s, C);
+  } else {
+    hipLaunchKernelGGL((k_gen<R, MODE_REFRESH>), dim3(C.grid), dim3(BLOCK), 0, s, C);
+    hipLaunchKernelGGL((k_tail<R, MODE_REFRESH>), dim3(C.n_inst), dim3(BLOCK), 0, s, C);
+  }
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_seed(const Ctx<R>& C, int inst, int mode, int64_t n, double sigma_v,
+                       uint32_t bsel, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + BLOCK - 1) / BLOCK;
+  hipLaunchKernelGGL((k_seed<R>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, C, inst, mode, n,
+                     sigma_v, bsel);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t occupancy_gen(int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_gen<R, MODE_STEP>, BLOCK,
+                                                      0);
+}
+
+template hipError_t launch_gen<float>(const Ctx<float>&, int, hipStream_t);
+template hipError_t launch_gen<double>(const Ctx<double>&, int, hipStream_t);
+template hipError_t launch_seed<float>(const Ctx<float>&, int, int, int64_t, double, uint32_t,
+                                       hipStream_t);
+template hipError_t launch_seed<double>(const Ctx<double>&, int, int, int64_t, double, uint32_t,
+                                        hipStream_t);
+template hipError_t occupancy_gen<float>(int*);
+template hipError_t occupancy_gen<double>(int*);
+
+hipError_t launch_philox_test(const uint32_t* ctr, uint32_t k0, uint32_t k1, int64_t n,
+                              uint32_t* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + BLOCK - 1) / BLOCK;
+  hipLaunchKernelGGL(k_philox_test, dim3((unsigned)blocks), dim3(BLOCK), 0, s, ctr, k0, k1, n,
+                     out);
+  return hipGetLastError();
+}
+
+}  // namespace slpic

@@ -1,0 +1,165 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import configs, xsec
+from parity import compare_populations, STAT_INT
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a HIP device", allow_module_level=True)
+
+import paper_2103_12194_amd as slpic  # noqa: E402
+
+
+def _c1_small(n_seed=5000, n_target=3000, **kw):
+    inst = configs.Instance(d=0.01, p_torr=1.0, V=300.0, cells=64,
+                            gamma_se=0.07, seed_mode=configs.SEED_MAXWELL_CELL0,
+                            n_seed=n_seed, n_target=n_target,
+                            capacity=configs.capacity_for(n_target, n_seed))
+    for k, v in kw.items():
+        setattr(inst, k, v)
+    return inst
+
+
+def test_device_philox_matches_oracle():
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2 ** 32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[0] = 0
+    ctr[1] = 0xFFFFFFFF
+    key = (0x5EED, 7)
+    got = slpic.philox_device(ctr, *key)
+    want = np.array([oracle.philox4x32(c, key) for c in ctr])
+    assert np.array_equal(got, want)
+
+
+def test_fp64_seeding_and_initial_field(xs_argon):
+    inst = _c1_small(n_seed=3001, n_target=0)
+    run = configs.Run(precision=64, w_j0=1e5)
+    gpu = slpic.Sim([inst], run, xs_argon)
+    ref = oracle.Sim(inst, run, xs_argon)
+    compare_populations(gpu.read(0), ref.read(0), 1e-12 * inst.cells, 1e-12,
+                        gpu.scalars()["v0"], label="seed")
+    for a, b, name in zip(gpu.fields(), ref.fields(), ("rho", "phi", "E")):
+        scale = np.abs(b).max()
+        assert np.allclose(a, b, rtol=0, atol=1e-11 * scale), name
+    sg, so = gpu.scalars(), ref.scalars()
+    for k in ("dx", "dt", "v0", "n_g", "nu_max_e", "nu_max_cx", "w_j"):
+        assert sg[k] == pytest.approx(so[k], rel=1e-15), k
+
+
+@pytest.mark.parametrize("steps", [60])
+def test_fp64_full_physics_matches_oracle_step_by_step(xs_argon, steps):
+    inst = _c1_small()
+    run = configs.Run(precision=64)
+    gpu = slpic.Sim([inst], run, xs_argon)
+    ref = oracle.Sim(inst, run, xs_argon)
+    v0 = gpu.scalars()["v0"]
+    for n in range(steps):
+        gpu.step(1)
+        ref.step(1)
+        sg, so = gpu.stats(), ref.stats()
+        for k in STAT_INT:
+            assert sg[k] == so[k], (n, k, sg[k], so[k])
+        assert sg["w_j"] == so["w_j"]
+        assert sg["w_e"] == pytest.approx(so["w_e"], rel=1e-9)
+        assert sg["w_i"] == pytest.approx(so["w_i"], rel=1e-9, abs=1e-9)
+    assert gpu.sync() == 0
+    for sp in (0, 1):
+        w = compare_populations(gpu.read(sp), ref.read(sp), 1e-12 * inst.cells,
+                                1e-12, v0, label=f"species {sp}")
+        print("fp64 full physics", sp, w)
+    E_g, E_o = gpu.fields()[2], ref.fields()[2]
+    assert np.allclose(E_g, E_o, rtol=1e-11)
+
+
+def test_fp32_single_step_from_loaded_state(xs_argon):
+    cells = 64
+    inst = configs.Instance(d=0.01, p_torr=3.0, V=300.0, cells=cells,
+                            gamma_se=0.3, seed_mode=configs.SEED_NONE,
+                            capacity=40000)
+    e, i = synth.markers.mixed(7, 9000, 4100, cells)
+    run32, run64 = configs.Run(precision=32), configs.Run(precision=64)
+    gpu = slpic.Sim([inst], run32, xs_argon)
+    ref = oracle.Sim(inst, run64, xs_argon)
+    for sim in (gpu, ref):
+        sim.load(0, e)
+        sim.load(1, i)
+    gpu.step(1)
+    ref.step(1)
+    assert gpu.sync() == 0
+    v0 = gpu.scalars()["v0"]
+    for sp in (0, 1):
+        w = compare_populations(gpu.read(sp), ref.read(sp), 1e-5 * cells, 1e-5,
+                                v0, tie_tol=1e-4, label=f"species {sp}")
+        print("fp32 single step", sp, w)
+    sg, so = gpu.stats(), ref.stats()
+    for k in STAT_INT:
+        assert abs(sg[k] - so[k]) <= 3, (k, sg[k], so[k])
+
+
+def test_fp32_fixed_event_many_steps():
+    xs = xsec.fixed_event([0.05, 0.02, 0.01], probs_cx=0.05)
+    inst = _c1_small(n_seed=4000, n_target=0, capacity=60000)
+    run32, run64 = configs.Run(precision=32), configs.Run(precision=64)
+    gpu = slpic.Sim([inst], run32, xs)
+    ref = oracle.Sim(inst, run64, xs)
+    gpu.step(40)
+    ref.step(40)
+    assert gpu.sync() == 0
+    v0 = gpu.scalars()["v0"]
+    for sp in (0, 1):
+        compare_populations(gpu.read(sp), ref.read(sp), 1e-4 * inst.cells, 1e-4,
+                            v0, tie_tol=1e-4, label=f"species {sp}")
+
+
+def test_batched_instances_match_independent_oracles(xs_argon):
+    insts = [_c1_small(n_seed=700, n_target=500),
+             configs.Instance(d=0.02, p_torr=0.5, V=250.0, cells=130,
+                              gamma_se=0.1, seed_mode=configs.SEED_CATHODE,
+                              n_seed=300, n_target=0, capacity=20000),
+             _c1_small(n_seed=0, n_target=0, capacity=256),
+             _c1_small(n_seed=1025, n_target=4000, V=400.0)]
+    run = configs.Run(precision=64)
+    gpu = slpic.Sim(insts, run, xs_argon)
+    refs = [oracle.Sim(x, run, xs_argon, instance_index=k) for k, x in enumerate(insts)]
+    gpu.step(25)
+    for r in refs:
+        r.step(25)
+    assert gpu.sync() == 0
+    for k, (x, r) in enumerate(zip(insts, refs)):
+        v0 = gpu.scalars(k)["v0"]
+        for sp in (0, 1):
+            w = compare_populations(gpu.read(sp, k), r.read(sp), 1e-12 * x.cells,
+                                    1e-12, v0, label=f"inst {k} sp {sp}")
+            print("batched", k, sp, w)
+        sg, so = gpu.stats(inst=k), r.stats()
+        for key in STAT_INT:
+            assert sg[key] == so[key], (k, key)
+
+
+def test_capacity_overflow_is_reported(xs_argon):
+    inst = _c1_small(n_seed=1000, n_target=0, capacity=1000)
+    gpu = slpic.Sim([inst], configs.Run(precision=32), xs_argon)
+    gpu.step(300)
+    with pytest.raises(slpic.SlpicError) as ei:
+        gpu.sync()
+    assert ei.value.code == -3
+    assert gpu.count(0) <= 1000 and gpu.count(1) <= 1000
+
+
+def test_invalid_load_is_rejected(xs_argon):
+    inst = _c1_small(n_seed=10, n_target=0)
+    gpu = slpic.Sim([inst], configs.Run(precision=32), xs_argon)
+    bad = synth.markers.electrons(1, 5, 64)
+    bad["cell"][2] = 64
+    with pytest.raises(slpic.SlpicError):
+        gpu.load(0, bad)
+    assert gpu.count(0) == 10
