@@ -48,7 +48,7 @@ uint32_t prob_threshold(double P) {
 }
 
 struct Layout {
-  size_t ip, st, counts, tile_start, tile_ev, acc, E, E64, phi, rho, scratch, ring, inst_err,
+  size_t ip, st, counts, ev, acc, E, E64, phi, rho, scratch, ring, inst_err,
       glob, xs_e, xs_sig, xs_thr, xs_kind;
   size_t part[2][2][6];  // [buffer][species][array]
   size_t total;
@@ -101,8 +101,7 @@ bool make_layout(const slpic_config* cfg, const slpic_instance* inst, int n_inst
   L.ip = take(sizeof(InstParams) * n_inst);
   L.st = take(sizeof(InstState) * 2 * n_inst);
   L.counts = take(sizeof(uint32_t) * 3 * 2 * MAX_PART * (size_t)n_inst);
-  L.tile_start = take(sizeof(uint32_t) * (2 * (size_t)n_inst + 1));
-  L.tile_ev = take(sizeof(uint32_t) * NEV * (size_t)L.max_tiles);
+  L.ev = take(sizeof(unsigned long long) * NEV * NSLOT * (size_t)n_inst);
   L.acc = take(sizeof(unsigned long long) * 2 * NSLOT * (size_t)nodes);
   L.E = take(rs * 2 * nodes);
   L.E64 = take(8 * 2 * (size_t)nodes);
@@ -298,8 +297,7 @@ void fill_ctx(slpic_t* h, Ctx<R>& C) {
     }
   C.st = reinterpret_cast<InstState*>(w + L.st);
   C.counts = reinterpret_cast<uint32_t*>(w + L.counts);
-  C.tile_start = reinterpret_cast<uint32_t*>(w + L.tile_start);
-  C.tile_ev = reinterpret_cast<uint32_t*>(w + L.tile_ev);
+  C.ev = reinterpret_cast<unsigned long long*>(w + L.ev);
   C.acc = reinterpret_cast<unsigned long long*>(w + L.acc);
   C.E = reinterpret_cast<R*>(w + L.E);
   C.E64 = reinterpret_cast<double*>(w + L.E64);
@@ -326,8 +324,11 @@ void fill_ctx(slpic_t* h, Ctx<R>& C) {
   while ((1ll << bits) <= capmax) ++bits;
   // a node sums at most one unit per marker; markers produced beyond the
   // capacity (up to 4x with ionization and splitting) still deposit
-  const int want = h->cfg.precision == 64 ? 44 : 32;
+  const int want = h->cfg.precision == 64 ? 44 : 31;
   C.dep_shift = std::min(want, 60 - bits);
+  int maxc = 0;
+  for (auto& I : h->inst) maxc = std::max(maxc, I.cells);
+  C.tail_lds = (maxc + 1) * (int)sizeof(double);
 }
 
 template <typename R>
@@ -546,6 +547,15 @@ int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst
     return rc;
   }
   h->grid = std::max(1, std::min(cus * std::max(per_cu, 1), h->L.max_tiles));
+  int lds_max = 0;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    lds_max = 65536;
+  int maxc = 0;
+  for (int i = 0; i < n_inst; ++i) maxc = std::max(maxc, inst[i].cells);
+  if ((size_t)(maxc + 1) * sizeof(double) + 1024 > (size_t)lds_max) {
+    delete h;
+    return fail(nullptr, SLPIC_INVALID_ARG, "too many cells for the device's shared memory per block");
+  }
   fill_ctx(h, h->c32);
   fill_ctx(h, h->c64);
   int rc = cfg->precision == 64 ? upload_tables(h, h->c64, xs) : upload_tables(h, h->c32, xs);
@@ -575,7 +585,7 @@ int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst
   if (e == hipSuccess) e = up(L.st, st.data(), sizeof(InstState) * st.size());
   if (e == hipSuccess) e = up(L.counts, counts.data(), sizeof(uint32_t) * counts.size());
   if (e == hipSuccess) e = up(L.glob, &G, sizeof(G));
-  if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.tile_start, 0, sizeof(uint32_t) * (2 * n_inst + 1), h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.ev, 0, sizeof(unsigned long long) * NEV * NSLOT * n_inst, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.acc, 0, sizeof(unsigned long long) * 2 * NSLOT * L.total_nodes, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.inst_err, 0, sizeof(uint32_t) * n_inst, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.ring, 0, sizeof(StatsRow) * RING * n_inst, h->stream);

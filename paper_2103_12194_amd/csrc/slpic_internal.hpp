@@ -101,8 +101,7 @@ struct Ctx {
   Soa<R> buf[2][2];          // [buffer][species]
   InstState* st;             // [2][n_inst]
   uint32_t* counts;          // [3][n_inst][2][MAX_PART]
-  uint32_t* tile_start;      // [2 n_inst + 1] tile prefix of the last launch
-  uint32_t* tile_ev;         // [max_tiles][NEV]
+  unsigned long long* ev;    // [n_inst][NEV][NSLOT] event counters of a step
   unsigned long long* acc;   // [2 species][total_nodes][NSLOT] fixed-point deposit
   R* E;                      // [2][total_nodes] field in kernel precision
   double* E64;               // [2][total_nodes]
@@ -123,6 +122,7 @@ struct Ctx {
   int fixed;
   uint32_t flags, seed;
   int dep_shift;             // fraction bits of the fixed-point deposit
+  int tail_lds;              // dynamic LDS bytes of the tail kernel
 };
 
 }  // namespace slpic

@@ -61,12 +61,12 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
                                      uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-    c0 = hi1 ^ c1 ^ k0;
-    c2 = hi0 ^ c3 ^ k1;
-    c1 = lo1;
-    c3 = lo0;
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -103,65 +103,71 @@ __device__ __forceinline__ void normals3(U4 r, R sigma, R& a, R& b, R& c) {
 }
 
 // ---------------------------------------------------------------- flight
+// Arithmetic of the flight solve.  The FP64 instantiation uses the
+// correctly rounded library functions; the FP32 one uses the hardware
+// square root, reciprocal and base-2 logarithm (about one ulp each), which
+// keeps the flight within a few 1e-7 relative, far inside the FP32 budget.
+template <typename R> struct Fm;
+template <> struct Fm<double> {
+  static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+  static __device__ __forceinline__ double div(double x, double y) { return x / y; }
+  static __device__ __forceinline__ double asinh(double x) { return ::asinh(x); }
+};
+template <> struct Fm<float> {
+  static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+  static __device__ __forceinline__ float div(float x, float y) { return x * __builtin_amdgcn_rcpf(y); }
+  // asinh for x >= 0: series below 1/16, else ln 2 * log2(x + sqrt(x^2 + 1))
+  static __device__ __forceinline__ float asinh(float x) {
+    if (x < 0.0625f) {
+      const float x2 = x * x;
+      return x * (1.0f - x2 * (0.16666667f - x2 * 0.075f));
+    }
+    return 0.69314718f * __builtin_amdgcn_logf(x + __builtin_amdgcn_sqrtf(x * x + 1.0f));
+  }
+};
+
 // Integral of sqrt(u^2 + c^2) over [p, p + len], p >= 0, in a form without
 // cancellation for short intervals (q = p + len, W(u) = sqrt(u^2 + c^2)):
 //   q W(q) - p W(p) = len (q + p)(q^2 + p^2 + c^2) / (q W(q) + p W(p)),
 //   asinh(q/c) - asinh(p/c) = asinh(len (q + p) / (q W(p) + p W(q))).
 template <typename R>
-__device__ R sqrt_span(R p, R len, R c) {
-  if (!(len > R(0))) return R(0);
+__device__ __forceinline__ R sqrt_span(R p, R len, R c) {
   const R q = p + len, sq = p + q;
-  if (c == R(0)) return R(0.5) * len * sq;
   const R c2 = c * c;
-  const R Wp = m_sqrt(p * p + c2), Wq = m_sqrt(q * q + c2);
-  const R t1 = len * sq * (q * q + p * p + c2) / (q * Wq + p * Wp);
-  const R t2 = c2 * m_asinh(len * sq / (q * Wp + p * Wq));
+  const R Wp = Fm<R>::sqrt(p * p + c2), Wq = Fm<R>::sqrt(q * q + c2);
+  const R den1 = q * Wq + p * Wp, den2 = q * Wp + p * Wq;
+  const bool empty = !(len > R(0)) || !(den1 > R(0));
+  const R t1 = empty ? R(0) : Fm<R>::div(len * sq * (q * q + p * p + c2), den1);
+  const R t2 = (empty || c2 == R(0)) ? R(0) : c2 * Fm<R>::asinh(Fm<R>::div(len * sq, den2));
   return R(0.5) * (t1 + t2);
 }
 
-// Wall-clock time (times |a|) to move s from a to a + len:
-// integral of max(1, sqrt(u^2 + c^2) / v0), split where |v| = v0 and at 0.
+// Integral of max(1, W(u)/v0) over [p, p + len] for p >= 0, where |v| < v0
+// (beta = 1) below u = ss: a linear part and one square-root part.
 template <typename R>
-__device__ R time_span(R a, R len, R c, R v0) {
-  const R ss = c < v0 ? m_sqrt(v0 * v0 - c * c) : R(0);
-  const R b = a + len;
-  R start = a, total = R(0);
-  const R brk[3] = {-ss, R(0), ss};
-#pragma unroll
-  for (int k = 0; k <= 3; ++k) {
-    R p = start, piece;
-    if (k < 3) {
-      if (!(brk[k] > start && brk[k] < b)) continue;
-      piece = brk[k] - start;
-      start = brk[k];
-    } else {
-      piece = (p == a) ? len : b - p;
-    }
-    const R mid = p + R(0.5) * piece;
-    if (c < v0 && (mid < ss && mid > -ss)) total += piece;
-    else if (mid < R(0)) total += sqrt_span(-(p + piece), piece, c) / v0;
-    else total += sqrt_span(p, piece, c) / v0;
-  }
-  return total;
+__device__ __forceinline__ R half_span(R p, R len, R c, R inv_v0, R ss) {
+  const R q = p + len;
+  const bool split = p < ss;
+  const R e = q < ss ? q : ss;                 // end of the linear part
+  const R lin = split ? e - p : R(0);
+  const R start = split ? e : p;
+  R rest = split ? q - e : len;                // keeps len exact when unsplit
+  rest = rest > R(0) ? rest : R(0);
+  return lin + sqrt_span(start, rest, c) * inv_v0;
 }
 
+// Wall-clock time (times |a|) for s to move from s0 to s0 + len: the
+// integral of max(1, |v|/v0) ds, split at s = 0 by symmetry.  Always two
+// half spans (one empty unless s crosses 0), chosen without branching.
 template <typename R>
-__device__ __forceinline__ R c0_time(R s, R v0) {  // time integral from 0 to s for c = 0
-  const R as = s < R(0) ? -s : s;
-  const R t = as <= v0 ? as : (as * as + v0 * v0) / (R(2) * v0);
-  return s < R(0) ? -t : t;
+__device__ __forceinline__ R time_span(R s0, R len, R c, R inv_v0, R ss) {
+  const R s1 = s0 + len;
+  const bool pos = s0 >= R(0), neg = !(s1 > R(0));
+  const R p1 = pos ? s0 : (neg ? -s1 : R(0));
+  const R l1 = (pos || neg) ? len : -s0;
+  const R l2 = (pos || neg) ? R(0) : s1;
+  return half_span(p1, l1, c, inv_v0, ss) + half_span(R(0), l2, c, inv_v0, ss);
 }
-
-template <typename R>
-__device__ __forceinline__ R c0_inverse(R y, R v0) {
-  const R ay = y < R(0) ? -y : y;
-  const R s = ay <= v0 ? ay : m_sqrt(R(2) * v0 * ay - v0 * v0);
-  return y < R(0) ? -s : s;
-}
-
-struct FlightOut {
-  bool turns;
-};
 
 // Exact speed-limited flight over dt in the uniform acceleration a along x.
 // Returns the displacement, the new v_x and, when v_x changes sign inside the
@@ -177,36 +183,57 @@ __device__ void flight(R vx, R c, R a, R dt, R v0, int limited, R& disp, R& vx1,
     tau = dt;  // beta == 1 along the whole flight
     dv = a * dt;
   } else if (a == R(0)) {
-    tau = dt * v0 / m_sqrt(w0sq);
+    tau = dt * v0 / Fm<R>::sqrt(w0sq);
     dv = R(0);
   } else {
+    // reflect so that a > 0, unknown delta = s1 - s0 in (0, |a| dt]:
+    //   time_span(s0, delta) = |a| dt
     const R sg = a > R(0) ? R(1) : R(-1);
     const R at = a * sg, s0 = sg * vx;
-    const R rhs = at * dt;
-    R lo = R(0), hi = rhs;
-    R delta = c0_inverse(c0_time(s0, v0) + rhs, v0) - s0;
-    if (!(delta > lo && delta < hi)) {
-      const R h0 = m_sqrt(w0sq) / v0;
-      delta = rhs / (h0 > R(1) ? h0 : R(1));
+    const R rhs = at * dt, inv_v0 = R(1) / v0;
+    const R ss = c < v0 ? Fm<R>::sqrt(v0 * v0 - c * c) : R(0);
+    const R w0 = Fm<R>::sqrt(w0sq);
+    R lo = R(0), hi = rhs, delta;
+    if (w0 > v0) {
+      // speed-limited start: path length w0 d + s0 d^2 / (2 w0) = v0 rhs
+      const R disc = w0 * w0 + R(2) * s0 * v0 * Fm<R>::div(rhs, w0);
+      delta = disc > R(0) ? Fm<R>::div(R(2) * v0 * rhs, w0 + Fm<R>::sqrt(disc)) : R(-1);
+    } else {
+      // slow start: the c = 0 motion (beta = 1 up to v0, then v0 ds = s ds)
+      const R as = s0 < R(0) ? -s0 : s0;
+      R y = as <= v0 ? as : (as * as + v0 * v0) * R(0.5) * inv_v0;
+      y = (s0 < R(0) ? -y : y) + rhs;
+      const R ay = y < R(0) ? -y : y;
+      const R sy = ay <= v0 ? ay : Fm<R>::sqrt(R(2) * v0 * ay - v0 * v0);
+      delta = (y < R(0) ? -sy : sy) - s0;
     }
-    const R tol = sizeof(R) == 4 ? R(2e-7) : R(4e-16);
+    if (!(delta > lo && delta < hi)) delta = rhs * (w0 > v0 ? v0 / w0 : R(1));
+    // Halley iteration on f(delta) = time_span - rhs, f' = max(1, W/v0),
+    // f'' = s / (v0 W) where W > v0, kept inside the bracket [lo, hi]
+    const R tol = sizeof(R) == 4 ? R(1e-7) : R(1e-16);
+    const R quick = sizeof(R) == 4 ? R(3e-4) : R(1e-8);  // error after a step ~ step^2
     for (int it = 0; it < 40; ++it) {
-      const R f = time_span(s0, delta, c, v0) - rhs;
+      const R f = time_span(s0, delta, c, inv_v0, ss) - rhs;
       if (f > R(0)) hi = delta;
       else if (f < R(0)) lo = delta;
       else break;
       const R s = s0 + delta;
-      R hp = m_sqrt(s * s + c * c) / v0;
-      hp = hp > R(1) ? hp : R(1);
-      const R step = -f / hp;
-      // converged: the Newton step is below the tolerance (and may be below
-      // the resolution of delta, where the bracket test would reject it)
-      if ((step < R(0) ? -step : step) <= tol * delta) {
-        const R dn = delta + step;
+      const R W = Fm<R>::sqrt(s * s + c * c);
+      R step;
+      if (W > v0) {
+        const R hp = W * inv_v0, hpp = Fm<R>::div(s * inv_v0, W);
+        step = Fm<R>::div(R(-2) * f * hp, R(2) * hp * hp - f * hpp);
+      } else {
+        step = -f;
+      }
+      R dn = delta + step;
+      const R astep = step < R(0) ? -step : step;
+      if (astep <= quick * delta) {
+        // converged to within step^2: take the step unless it leaves the
+        // bracket (possible when it is below the resolution of delta)
         if (dn > lo && dn < hi) delta = dn;
         break;
       }
-      R dn = delta + step;
       if (!(dn > lo && dn < hi)) dn = R(0.5) * (lo + hi);
       delta = dn;
       if (hi - lo <= tol * hi) break;
@@ -308,30 +335,16 @@ struct Mk {  // one marker's state
 __device__ __forceinline__ uint32_t gen_slot3(uint32_t g, uint32_t k) { return (g + k) % 3u; }
 
 template <typename R>
-__device__ __forceinline__ unsigned long long fixed_pt(R w, int shift) {
-  // w in [0, 1] -> round(w 2^shift)
-  return (unsigned long long)((double)w * (double)(1ull << shift) + 0.5);
+__device__ __forceinline__ unsigned long long fixed_pt(R w, int shift);
+// w in [0, 1] -> round(w 2^shift); FP32 uses shift <= 31 so one
+// conversion to a 32-bit integer suffices
+template <>
+__device__ __forceinline__ unsigned long long fixed_pt<float>(float w, int shift) {
+  return (unsigned long long)__float2uint_rn(__builtin_ldexpf(w, shift));
 }
-
-// inclusive segmented sum over lanes with equal key in runs; returns true in
-// the last lane of each run
-__device__ __forceinline__ bool seg_reduce(int key, unsigned long long& lo,
-                                           unsigned long long& hi) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int prev = __shfl_up(key, 1);
-  int head = (lane == 0 || prev != key) ? 1 : 0;
-#pragma unroll
-  for (int d = 1; d < WAVE; d <<= 1) {
-    const unsigned long long lo_u = __shfl_up(lo, d);
-    const unsigned long long hi_u = __shfl_up(hi, d);
-    const int head_u = __shfl_up(head, d);
-    if (lane >= d) {
-      if (!head) { lo += lo_u; hi += hi_u; }
-      head |= head_u;
-    }
-  }
-  const int next = __shfl_down(key, 1);
-  return lane == WAVE - 1 || next != key;
+template <>
+__device__ __forceinline__ unsigned long long fixed_pt<double>(double w, int shift) {
+  return (unsigned long long)(__builtin_ldexp(w, shift) + 0.5);
 }
 
 // ---------------------------------------------------------------- tail
@@ -344,132 +357,174 @@ __device__ __forceinline__ bool seg_reduce(int key, unsigned long long& lo,
 // over the half cell at each electrode.
 constexpr double EPS0 = 8.8541878128e-12;
 
-__device__ double block_exclusive_scan(double v, double* sh, double& total) {
-  // 256 threads, returns the exclusive prefix of v; total receives the sum
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int d = 1; d < BLOCK; d <<= 1) {
-    const double add = t >= d ? sh[t - d] : 0.0;
-    __syncthreads();
-    sh[t] += add;
-    __syncthreads();
-  }
-  const double incl = sh[t];
-  total = sh[BLOCK - 1];
-  __syncthreads();
-  return incl - v;
-}
 
 __device__ __forceinline__ size_t cidx(int n_inst, uint32_t slot, int inst, int sp, int p) {
   return (((size_t)slot * n_inst + inst) * 2 + sp) * MAX_PART + p;
 }
 
+// Exclusive prefix sums of NV values over the 256 threads of a workgroup:
+// wave-level shuffles, then one exchange of the four wave totals through
+// LDS (sh holds 4 NV doubles).  ex[] receives the prefixes, tot[] the sums.
+template <int NV>
+__device__ __forceinline__ void block_scan(const double (&v)[NV], double (&ex)[NV],
+                                           double (&tot)[NV], double* sh) {
+  const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+  double inc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) inc[k] = v[k];
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const double u = __shfl_up(inc[k], d);
+      if (lane >= d) inc[k] += u;
+    }
+  }
+  if (lane == WAVE - 1)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[wave * NV + k] = inc[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double base = 0.0, t = 0.0;
+    for (int w = 0; w < BLOCK / WAVE; ++w) {
+      const double sw = sh[w * NV + k];
+      if (w < wave) base += sw;
+      t += sw;
+    }
+    const double prev = __shfl_up(inc[k], 1);
+    ex[k] = base + (lane == 0 ? 0.0 : prev);
+    tot[k] = t;
+  }
+  __syncthreads();
+}
+
 // One workgroup per instance, launched after the particle kernel: charge
 // density from the fixed-point deposit, Poisson solve, statistics row,
 // population-control decision for the next step and the generation switch.
+// Every global load is issued up front; the prefix sums run in LDS
+// (dynamic shared memory of cells + 1 doubles).
 template <typename R, int MODE>
 __global__ void __launch_bounds__(BLOCK) k_tail(Ctx<R> C) {
-  __shared__ double sh[BLOCK];
+  extern __shared__ double s_S[];          // rho, then S
+  __shared__ double sh[4 * 3];
+  __shared__ unsigned long long s_ev[NEV];
+  __shared__ uint32_t s_cnt[2][2];         // [in, out][species]
+  __shared__ InstState s_cur;
+  __shared__ uint32_t s_bs;
   const int inst = blockIdx.x, t = threadIdx.x;
   const uint32_t g = (uint32_t)(C.g->wgc / (unsigned long long)C.grid) - 1u;
   const InstParams& P = C.ip[inst];
   const int N = P.cells, node = P.node;
-  const uint32_t sc = g % 2u, sn = (g + 1) % 2u;
-  const InstState cur = C.st[sc * C.n_inst + inst];
+  const uint32_t sn = (g + 1) % 2u;
+  if (t < NEV) s_ev[t] = 0ull;
+  if (t < 4) s_cnt[t / 2][t % 2] = 0u;
+  if (t == 0) {
+    s_cur = C.st[(g % 2u) * C.n_inst + inst];
+    s_bs = C.g->bufsel[g % 2u];
+  }
+  __syncthreads();
+  const InstState cur = s_cur;
   const double factor = MODE == MODE_STEP
                             ? (cur.popmode == POP_ROULETTE ? 2.0 : (cur.popmode == POP_SPLIT ? 0.5 : 1.0))
                             : 1.0;
   const double wj = cur.w_j * factor;
   const double unit = 1.0 / (double)(1ull << C.dep_shift);
   const double qvol = QE * wj * unit / (P.area * P.dx);
-  unsigned long long* acc_e = C.acc + (size_t)node * NSLOT;
-  unsigned long long* acc_i = C.acc + ((size_t)C.total_nodes + node) * NSLOT;
-  double* rho = C.rho + (size_t)sn * C.total_nodes + node;
-  double* S = C.scratch + node;
-  const int chunk = (N + 1 + BLOCK - 1) / BLOCK;
-  const int i0 = t * chunk, i1 = min(i0 + chunk, N + 1);
 
-  // pass 1: charge density, species totals, interior prefix S
-  double se = 0.0, si = 0.0, loc = 0.0;
-  for (int i = i0; i < i1; ++i) {
-    unsigned long long ae = 0ull, ai = 0ull;
-    for (int q = 0; q < NSLOT; ++q) {
-      ae += acc_e[(size_t)i * NSLOT + q];
-      ai += acc_i[(size_t)i * NSLOT + q];
-      acc_e[(size_t)i * NSLOT + q] = 0ull;
-      acc_i[(size_t)i * NSLOT + q] = 0ull;
+  // charge density at the nodes (strided: coalesced reads of the NSLOT
+  // copies), species totals; events and marker counts alongside
+  double se = 0.0, si = 0.0;
+  {
+    unsigned long long* acc_e = C.acc + (size_t)node * NSLOT;
+    unsigned long long* acc_i = C.acc + ((size_t)C.total_nodes + node) * NSLOT;
+    double* rho = C.rho + (size_t)sn * C.total_nodes + node;
+    for (int i = t; i <= N; i += BLOCK) {
+      unsigned long long ae = 0ull, ai = 0ull;
+#pragma unroll
+      for (int q = 0; q < NSLOT; ++q) {
+        ae += acc_e[(size_t)i * NSLOT + q];
+        ai += acc_i[(size_t)i * NSLOT + q];
+      }
+#pragma unroll
+      for (int q = 0; q < NSLOT; ++q) {
+        acc_e[(size_t)i * NSLOT + q] = 0ull;
+        acc_i[(size_t)i * NSLOT + q] = 0ull;
+      }
+      se += (double)ae;
+      si += (double)ai;
+      double r = ((double)ai - (double)ae) * qvol;
+      if (i == 0 || i == N) r *= 2.0;  // half cells at the electrodes
+      rho[i] = r;
+      s_S[i] = r;
     }
-    se += (double)ae;
-    si += (double)ai;
-    double r = ((double)ai - (double)ae) * qvol;
-    if (i == 0 || i == N) r *= 2.0;  // half cells at the electrodes
-    rho[i] = r;
-    if (i >= 1 && i <= N - 1) loc += r;
-  }
-  double tot;
-  const double off1 = block_exclusive_scan(loc, sh, tot);
-  double se_tot, si_tot;
-  block_exclusive_scan(se, sh, se_tot);
-  block_exclusive_scan(si, sh, si_tot);
-  // pass 2: S_i = sum_{j=1..i} rho_j (S_0 = 0), U = sum over k < N of S_k
-  double run = off1, usum = 0.0;
-  for (int i = i0; i < i1; ++i) {
-    if (i >= 1 && i <= N - 1) run += rho[i];
-    const double s = (i == 0) ? 0.0 : (i <= N - 1 ? run : 0.0);
-    S[i] = s;
-    if (i <= N - 1) usum += s;
-  }
-  double T;
-  const double off2 = block_exclusive_scan(usum, sh, T);
-  const double dx = P.dx, k = dx / EPS0;
-  const double Ehalf = (-P.V / dx - k * T) / (double)N;
-  double* phi = C.phi + (size_t)sn * C.total_nodes + node;
-  double* E64 = C.E64 + (size_t)sn * C.total_nodes + node;
-  R* ER = C.E + (size_t)sn * C.total_nodes + node;
-  double U = off2;
-  for (int i = i0; i < i1; ++i) {
-    double e;
-    if (i == 0) e = Ehalf - rho[0] * dx / (2.0 * EPS0);
-    else if (i == N) e = Ehalf + k * S[N - 1] + rho[N] * dx / (2.0 * EPS0);
-    else e = Ehalf + k * 0.5 * (S[i - 1] + S[i]);
-    phi[i] = (i == N) ? P.V : -dx * ((double)i * Ehalf + k * U);
-    E64[i] = e;
-    ER[i] = (R)e;
-    if (i <= N - 1) U += S[i];
-  }
-  // events of the instance's tiles
-  uint32_t ev[NEV];
-  for (int q = 0; q < NEV; ++q) ev[q] = 0;
-  if (MODE == MODE_STEP) {
-    const uint32_t t0 = C.tile_start[2 * inst], t1 = C.tile_start[2 * inst + 2];
-    for (uint32_t tt = t0 + t; tt < t1; tt += BLOCK)
-      for (int q = 0; q < NEV; ++q) ev[q] += C.tile_ev[(size_t)tt * NEV + q];
-  }
-  __syncthreads();
-  int64_t evsum[NEV];
-  for (int q = 0; q < NEV; ++q) {
-    double tq;
-    block_exclusive_scan((double)ev[q], sh, tq);
-    evsum[q] = (int64_t)tq;
-  }
-  if (t == 0) {
-    int64_t n[2] = {0, 0}, nin = 0;
-    for (int sp = 0; sp < 2; ++sp)
-      for (int p = 0; p < P.parts; ++p) {
+    if (t < NEV * NSLOT) {
+      unsigned long long* e = C.ev + (size_t)inst * NEV * NSLOT + t;
+      const unsigned long long v = *e;
+      *e = 0ull;
+      if (v) atomicAdd(&s_ev[t / NSLOT], v);
+    }
+    if (t < 2 * MAX_PART) {
+      const int sp = t / MAX_PART, p = t % MAX_PART;
+      if (p < P.parts) {
         uint32_t* ci = C.counts + cidx(C.n_inst, g % 3u, inst, sp, p);
         uint32_t* co = C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, sp, p);
         uint32_t* cf = C.counts + cidx(C.n_inst, (g + 2) % 3u, inst, sp, p);
-        nin += *ci;
-        uint32_t c = MODE == MODE_STEP ? *co : *ci;
+        const uint32_t cin = *ci;
+        uint32_t c = MODE == MODE_STEP ? *co : cin;
         if (c > (uint32_t)P.cap_p) {
           atomicOr(C.inst_err + inst, (uint32_t)ERR_CAPACITY);
           c = (uint32_t)P.cap_p;
         }
         *co = c;
         *cf = 0u;
-        n[sp] += c;
+        atomicAdd(&s_cnt[0][sp], cin);
+        atomicAdd(&s_cnt[1][sp], c);
       }
+    }
+  }
+  __syncthreads();
+
+  // S_i = sum_{j=1..i} rho_j for i < N (S_0 = 0), then U_i = sum_{k<i} S_k,
+  // both over contiguous chunks per thread
+  const int chunk = (N + 1 + BLOCK - 1) / BLOCK;
+  const int i0 = t * chunk, i1 = min(i0 + chunk, N + 1);
+  const double rho0 = s_S[0], rhoN = s_S[N];
+  double loc = 0.0;
+  for (int i = i0; i < i1; ++i)
+    if (i >= 1 && i <= N - 1) loc += s_S[i];
+  double v3[3] = {loc, se, si}, ex3[3], tot3[3];
+  block_scan<3>(v3, ex3, tot3, sh);
+  double run = ex3[0], usum = 0.0;
+  for (int i = i0; i < i1; ++i) {
+    if (i >= 1 && i <= N - 1) run += s_S[i];
+    const double sv = (i == 0) ? 0.0 : (i <= N - 1 ? run : 0.0);
+    s_S[i] = sv;
+    if (i <= N - 1) usum += sv;
+  }
+  double v1[1] = {usum}, ex1[1], tot1[1];
+  block_scan<1>(v1, ex1, tot1, sh);  // its barriers also publish s_S
+  const double T = tot1[0];
+  const double dx = P.dx, k = dx / EPS0;
+  const double Ehalf = (-P.V / dx - k * T) / (double)N;
+  double* phi = C.phi + (size_t)sn * C.total_nodes + node;
+  double* E64 = C.E64 + (size_t)sn * C.total_nodes + node;
+  R* ER = C.E + (size_t)sn * C.total_nodes + node;
+  double U = ex1[0];
+  for (int i = i0; i < i1; ++i) {
+    double e;
+    if (i == 0) e = Ehalf - rho0 * dx / (2.0 * EPS0);
+    else if (i == N) e = Ehalf + k * s_S[N - 1] + rhoN * dx / (2.0 * EPS0);
+    else e = Ehalf + k * 0.5 * (s_S[i - 1] + s_S[i]);
+    phi[i] = (i == N) ? P.V : -dx * ((double)i * Ehalf + k * U);
+    E64[i] = e;
+    ER[i] = (R)e;
+    if (i <= N - 1) U += s_S[i];
+  }
+
+  if (t == 0) {
+    const int64_t n[2] = {(int64_t)s_cnt[1][0], (int64_t)s_cnt[1][1]};
+    const int64_t nin = (int64_t)s_cnt[0][0] + s_cnt[0][1];
     const int64_t nout = n[0] + n[1];
     int32_t pm = POP_NONE;
     if (P.n_target > 0) {
@@ -487,15 +542,14 @@ __global__ void __launch_bounds__(BLOCK) k_tail(Ctx<R> C) {
       row.n_e = n[0];
       row.n_i = n[1];
       row.n_in = nin;
-      row.w_e = se_tot * unit * wj;
-      row.w_i = si_tot * unit * wj;
+      row.w_e = tot3[1] * unit * wj;
+      row.w_i = tot3[2] * unit * wj;
       row.w_j = wj;
-      for (int q = 0; q < NEV; ++q) row.ev[q] = evsum[q];
+      for (int q = 0; q < NEV; ++q) row.ev[q] = (int64_t)s_ev[q];
       row.err = C.inst_err[inst];
       C.ring[(size_t)inst * RING + (nx.step - 1) % RING] = row;
     }
-    const uint32_t bs = C.g->bufsel[g % 2u];
-    C.g->bufsel[(g + 1) % 2u] = MODE == MODE_STEP ? 1u - bs : bs;
+    C.g->bufsel[(g + 1) % 2u] = MODE == MODE_STEP ? 1u - s_bs : s_bs;
     C.g->cur_gen = g + 1;
   }
 }
@@ -528,8 +582,15 @@ __device__ __forceinline__ void dep_add(const unsigned long long* acc_base, unsi
 }
 
 template <typename R>
-__device__ void dep_flush(const Ctx<R>& C, unsigned long long (*hist)[HWIN], const DepWin& w) {
+__device__ void dep_flush(const Ctx<R>& C, unsigned long long (*hist)[HWIN], const DepWin& w,
+                          uint32_t* ev) {
   __syncthreads();
+  if (threadIdx.x < NEV) {
+    const uint32_t v = ev[threadIdx.x];
+    if (v) atomicAdd(C.ev + ((size_t)w.inst * NEV + threadIdx.x) * NSLOT + blockIdx.x % NSLOT,
+                     (unsigned long long)v);
+    ev[threadIdx.x] = 0u;
+  }
   const InstParams& P = C.ip[w.inst];
   const int nn = min(HWIN, P.cells + 1 - w.anchor);
   const int slot = blockIdx.x % NSLOT;
@@ -552,6 +613,288 @@ struct LaneOut {
   int ne, ni;   // how many of e[] / i1 are set
 };
 
+constexpr int QCAP = 2 * BLOCK;  // collision-queue slots per workgroup
+
+// What a workgroup is working on: one (instance, species) and the output
+// partition of its current tile.
+struct Work {
+  int inst, sp, part;
+  uint32_t step;
+  int pop;
+  int64_t pbase;
+};
+
+struct Shared {
+  unsigned long long (*hist)[HWIN];
+  uint32_t* ev;
+  uint32_t (*wave)[2];
+  uint32_t* base;
+};
+
+// Population control, charge deposit, event counts and stream compaction of
+// the markers each lane produced.  Called by all threads of the workgroup.
+template <typename R, int MODE>
+__device__ void emit(const Ctx<R>& C, const Work& W, const DepWin& win, const Shared& S,
+                     const LaneOut<R>& o, uint32_t ev, uint32_t err, uint32_t g, uint32_t bsel) {
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
+  const InstParams& P = C.ip[W.inst];
+  const int inst = W.inst, pop = W.pop;
+  const uint32_t step = W.step;
+  const R v0 = (R)P.v0;
+  const int limited = P.limited;
+
+  // population control: each output is kept (roulette) or doubled (split)
+  uint32_t keep_e = 0, keep_i = 0;
+  uint64_t clone_e[2] = {0, 0}, clone_i = 0;
+  int cnt_e = 0, cnt_i = 0;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    if (j >= o.ne) continue;
+    if (pop == POP_ROULETTE) {
+      const U4 r = draw(o.e[j].id, step, CH_ROULETTE, C.seed, inst);
+      if ((r.x >> 9) < (1u << 22)) { keep_e |= 1u << j; ++cnt_e; }
+    } else {
+      keep_e |= 1u << j;
+      ++cnt_e;
+      if (pop == POP_SPLIT) {
+        const U4 r = draw(o.e[j].id, step, CH_CHILD | (1u << 8), C.seed, inst);
+        clone_e[j] = child(r.x, r.y);
+        ++cnt_e;
+      }
+    }
+  }
+  if (o.ni) {
+    if (pop == POP_ROULETTE) {
+      const U4 r = draw(o.i1.id, step, CH_ROULETTE, C.seed, inst);
+      if ((r.x >> 9) < (1u << 22)) { keep_i = 1; ++cnt_i; }
+    } else {
+      keep_i = 1;
+      ++cnt_i;
+      if (pop == POP_SPLIT) {
+        const U4 r = draw(o.i1.id, step, CH_CHILD | (1u << 8), C.seed, inst);
+        clone_i = child(r.x, r.y);
+        ++cnt_i;
+      }
+    }
+  }
+  const int removed = pop == POP_ROULETTE ? (o.ne + o.ni) - (cnt_e + cnt_i) : 0;
+  const int split_added = pop == POP_SPLIT ? (o.ne + o.ni) : 0;
+
+  // deposit (fixed point, units of q w_j): every kept marker adds its two
+  // linear weights to the LDS window (clones count twice)
+  {
+    const int shift = C.dep_shift;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (q >= o.ne || !(keep_e >> q & 1u)) continue;
+      const Mk<R>& e = o.e[q];
+      const R b = beta_of(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
+      const unsigned long long mul = clone_e[q] ? 2ull : 1ull;
+      dep_add(C.acc, C.acc, S.hist, win, 0, P.node, C.total_nodes, e.cell,
+              fixed_pt<R>(b * (R(1) - e.off), shift) * mul, fixed_pt<R>(b * e.off, shift) * mul);
+    }
+    if (o.ni && keep_i) {
+      const Mk<R>& e = o.i1;
+      const R b = beta_of(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
+      const unsigned long long mul = clone_i ? 2ull : 1ull;
+      dep_add(C.acc, C.acc, S.hist, win, 1, P.node, C.total_nodes, e.cell,
+              fixed_pt<R>(b * (R(1) - e.off), shift) * mul, fixed_pt<R>(b * e.off, shift) * mul);
+    }
+  }
+
+  // events
+  {
+    uint32_t add[NEV];
+#pragma unroll
+    for (int q = 0; q < NEV; ++q) add[q] = (uint32_t)__popcll(__ballot((ev >> q) & 1u));
+    int rem = removed, spl = split_added;
+    for (int d = WAVE / 2; d > 0; d >>= 1) {
+      rem += __shfl_xor(rem, d);
+      spl += __shfl_xor(spl, d);
+    }
+    add[EV_ROULETTE] = (uint32_t)rem;
+    add[EV_SPLIT] = (uint32_t)spl;
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < NEV; ++q)
+        if (add[q]) atomicAdd(&S.ev[q], add[q]);
+    }
+    if (err) atomicOr(C.inst_err + inst, err);
+  }
+
+  if (MODE != MODE_STEP) return;
+  // compaction: wave prefix by bit-sliced ballots, one reservation per
+  // workgroup and species on the partition's counter
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const unsigned long long be0 = __ballot(cnt_e & 1), be1 = __ballot(cnt_e & 2),
+                           be2 = __ballot(cnt_e & 4);
+  const unsigned long long bi0 = __ballot(cnt_i & 1), bi1 = __ballot(cnt_i & 2);
+  const uint32_t pre_e = __popcll(be0 & lt) + 2 * __popcll(be1 & lt) + 4 * __popcll(be2 & lt);
+  const uint32_t pre_i = __popcll(bi0 & lt) + 2 * __popcll(bi1 & lt);
+  if (lane == 0) {
+    S.wave[wave][0] = __popcll(be0) + 2 * __popcll(be1) + 4 * __popcll(be2);
+    S.wave[wave][1] = __popcll(bi0) + 2 * __popcll(bi1);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t te = 0, ti = 0;
+    for (int w = 0; w < BLOCK / WAVE; ++w) {
+      const uint32_t a = S.wave[w][0], b = S.wave[w][1];
+      S.wave[w][0] = te;
+      S.wave[w][1] = ti;
+      te += a;
+      ti += b;
+    }
+    S.base[0] = te ? atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 0, W.part), te) : 0u;
+    S.base[1] = ti ? atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 1, W.part), ti) : 0u;
+  }
+  __syncthreads();
+  const Soa<R> oe = C.buf[1 - bsel][0], oi = C.buf[1 - bsel][1];
+  uint32_t pe = S.base[0] + S.wave[wave][0] + pre_e;
+  uint32_t pi = S.base[1] + S.wave[wave][1] + pre_i;
+  __syncthreads();  // S.wave / S.base are reused by the next call
+  uint32_t werr = 0;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    if (j >= o.ne || !(keep_e >> j & 1u)) continue;
+#pragma unroll
+    for (int rep = 0; rep < 2; ++rep) {
+      if (rep == 1 && !clone_e[j]) continue;
+      if (pe < (uint32_t)P.cap_p) {
+        const int64_t s = W.pbase + pe;
+        oe.cell[s] = o.e[j].cell;
+        oe.off[s] = o.e[j].off;
+        oe.vx[s] = o.e[j].vx;
+        oe.vy[s] = o.e[j].vy;
+        oe.vz[s] = o.e[j].vz;
+        oe.id[s] = rep ? clone_e[j] : o.e[j].id;
+      } else {
+        werr |= ERR_CAPACITY;
+      }
+      ++pe;
+    }
+  }
+  if (o.ni && keep_i) {
+#pragma unroll
+    for (int rep = 0; rep < 2; ++rep) {
+      if (rep == 1 && !clone_i) continue;
+      if (pi < (uint32_t)P.cap_p) {
+        const int64_t s = W.pbase + pi;
+        oi.cell[s] = o.i1.cell;
+        oi.off[s] = o.i1.off;
+        oi.vx[s] = o.i1.vx;
+        oi.vy[s] = o.i1.vy;
+        oi.vz[s] = o.i1.vz;
+        oi.id[s] = rep ? clone_i : o.i1.id;
+      } else {
+        werr |= ERR_CAPACITY;
+      }
+      ++pi;
+    }
+  }
+  if (werr) atomicOr(C.inst_err + inst, werr);
+}
+
+// Electron-neutral collision of a candidate (Sec. III, Sec. IV): channel by
+// the SLPIC rate of Eq. (16) or the fixed-event thresholds, then the scatter
+// law of the channel; ionization spawns an electron and an ion.
+template <typename R>
+__device__ void collide_electron(const Ctx<R>& C, const InstParams& P, int inst, uint32_t step,
+                                 Mk<R>& m, LaneOut<R>& o, uint32_t& ev, uint32_t& err) {
+  const U4 r = draw(m.id, step, CH_COLL, C.seed, inst);
+  const R v2 = m.vx * m.vx + m.vy * m.vy + m.vz * m.vz;
+  const R eps = v2 * (R)(0.5 * ME / QE);
+  int ch = -1;
+  if (C.fixed) {
+    const uint32_t u = r.x >> 9;
+    for (int q = 0; q < C.n_chan; ++q)
+      if (ch < 0 && u < P.t_fixed[q]) ch = q;
+  } else {
+    const R sp0 = m_sqrt(v2);
+    const R v0 = (R)P.v0;
+    const R slow = P.limited ? (sp0 < v0 ? sp0 : v0) : sp0;
+    const R numax = (R)P.nu_max_e;
+    R cum;
+    ch = select_channel(C, eps, (R)P.n_g * slow, unif<R>(r.y) * numax, cum);
+    if (cum > numax * R(1.000001)) err |= ERR_NU_BOUND;
+  }
+  if (ch >= 0) {
+    const int kind = C.xs_kind[ch];
+    const R thr = C.xs_thr[ch];
+    R hx, hy, hz, ox, oy, oz;
+    unit3(m.vx, m.vy, m.vz, hx, hy, hz);
+    if (kind == 0) {  // elastic, Vahedi-Surendra angle
+      const R cx = vs_cos(eps, unif<R>(r.z));
+      const R e1 = eps * (R(1) - R(2.0 * ME / MAR) * (R(1) - cx));
+      turn(hx, hy, hz, cx, unif<R>(r.w), ox, oy, oz);
+      const R sp1 = m_sqrt(e1 * (R)(2.0 * QE / ME));
+      m.vx = sp1 * ox; m.vy = sp1 * oy; m.vz = sp1 * oz;
+      ev |= 1u << EV_ELASTIC;
+    } else if (kind == 1) {  // excitation, isotropic
+      R e1 = eps - thr;
+      e1 = e1 > R(0) ? e1 : R(0);
+      turn(hx, hy, hz, R(1) - R(2) * unif<R>(r.z), unif<R>(r.w), ox, oy, oz);
+      const R sp1 = m_sqrt(e1 * (R)(2.0 * QE / ME));
+      m.vx = sp1 * ox; m.vy = sp1 * oy; m.vz = sp1 * oz;
+      ev |= 1u << EV_EXCIT;
+    } else {  // ionization: share eps - I, spawn e- and Ar+
+      const U4 q = draw(m.id, step, CH_IONIZ, C.seed, inst);
+      const U4 b = draw(m.id, step, CH_IONBIRTH, C.seed, inst);
+      const U4 cid = draw(m.id, step, CH_CHILD, C.seed, inst);
+      R eav = eps - thr;
+      eav = eav > R(0) ? eav : R(0);
+      const R B = (R)C.ion_B;
+      R eej = B * m_tan(unif<R>(q.x) * m_atan(eav / (R(2) * B)));
+      R esc = eav - eej;
+      if (C.flags & 1u) { eej = R(0); esc = R(0); }
+      turn(hx, hy, hz, vs_cos(esc, unif<R>(r.z)), unif<R>(r.w), ox, oy, oz);
+      const R sps = m_sqrt(esc * (R)(2.0 * QE / ME));
+      R jx, jy, jz;
+      turn(hx, hy, hz, vs_cos(eej, unif<R>(q.y)), unif<R>(q.z), jx, jy, jz);
+      const R spj = m_sqrt(eej * (R)(2.0 * QE / ME));
+      m.vx = sps * ox; m.vy = sps * oy; m.vz = sps * oz;
+      Mk<R> e2 = m;
+      e2.vx = spj * jx; e2.vy = spj * jy; e2.vz = spj * jz;
+      e2.id = child(cid.x, cid.y);
+      Mk<R> i2 = m;
+      normals3<R>(b, (R)P.vth_i, i2.vx, i2.vy, i2.vz);
+      i2.id = child(cid.z, cid.w);
+      o.e[1] = e2;
+      o.i1 = i2;
+      o.ni = 1;
+      ev |= 1u << EV_IONIZ;
+    }
+  }
+  o.e[0] = m;
+  o.ne = o.ni ? 2 : 1;
+}
+
+// Ar+ charge exchange of a candidate: the ion takes a neutral's thermal
+// velocity.
+template <typename R>
+__device__ void collide_ion(const Ctx<R>& C, const InstParams& P, int inst, uint32_t step,
+                            Mk<R>& m, LaneOut<R>& o, uint32_t& ev, uint32_t& err) {
+  bool hit = true;  // fixed-event candidates always exchange
+  if (!C.fixed) {
+    const U4 r = draw(m.id, step, CH_CX, C.seed, inst);
+    const R v2 = m.vx * m.vx + m.vy * m.vy + m.vz * m.vz;
+    const R sp1 = m_sqrt(v2);
+    const R v0 = (R)P.v0;
+    const R slow = P.limited ? (sp1 < v0 ? sp1 : v0) : sp1;
+    const R nu = (R)P.n_g * (R)P.sigma_cx * slow;
+    const R numax = (R)P.nu_max_cx;
+    if (nu > numax * R(1.000001)) err |= ERR_NU_BOUND;
+    hit = unif<R>(r.y) * numax < nu;
+  }
+  if (hit) {
+    const U4 b = draw(m.id, step, CH_CX | (1u << 8), C.seed, inst);
+    normals3<R>(b, (R)P.vth_i, m.vx, m.vy, m.vz);
+    ev |= 1u << EV_CX;
+  }
+  o.i1 = m;
+  o.ni = 1;
+}
+
 template <typename R, int MODE>
 __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
   __shared__ uint32_t s_prefix[2 * MAX_INST + 1];
@@ -560,17 +903,24 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
   __shared__ uint32_t s_wave[BLOCK / WAVE][2];
   __shared__ uint32_t s_base[2];
   __shared__ uint32_t s_ev[NEV];
-  __shared__ double s_scan[BLOCK];
+  __shared__ double s_scan[4];
+  // collision queue (ring): candidates of the current (instance, species)
+  __shared__ int32_t q_cell[QCAP];
+  __shared__ R q_off[QCAP], q_vx[QCAP], q_vy[QCAP], q_vz[QCAP];
+  __shared__ uint64_t q_id[QCAP];
+  __shared__ uint32_t s_qadd;
 
-  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
+  const int tid = threadIdx.x;
   if (tid == 0) {
     const unsigned long long ticket = atomicAdd(&C.g->wgc, 1ull);
     s_gen = (uint32_t)(ticket / (unsigned long long)C.grid);
+    s_qadd = 0u;
   }
   if (tid < NEV) s_ev[tid] = 0;
   for (int i = tid; i < 2 * HWIN; i += BLOCK) s_hist[i / HWIN][i % HWIN] = 0ull;
   __syncthreads();
   const uint32_t g = s_gen;
+  const Shared S{s_hist, s_ev, s_wave, s_base};
 
   // tile space of this generation: electrons of instance 0, ions of
   // instance 0, electrons of instance 1, ...; an (instance, species) with P
@@ -578,22 +928,29 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
   // partition j mod P
   const int nk = 2 * C.n_inst;
   {
+    // per (instance, species): the largest partition count, read with one
+    // thread per (instance, species, partition) so the loads overlap
+    for (int k = tid; k <= nk; k += BLOCK) s_prefix[k] = 0u;
+    __syncthreads();
+    for (int q = tid; q < nk * MAX_PART; q += BLOCK) {
+      const int k = q / MAX_PART, p = q % MAX_PART;
+      if (p < C.ip[k >> 1].parts) {
+        const uint32_t n = C.counts[cidx(C.n_inst, g % 3u, k >> 1, k & 1, p)];
+        if (n) atomicMax(&s_prefix[k + 1], n);
+      }
+    }
+    __syncthreads();
     const int per = (nk + BLOCK - 1) / BLOCK;
     uint32_t loc = 0;
     for (int k = tid * per; k < min(nk, (tid + 1) * per); ++k) {
-      const int parts = C.ip[k >> 1].parts;
-      uint32_t mx = 0;
-      for (int p = 0; p < parts; ++p) {
-        const uint32_t n = C.counts[cidx(C.n_inst, g % 3u, k >> 1, k & 1, p)];
-        mx = n > mx ? n : mx;
-      }
-      const uint32_t tl = ((mx + BLOCK - 1) / BLOCK) * (uint32_t)parts;
+      const uint32_t mx = s_prefix[k + 1];
+      const uint32_t tl = ((mx + BLOCK - 1) / BLOCK) * (uint32_t)C.ip[k >> 1].parts;
       s_prefix[k + 1] = tl;
       loc += tl;
     }
-    double tot;
-    const double ex = block_exclusive_scan((double)loc, s_scan, tot);
-    uint32_t run = (uint32_t)ex;
+    double v1[1] = {(double)loc}, ex1[1], tot1[1];
+    block_scan<1>(v1, ex1, tot1, s_scan);
+    uint32_t run = (uint32_t)ex1[0];
     if (tid == 0) s_prefix[0] = 0;
     __syncthreads();
     for (int k = tid * per; k < min(nk, (tid + 1) * per); ++k) {
@@ -604,14 +961,39 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
   }
   const uint32_t n_tiles = s_prefix[nk];
   const uint32_t bsel = C.g->bufsel[g % 2u];
-  if (blockIdx.x == 0)
-    for (int k = tid; k <= nk; k += BLOCK) C.tile_start[k] = s_prefix[k];
 
   // each workgroup takes a contiguous run of tiles, so that (for markers in
   // cell order) its deposits stay inside one LDS window
   const uint32_t per = (n_tiles + (uint32_t)C.grid - 1) / (uint32_t)C.grid;
   const uint32_t t_begin = blockIdx.x * per, t_end = min(n_tiles, t_begin + per);
   DepWin win{-1, 0};
+  Work W{-1, -1, 0, 0u, POP_NONE, 0};
+  uint32_t q_head = 0, q_count = 0;  // uniform over the workgroup
+
+  // collide up to BLOCK queued candidates and emit the results
+  auto run_queue = [&](uint32_t n) {
+    LaneOut<R> o;
+    o.ne = o.ni = 0;
+    uint32_t ev = 0, err = 0;
+    if ((uint32_t)tid < n) {
+      const uint32_t s = (q_head + tid) % QCAP;
+      Mk<R> m;
+      m.cell = q_cell[s];
+      m.off = q_off[s];
+      m.vx = q_vx[s];
+      m.vy = q_vy[s];
+      m.vz = q_vz[s];
+      m.id = q_id[s];
+      const InstParams& P = C.ip[W.inst];
+      if (W.sp == 0) collide_electron(C, P, W.inst, W.step, m, o, ev, err);
+      else collide_ion(C, P, W.inst, W.step, m, o, ev, err);
+    }
+    __syncthreads();  // queue slots read before later appends reuse them
+    q_head = (q_head + n) % QCAP;
+    q_count -= n;
+    emit<R, MODE>(C, W, win, S, o, ev, err, g, bsel);
+  };
+
   for (uint32_t t = t_begin; t < t_end; ++t) {
     // (instance, species) of the tile
     int lo = 0, hi = nk;
@@ -628,24 +1010,33 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
     const uint32_t idx = (j / (uint32_t)P.parts) * BLOCK + tid;
     const bool valid = idx < n_in;
     const int64_t pbase = P.seg + (int64_t)part * P.cap_p;
-    if (inst != win.inst) {
-      // new instance for this workgroup: flush the old window, anchor the
-      // new one a quarter window below the tile's first marker
-      if (win.inst >= 0) dep_flush(C, s_hist, win);
-      const uint32_t first = (j / (uint32_t)P.parts) * BLOCK;
-      int c0 = first < n_in ? C.buf[bsel][sp].cell[pbase + first] : 0;
-      int anchor = c0 - HWIN / 4;
-      const int top = P.cells + 1 - HWIN;
-      anchor = anchor > top ? top : anchor;
-      win.anchor = anchor < 0 ? 0 : anchor;
-      win.inst = inst;
+    if (inst != W.inst || sp != W.sp) {
+      // new (instance, species): collide what is queued for the old one
+      while (q_count > 0) run_queue(q_count < (uint32_t)BLOCK ? q_count : (uint32_t)BLOCK);
+      if (inst != win.inst) {
+        // flush the old deposit window, anchor the new one a quarter window
+        // below the tile's first marker
+        if (win.inst >= 0) dep_flush(C, s_hist, win, s_ev);
+        const uint32_t first = (j / (uint32_t)P.parts) * BLOCK;
+        int c0 = first < n_in ? C.buf[bsel][sp].cell[pbase + first] : 0;
+        int anchor = c0 - HWIN / 4;
+        const int top = P.cells + 1 - HWIN;
+        anchor = anchor > top ? top : anchor;
+        win.anchor = anchor < 0 ? 0 : anchor;
+        win.inst = inst;
+      }
+      const InstState S0 = C.st[(g % 2u) * C.n_inst + inst];
+      W.inst = inst;
+      W.sp = sp;
+      W.step = S0.step;
+      W.pop = MODE == MODE_STEP ? S0.popmode : POP_NONE;
     }
-    const InstState S0 = C.st[(g % 2u) * C.n_inst + inst];
-    const uint32_t step = S0.step;
-    const int pop = MODE == MODE_STEP ? S0.popmode : POP_NONE;
+    W.part = part;
+    W.pbase = pbase;
     const Soa<R> in = C.buf[bsel][sp];
     const R v0 = (R)P.v0;
     const int limited = P.limited;
+    const uint32_t step = W.step;
 
     Mk<R> m;
     if (valid) {
@@ -659,9 +1050,8 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
     }
     LaneOut<R> o;
     o.ne = o.ni = 0;
-    uint32_t ev = 0;    // bit per event slot
-    uint32_t err = 0;
-    bool see = false;
+    uint32_t ev = 0, err = 0;
+    bool cand = false;
 
     if (valid && MODE == MODE_REFRESH) {
       if (sp == 0) { o.e[0] = m; o.ne = 1; }
@@ -698,7 +1088,6 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
           // the cathode with probability gamma_se
           const U4 r = draw(m.id, step, CH_SEE, C.seed, inst);
           if ((r.x >> 9) < P.t_see) {
-            see = true;
             ev |= 1u << EV_SEE;
             Mk<R> e;
             e.cell = 0;
@@ -715,274 +1104,42 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
         m.cell = cell;
         m.off = f;
         m.vx = vx1;
-        if (sp == 0) {
-          // ---------------- electron-neutral collision
-          const U4 r = draw(m.id, step, CH_COLL, C.seed, inst);
-          const R v2 = m.vx * m.vx + m.vy * m.vy + m.vz * m.vz;
-          const R eps = v2 * (R)(0.5 * ME / QE);
-          int ch = -1;
-          if (C.fixed) {
-            const uint32_t u = r.x >> 9;
-            for (int q = 0; q < C.n_chan; ++q)
-              if (ch < 0 && u < P.t_fixed[q]) ch = q;
-          } else if ((r.x >> 9) < P.t_null_e) {
-            const R sp0 = m_sqrt(v2);
-            const R slow = limited ? (sp0 < v0 ? sp0 : v0) : sp0;
-            const R numax = (R)P.nu_max_e;
-            R cum;
-            ch = select_channel(C, eps, (R)P.n_g * slow, unif<R>(r.y) * numax, cum);
-            if (cum > numax * R(1.000001)) err |= ERR_NU_BOUND;
-          }
-          if (ch >= 0) {
-            const int kind = C.xs_kind[ch];
-            const R thr = C.xs_thr[ch];
-            R hx, hy, hz, ox, oy, oz;
-            unit3(m.vx, m.vy, m.vz, hx, hy, hz);
-            if (kind == 0) {  // elastic, Vahedi-Surendra angle
-              const R cx = vs_cos(eps, unif<R>(r.z));
-              const R e1 = eps * (R(1) - R(2.0 * ME / MAR) * (R(1) - cx));
-              turn(hx, hy, hz, cx, unif<R>(r.w), ox, oy, oz);
-              const R sp1 = m_sqrt(e1 * (R)(2.0 * QE / ME));
-              m.vx = sp1 * ox; m.vy = sp1 * oy; m.vz = sp1 * oz;
-              ev |= 1u << EV_ELASTIC;
-            } else if (kind == 1) {  // excitation, isotropic
-              R e1 = eps - thr;
-              e1 = e1 > R(0) ? e1 : R(0);
-              turn(hx, hy, hz, R(1) - R(2) * unif<R>(r.z), unif<R>(r.w), ox, oy, oz);
-              const R sp1 = m_sqrt(e1 * (R)(2.0 * QE / ME));
-              m.vx = sp1 * ox; m.vy = sp1 * oy; m.vz = sp1 * oz;
-              ev |= 1u << EV_EXCIT;
-            } else {  // ionization: share eps - I, spawn e- and Ar+
-              const U4 q = draw(m.id, step, CH_IONIZ, C.seed, inst);
-              const U4 b = draw(m.id, step, CH_IONBIRTH, C.seed, inst);
-              const U4 cid = draw(m.id, step, CH_CHILD, C.seed, inst);
-              R eav = eps - thr;
-              eav = eav > R(0) ? eav : R(0);
-              const R B = (R)C.ion_B;
-              R eej = B * m_tan(unif<R>(q.x) * m_atan(eav / (R(2) * B)));
-              R esc = eav - eej;
-              if (C.flags & 1u) { eej = R(0); esc = R(0); }
-              turn(hx, hy, hz, vs_cos(esc, unif<R>(r.z)), unif<R>(r.w), ox, oy, oz);
-              const R sps = m_sqrt(esc * (R)(2.0 * QE / ME));
-              R jx, jy, jz;
-              turn(hx, hy, hz, vs_cos(eej, unif<R>(q.y)), unif<R>(q.z), jx, jy, jz);
-              const R spj = m_sqrt(eej * (R)(2.0 * QE / ME));
-              m.vx = sps * ox; m.vy = sps * oy; m.vz = sps * oz;
-              Mk<R> e2 = m;
-              e2.vx = spj * jx; e2.vy = spj * jy; e2.vz = spj * jz;
-              e2.id = child(cid.x, cid.y);
-              Mk<R> i2 = m;
-              normals3<R>(b, (R)P.vth_i, i2.vx, i2.vy, i2.vz);
-              i2.id = child(cid.z, cid.w);
-              o.e[1] = e2;
-              o.i1 = i2;
-              o.ni = 1;
-              ev |= 1u << EV_IONIZ;
-            }
-          }
-          o.e[0] = m;
-          o.ne = (o.ni == 1) ? 2 : 1;
-        } else {
-          // ---------------- Ar+ charge exchange
-          const U4 r = draw(m.id, step, CH_CX, C.seed, inst);
-          bool hit = false;
-          if (C.fixed) {
-            hit = (r.x >> 9) < P.t_fixed_cx;
-          } else if ((r.x >> 9) < P.t_null_cx) {
-            const R v2 = m.vx * m.vx + m.vy * m.vy + m.vz * m.vz;
-            const R sp1 = m_sqrt(v2);
-            const R slow = limited ? (sp1 < v0 ? sp1 : v0) : sp1;
-            const R nu = (R)P.n_g * (R)P.sigma_cx * slow;
-            const R numax = (R)P.nu_max_cx;
-            if (nu > numax * R(1.000001)) err |= ERR_NU_BOUND;
-            hit = unif<R>(r.y) * numax < nu;
-          }
-          if (hit) {
-            const U4 b = draw(m.id, step, CH_CX | (1u << 8), C.seed, inst);
-            normals3<R>(b, (R)P.vth_i, m.vx, m.vy, m.vz);
-            ev |= 1u << EV_CX;
-          }
-          o.i1 = m;
-          o.ni = 1;
+        // null-collision test: candidates go to the queue
+        const U4 r = draw(m.id, step, sp == 0 ? (uint32_t)CH_COLL : (uint32_t)CH_CX, C.seed, inst);
+        const uint32_t u = r.x >> 9;
+        uint32_t tcand;
+        if (C.fixed) tcand = sp == 0 ? (C.n_chan > 0 ? P.t_fixed[C.n_chan - 1] : 0u) : P.t_fixed_cx;
+        else tcand = sp == 0 ? P.t_null_e : (P.sigma_cx > 0.0 ? P.t_null_cx : 0u);
+        cand = u < tcand;
+        if (!cand) {
+          if (sp == 0) { o.e[0] = m; o.ne = 1; }
+          else { o.i1 = m; o.ni = 1; }
         }
       }
     }
-
-    // ------------- population control on this lane's outputs
-    // electrons: o.e[0..ne), ions: o.i1 if ni; each kept (roulette) or
-    // doubled (split); clones are written right after the original
-    uint32_t keep_e = 0, keep_i = 0;  // bit j: output j survives roulette
-    uint64_t clone_e[2] = {0, 0}, clone_i = 0;
-    int cnt_e = 0, cnt_i = 0;
-    for (int j = 0; j < 2; ++j) {
-      if (j >= o.ne) break;
-      if (pop == POP_ROULETTE) {
-        const U4 r = draw(o.e[j].id, step, CH_ROULETTE, C.seed, inst);
-        if ((r.x >> 9) < (1u << 22)) { keep_e |= 1u << j; ++cnt_e; }
-      } else {
-        keep_e |= 1u << j;
-        ++cnt_e;
-        if (pop == POP_SPLIT) {
-          const U4 r = draw(o.e[j].id, step, CH_CHILD | (1u << 8), C.seed, inst);
-          clone_e[j] = child(r.x, r.y);
-          ++cnt_e;
-        }
-      }
-    }
-    if (o.ni) {
-      if (pop == POP_ROULETTE) {
-        const U4 r = draw(o.i1.id, step, CH_ROULETTE, C.seed, inst);
-        if ((r.x >> 9) < (1u << 22)) { keep_i = 1; ++cnt_i; }
-      } else {
-        keep_i = 1;
-        ++cnt_i;
-        if (pop == POP_SPLIT) {
-          const U4 r = draw(o.i1.id, step, CH_CHILD | (1u << 8), C.seed, inst);
-          clone_i = child(r.x, r.y);
-          ++cnt_i;
-        }
-      }
-    }
-    const int removed = pop == POP_ROULETTE ? (o.ne + o.ni) - (cnt_e + cnt_i) : 0;
-    const int split_added = pop == POP_SPLIT ? (o.ne + o.ni) : 0;
-
-    // ------------- deposit (fixed point, units of q w_j)
-    {
-      unsigned long long own_lo = 0, own_hi = 0;
-      int key = -1;
-      const int shift = C.dep_shift;
-      // markers of the tile's own species go through the wave reduction,
-      // the other species (new ions, secondary electrons) straight to LDS
-      for (int q = 0; q < o.ne; ++q) {
-        if (!(keep_e >> q & 1u)) continue;
-        const Mk<R>& e = o.e[q];
-        const R b = beta_of(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
-        const unsigned long long mul = clone_e[q] ? 2ull : 1ull;
-        const unsigned long long wl = fixed_pt<R>(b * (R(1) - e.off), shift) * mul;
-        const unsigned long long wh = fixed_pt<R>(b * e.off, shift) * mul;
-        if (sp == 0) {
-          key = e.cell;
-          own_lo += wl;
-          own_hi += wh;
-        } else {
-          dep_add(C.acc, C.acc, s_hist, win, 0, P.node, C.total_nodes, e.cell, wl, wh);
-        }
-      }
-      if (o.ni && keep_i) {
-        const Mk<R>& e = o.i1;
-        const R b = beta_of(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
-        const unsigned long long mul = clone_i ? 2ull : 1ull;
-        const unsigned long long wl = fixed_pt<R>(b * (R(1) - e.off), shift) * mul;
-        const unsigned long long wh = fixed_pt<R>(b * e.off, shift) * mul;
-        if (sp == 1) {
-          key = e.cell;
-          own_lo += wl;
-          own_hi += wh;
-        } else {
-          dep_add(C.acc, C.acc, s_hist, win, 1, P.node, C.total_nodes, e.cell, wl, wh);
-        }
-      }
-      const bool last = seg_reduce(key, own_lo, own_hi);
-      if (last && key >= 0)
-        dep_add(C.acc, C.acc, s_hist, win, sp, P.node, C.total_nodes, key, own_lo, own_hi);
-    }
-
-    // ------------- events (per tile, no global atomics)
-    {
-      uint32_t add[NEV];
-#pragma unroll
-      for (int q = 0; q < NEV; ++q) add[q] = (uint32_t)__popcll(__ballot((ev >> q) & 1u));
-      // roulette / split counts are not 0/1 per lane: reduce them in the wave
-      int rem = removed, spl = split_added;
-      for (int d = WAVE / 2; d > 0; d >>= 1) {
-        rem += __shfl_xor(rem, d);
-        spl += __shfl_xor(spl, d);
-      }
-      add[EV_ROULETTE] = (uint32_t)rem;
-      add[EV_SPLIT] = (uint32_t)spl;
-      if (lane == 0) {
-#pragma unroll
-        for (int q = 0; q < NEV; ++q)
-          if (add[q]) atomicAdd(&s_ev[q], add[q]);
-      }
-      if (err) atomicOr(C.inst_err + inst, err);
-    }
-
     if (MODE == MODE_STEP) {
-      // ------------- compaction: wave prefix by bit-sliced ballots
-      const unsigned long long lt = (1ull << lane) - 1ull;
-      const unsigned long long be0 = __ballot(cnt_e & 1), be1 = __ballot(cnt_e & 2),
-                               be2 = __ballot(cnt_e & 4);
-      const unsigned long long bi0 = __ballot(cnt_i & 1), bi1 = __ballot(cnt_i & 2);
-      const uint32_t pre_e = __popcll(be0 & lt) + 2 * __popcll(be1 & lt) + 4 * __popcll(be2 & lt);
-      const uint32_t pre_i = __popcll(bi0 & lt) + 2 * __popcll(bi1 & lt);
-      if (lane == 0) {
-        s_wave[wave][0] = __popcll(be0) + 2 * __popcll(be1) + 4 * __popcll(be2);
-        s_wave[wave][1] = __popcll(bi0) + 2 * __popcll(bi1);
+      if (cand) {
+        const uint32_t s = (q_head + q_count + atomicAdd(&s_qadd, 1u)) % QCAP;
+        q_cell[s] = m.cell;
+        q_off[s] = m.off;
+        q_vx[s] = m.vx;
+        q_vy[s] = m.vy;
+        q_vz[s] = m.vz;
+        q_id[s] = m.id;
       }
-      __syncthreads();
-      if (tid == 0) {
-        uint32_t te = 0, ti = 0;
-        for (int w = 0; w < BLOCK / WAVE; ++w) {
-          const uint32_t a = s_wave[w][0], b = s_wave[w][1];
-          s_wave[w][0] = te;
-          s_wave[w][1] = ti;
-          te += a;
-          ti += b;
-        }
-        s_base[0] = te ? atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 0, part), te) : 0u;
-        s_base[1] = ti ? atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 1, part), ti) : 0u;
-      }
-      __syncthreads();
-      const Soa<R> oe = C.buf[1 - bsel][0], oi = C.buf[1 - bsel][1];
-      uint32_t pe = s_base[0] + s_wave[wave][0] + pre_e;
-      uint32_t pi = s_base[1] + s_wave[wave][1] + pre_i;
-      uint32_t werr = 0;
-      for (int j = 0; j < o.ne; ++j) {
-        if (!(keep_e >> j & 1u)) continue;
-        for (int rep = 0; rep < (clone_e[j] ? 2 : 1); ++rep) {
-          if (pe < (uint32_t)P.cap_p) {
-            const int64_t s = pbase + pe;
-            oe.cell[s] = o.e[j].cell;
-            oe.off[s] = o.e[j].off;
-            oe.vx[s] = o.e[j].vx;
-            oe.vy[s] = o.e[j].vy;
-            oe.vz[s] = o.e[j].vz;
-            oe.id[s] = rep ? clone_e[j] : o.e[j].id;
-          } else {
-            werr |= ERR_CAPACITY;
-          }
-          ++pe;
-        }
-      }
-      if (o.ni && keep_i) {
-        for (int rep = 0; rep < (clone_i ? 2 : 1); ++rep) {
-          if (pi < (uint32_t)P.cap_p) {
-            const int64_t s = pbase + pi;
-            oi.cell[s] = o.i1.cell;
-            oi.off[s] = o.i1.off;
-            oi.vx[s] = o.i1.vx;
-            oi.vy[s] = o.i1.vy;
-            oi.vz[s] = o.i1.vz;
-            oi.id[s] = rep ? clone_i : o.i1.id;
-          } else {
-            werr |= ERR_CAPACITY;
-          }
-          ++pi;
-        }
-      }
-      if (werr) atomicOr(C.inst_err + inst, werr);
-      (void)see;
     }
-
-    // ------------- per-tile event counts for the tail kernel
-    __syncthreads();
-    if (tid == 0 && MODE == MODE_STEP)
-      for (int q = 0; q < NEV; ++q) C.tile_ev[(size_t)t * NEV + q] = s_ev[q];
-    __syncthreads();
-    if (tid < NEV) s_ev[tid] = 0;
+    emit<R, MODE>(C, W, win, S, o, ev, err, g, bsel);  // has barriers: appends are done
+    if (MODE == MODE_STEP) {
+      q_count += s_qadd;
+      __syncthreads();
+      if (tid == 0) s_qadd = 0u;
+      __syncthreads();  // the reset lands before the next tile's appends
+      if (q_count >= (uint32_t)BLOCK) run_queue((uint32_t)BLOCK);
+    }
   }
-  if (win.inst >= 0) dep_flush(C, s_hist, win);
+  while (q_count > 0) run_queue(q_count < (uint32_t)BLOCK ? q_count : (uint32_t)BLOCK);
+  __syncthreads();
+  if (win.inst >= 0) dep_flush(C, s_hist, win, s_ev);
 }
 
 // ---------------------------------------------------------------- seeding
@@ -1029,10 +1186,10 @@ template <typename R>
 hipError_t launch_gen(const Ctx<R>& C, int mode, hipStream_t s) {
   if (mode == MODE_STEP) {
     hipLaunchKernelGGL((k_gen<R, MODE_STEP>), dim3(C.grid), dim3(BLOCK), 0, s, C);
-    hipLaunchKernelGGL((k_tail<R, MODE_STEP>), dim3(C.n_inst), dim3(BLOCK), 0, s, C);
+    hipLaunchKernelGGL((k_tail<R, MODE_STEP>), dim3(C.n_inst), dim3(BLOCK), C.tail_lds, s, C);
   } else {
     hipLaunchKernelGGL((k_gen<R, MODE_REFRESH>), dim3(C.grid), dim3(BLOCK), 0, s, C);
-    hipLaunchKernelGGL((k_tail<R, MODE_REFRESH>), dim3(C.n_inst), dim3(BLOCK), 0, s, C);
+    hipLaunchKernelGGL((k_tail<R, MODE_REFRESH>), dim3(C.n_inst), dim3(BLOCK), C.tail_lds, s, C);
   }
   return hipGetLastError();
 }
