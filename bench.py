@@ -1,0 +1,264 @@
+"""Throughput of the speed-limited PIC/MCC step on one MI355X.
+
+Workload: the batched Paschen sweep -- 64 independent argon gaps (d = 1 cm,
+pd log-spaced from 0.1 to 100 Torr cm, quarter-mean-free-path cells clamped
+to 128..4096, 1e4..2e6 target markers each, about 2.5e7 in all), FP32
+particles with FP64 Poisson solves and population totals, every instance
+advanced by the same launch pair.  A step is one pass of push, null-collision
+MCC (elastic, excitation, ionization with spawn; ion charge exchange),
+ion-induced secondary emission, population control, deposit and the Poisson
+solve over every instance.  Markers start from the seeded state (uniform in
+the first cell, kT_e = 1 eV) and are resident in HBM before timing starts.
+
+Prints one JSON line:
+  value       particle-steps/s = sum over timed steps and instances of the
+              markers entering the step, over the wall time of the steps
+  roofline    particle kernel: 56 algorithmic bytes per marker-step (28-byte
+              record read + 28-byte record written) over its average
+              HIP-event duration, against 8 TB/s
+  plain       the same instances stepped one handle at a time (n_inst = 1)
+  cpu_baseline the FP64 oracle on a bounded sample of the same instances
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-plain]
+       [--no-cpu] [--graph] [--scale S]
+       python bench.py --copy-calibration   (plain device copy of 1 GiB,
+       for scaling HBM counters)
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BYTES_PER_MARKER_STEP = 56.0      # 28-byte FP32 record in + out
+HBM_PEAK_GBS = 8000.0             # MI355X HBM3E
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_gen_c4_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2103_12194_amd", "csrc", f)
+                  for f in ("slpic_kernels.hip", "slpic_internal.hpp")]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per particle-kernel launch and per marker-step from the
+    committed counter summary, or None when the kernel sources changed
+    since the counters were taken."""
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    m = re.search(r"kernel source sha256/16: ([0-9a-f]+)", text)
+    b = re.search(r"HBM bytes per launch: ([0-9.eE+]+)", text)
+    pm = re.search(r"HBM bytes per marker-step: ([0-9.eE+]+)", text)
+    if not (m and b and pm) or m.group(1) != kernel_source_hash():
+        return None
+    return float(b.group(1)), float(pm.group(1))
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--scale", type=float, default=1.0,
+                    help="marker-count scale of the sweep (1 = full size)")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time graph replay of the same steps")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true")
+    return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n,
+                      "launches": 3}), flush=True)
+
+
+def workload(scale):
+    import synth
+    from synth import configs
+    xs = synth.argon_like()
+    w = configs.c4(xs.sigma_total_max(), precision=32)
+    if scale != 1.0:
+        w = configs.scaled(w, scale)
+    return w, xs
+
+
+def history_total(sim, first, n):
+    total = 0
+    for k in range(sim.n_inst):
+        total += int(sim.history(first, n, inst=k)["n_in"].sum())
+    return total
+
+
+def time_steps(sim, steps, profile):
+    import torch
+    if profile:
+        sim.profile(True)
+    s0 = sim.steps_done()
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = sim.kernel_times() if profile else None
+    if profile:
+        sim.profile(False)
+    return s0, t1 - t0, kt
+
+
+def plain_leg(w, xs, steps, warmup):
+    """Each instance in a handle of its own, stepped alone."""
+    import paper_2103_12194_amd as slpic
+    ps, secs = 0, 0.0
+    for inst in w.instances:
+        sim = slpic.Sim([inst], w.run, xs)
+        sim.step(warmup)
+        s0, dt, _ = time_steps(sim, steps, profile=False)
+        ps += history_total(sim, s0, steps)
+        secs += dt
+        sim.close()
+        del sim
+    return ps, secs
+
+
+def cpu_leg(w, xs, budget_s):
+    """The oracle on a sample: every 8th instance of the sweep with markers
+    scaled so one step stays well under a second, stepped from its seeded
+    state until the time budget is spent."""
+    import oracle
+    from synth import configs
+    sample = w.instances[::8]
+    per = budget_s / len(sample)
+    ps, secs, steps = 0, 0.0, 0
+    for k, inst in enumerate(sample):
+        scale = min(1.0, 20000.0 / max(inst.n_seed, 1))
+        small = configs.scaled(configs.Workload("s", w.run, [inst], 1), scale).instances[0]
+        sim = oracle.Sim(small, w.run, xs, instance_index=8 * k)
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < per:
+            sim.step(1)
+            ps += int(sim.stats()["n_in"])
+            n += 1
+        secs += time.perf_counter() - t0
+        steps += n
+    desc = (f"every 8th instance of the sweep ({len(sample)} instances) with "
+            f"at most 2e4 seeded markers each, FP64, stepped from the seeded "
+            f"state for {per:.1f} s each ({steps} steps in all)")
+    return ps / secs, desc
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(instances of a sweep are independent and would be spread "
+              f"over GPUs by a launcher, which this build does not include)",
+              file=sys.stderr)
+        return 2
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        return 1
+    if args.copy_calibration:
+        copy_calibration()
+        return 0
+    import paper_2103_12194_amd as slpic
+    if not os.path.exists(slpic.LIB):
+        slpic.build()
+    w, xs = workload(args.scale)
+    print(f"# {w.name}: {len(w.instances)} instances, "
+          f"{sum(i.n_target for i in w.instances):.3e} target markers", file=sys.stderr, flush=True)
+
+    sim = slpic.Sim(w.instances, w.run, xs)
+    sim.step(args.warmup)
+    sim.sync()
+    print(f"# warmup {args.warmup} steps done", file=sys.stderr, flush=True)
+    s0, secs, (gen_ms, tail_ms, nk) = time_steps(sim, args.steps, profile=True)
+    ps = history_total(sim, s0, args.steps)
+    value = ps / secs
+    print(f"# timed {args.steps} steps: {secs * 1e3 / args.steps:.3f} ms/step, "
+          f"particle kernel {gen_ms / nk:.3f} ms, tail {tail_ms / nk:.3f} ms",
+          file=sys.stderr, flush=True)
+    graph = None
+    if args.graph:
+        sim.use_graph(True)
+        sg, gsecs, _ = time_steps(sim, args.steps, profile=False)
+        graph = {"value": history_total(sim, sg, args.steps) / gsecs,
+                 "ms_per_step": gsecs * 1e3 / args.steps}
+
+    per_launch = BYTES_PER_MARKER_STEP * ps / nk
+    achieved = per_launch / (gen_ms / nk * 1e-3) / 1e9
+    tr = measured_traffic()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if tr is None else tr[0],
+                "kernel": "k_gen (particle kernel)",
+                "bytes_per_launch": per_launch,
+                "kernel_ms": gen_ms / nk, "tail_kernel_ms": tail_ms / nk}
+    n_markers = ps / args.steps
+    sim.close()
+    del sim
+
+    plain = None
+    if not args.no_plain:
+        pps, psecs = plain_leg(w, xs, args.steps, args.warmup)
+        plain = {"value": pps / psecs, "unit": "particle-steps/s",
+                 "ms_per_step_all_instances": psecs * 1e3 / args.steps,
+                 "batched_over_plain": value / (pps / psecs)}
+        print(f"# plain leg: {plain['value']:.3e} particle-steps/s", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu:
+        rate, desc = cpu_leg(w, xs, args.cpu_seconds)
+        cpu = {"value": rate, "unit": "particle-steps/s", "cores": 1,
+               "kind": "oracle", "sample": desc}
+
+    line = {
+        "metric": "particle-steps/s (push+MCC+deposit); batched FP32 vs plain at fixed V_b error",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": secs * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched Paschen sweep: 64 argon gaps, d=1 cm, "
+                               "pd 0.1-100 Torr cm log-spaced, 128-4096 cells, "
+                               "1e4-2e6 target markers each; FP32 particles, "
+                               "FP64 Poisson and totals; one launch pair per step",
+                   "n_inst": len(w.instances), "marker_scale": args.scale,
+                   "markers_per_step": n_markers, "parallelism": "none (1 GPU)"},
+        "roofline": roofline, "plain": plain, "graph": graph,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

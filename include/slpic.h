@@ -155,6 +155,20 @@ int slpic_sync(slpic_t* h);
  * launches (0).  Default 0. */
 int slpic_use_graph(slpic_t* h, int enable);
 
+/* Kernel timing.  enable != 0 starts recording HIP events on the handle's
+ * stream before the particle kernel, between it and the per-instance tail
+ * kernel, and after the tail kernel of every following step (steps are then
+ * launched one by one, never from the graph) and clears the totals;
+ * enable == 0 adds what is pending to the totals and stops.  The handle owns
+ * the events.  Returns SLPIC_HIP_ERROR if events cannot be created. */
+int slpic_profile(slpic_t* h, int enable);
+
+/* Totals since profiling was last enabled: summed particle-kernel and
+ * tail-kernel durations [ms] and the number of steps they cover.  Waits for
+ * the recorded events.  All three outputs are host pointers and must be
+ * non-NULL (else SLPIC_INVALID_ARG). */
+int slpic_kernel_times(slpic_t* h, double* gen_ms, double* tail_ms, int64_t* steps);
+
 /* Replace the markers of one species of one instance with n host-side
  * markers (x = (cell + off) dx, cell in [0, cells), off in [0, 1)), then
  * rebuild that handle's fields.  Synchronizes. */
@@ -164,6 +178,13 @@ int slpic_load_markers(slpic_t* h, int inst, int species, int64_t n,
 
 /* Number of markers of one species of one instance.  Synchronizes. */
 int slpic_count(slpic_t* h, int inst, int species, int64_t* n);
+
+/* Storage diagnostics: markers of one species of one instance are kept in
+ * *parts output partitions of *cap_p slots each (the capacity split for
+ * spreading compaction counters); counts (host, 16 entries) receives each
+ * partition's occupancy, zero past *parts.  Synchronizes. */
+int slpic_partitions(slpic_t* h, int inst, int species, int32_t* parts, int64_t* cap_p,
+                     uint32_t* counts);
 
 /* Copy one species of one instance to host arrays of at least max_n
  * entries (NULL to skip an array); *n receives the count.  Synchronizes. */

@@ -72,7 +72,8 @@ EXPORTS = ["slpic_workspace_bytes", "slpic_create", "slpic_step", "slpic_sync",
            "slpic_use_graph", "slpic_load_markers", "slpic_count",
            "slpic_read_markers", "slpic_read_fields", "slpic_read_stats",
            "slpic_scalars", "slpic_steps_done", "slpic_last_error",
-           "slpic_destroy", "slpic_philox_device"]
+           "slpic_destroy", "slpic_philox_device", "slpic_profile",
+           "slpic_kernel_times", "slpic_partitions"]
 
 
 def lib():
@@ -102,6 +103,9 @@ def lib():
         L.slpic_last_error.restype = C.c_char_p
         L.slpic_last_error.argtypes = [vp]
         L.slpic_destroy.argtypes = [vp]
+        L.slpic_profile.argtypes = [vp, i32]
+        L.slpic_partitions.argtypes = [vp, i32, i32, P(C.c_int32), P(i64), vp]
+        L.slpic_kernel_times.argtypes = [vp, P(C.c_double), P(C.c_double), P(i64)]
         L.slpic_philox_device.argtypes = [vp, C.c_uint32, C.c_uint32, i64, vp, vp]
         _lib = L
     return _lib
@@ -219,6 +223,17 @@ class Sim:
     def use_graph(self, enable=True):
         _check(lib().slpic_use_graph(self.h, 1 if enable else 0), self.h)
 
+    def profile(self, enable=True):
+        """Record per-kernel HIP events around the following steps."""
+        _check(lib().slpic_profile(self.h, 1 if enable else 0), self.h)
+
+    def kernel_times(self):
+        """(particle-kernel ms, tail-kernel ms, steps) since profile(True)."""
+        g, t, n = C.c_double(), C.c_double(), C.c_int64()
+        _check(lib().slpic_kernel_times(self.h, C.byref(g), C.byref(t),
+                                        C.byref(n)), self.h)
+        return g.value, t.value, int(n.value)
+
     def steps_done(self):
         return int(lib().slpic_steps_done(self.h))
 
@@ -236,6 +251,14 @@ class Sim:
         n = C.c_int64()
         _check(lib().slpic_count(self.h, inst, species, C.byref(n)), self.h)
         return int(n.value)
+
+    def partitions(self, species, inst=0):
+        """(occupancy of each output partition, slots per partition)."""
+        parts, cap = C.c_int32(), C.c_int64()
+        out = np.zeros(16, np.uint32)
+        _check(lib().slpic_partitions(self.h, inst, species, C.byref(parts),
+                                      C.byref(cap), _p(out)), self.h)
+        return out[:parts.value].copy(), int(cap.value)
 
     def read(self, species, inst=0):
         n = self.count(species, inst)

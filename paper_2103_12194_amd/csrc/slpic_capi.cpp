@@ -14,7 +14,8 @@
 #include "slpic_internal.hpp"
 
 namespace slpic {
-template <typename R> hipError_t launch_gen(const Ctx<R>&, int, hipStream_t);
+template <typename R> hipError_t launch_particles(const Ctx<R>&, int, hipStream_t);
+template <typename R> hipError_t launch_tail(const Ctx<R>&, int, hipStream_t);
 template <typename R>
 hipError_t launch_seed(const Ctx<R>&, int, int, int64_t, double, uint32_t, hipStream_t);
 template <typename R> hipError_t occupancy_gen(int*);
@@ -58,13 +59,15 @@ struct Layout {
   std::vector<int64_t> seg, cap_p;
 };
 
-// Output partitions of an instance: enough that the per-tile compaction
-// counters are spread over several addresses for large instances, one for
-// small ones.  Each partition gets an equal share of the capacity plus one
-// tile of slack for uneven growth.
+// Output partitions of an instance (a power of two): enough that the
+// per-emit compaction counters are spread over several addresses for large
+// instances, while every partition keeps room for at least 32 tiles, so that
+// the random spread of emits over partitions stays small against a
+// partition's capacity.  Each partition gets an equal share of the capacity
+// plus one tile of slack.
 int partitions_for(int64_t cap) {
   int p = 1;
-  while (p < MAX_PART && (int64_t)p * 2 * 4 * BLOCK <= cap) p *= 2;
+  while (p < MAX_PART && (int64_t)p * 2 * 32 * BLOCK <= cap) p *= 2;
   return p;
 }
 
@@ -260,6 +263,14 @@ struct slpic_handle {
   bool use_graph = false;
   int graph_period = 16;
   hipGraphExec_t graph = nullptr;
+  // kernel timing: events before the particle kernel, between the two
+  // kernels and after the tail kernel of each profiled step, in two pools
+  // so that one can be read back while the other fills
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool[2];
+  int ev_cur = 0, ev_used[2] = {0, 0};
+  double t_gen_ms = 0, t_tail_ms = 0;
+  int64_t t_steps = 0;
   std::string err;
 };
 
@@ -359,12 +370,76 @@ int upload_tables(slpic_t* h, Ctx<R>& C, const slpic_xs* xs) {
   return SLPIC_OK;
 }
 
+template <typename R>
+hipError_t launch_pair(const Ctx<R>& C, int mode, hipStream_t s) {
+  hipError_t e = launch_particles<R>(C, mode, s);
+  return e != hipSuccess ? e : launch_tail<R>(C, mode, s);
+}
+
+hipError_t launch_pair_any(slpic_t* h, int mode) {
+  return h->cfg.precision == 64 ? launch_pair<double>(h->c64, mode, h->stream)
+                                : launch_pair<float>(h->c32, mode, h->stream);
+}
+
+constexpr int kEvPool = 3 * 512;   // events per timing pool (512 steps)
+
+// Adds the durations of the steps recorded in pool b to the totals.
+int drain_pool(slpic_t* h, int b) {
+  std::vector<hipEvent_t>& P = h->ev_pool[b];
+  if (h->ev_used[b] == 0) return SLPIC_OK;
+  HIPCHK(h, hipEventSynchronize(P[h->ev_used[b] - 1]));
+  for (int k = 0; k < h->ev_used[b]; k += 3) {
+    float a = 0, c = 0;
+    HIPCHK(h, hipEventElapsedTime(&a, P[k], P[k + 1]));
+    HIPCHK(h, hipEventElapsedTime(&c, P[k + 1], P[k + 2]));
+    h->t_gen_ms += a;
+    h->t_tail_ms += c;
+    h->t_steps += 1;
+  }
+  h->ev_used[b] = 0;
+  return SLPIC_OK;
+}
+
+int launch_timed(slpic_t* h, int mode) {
+  int b = h->ev_cur;
+  if (h->ev_used[b] + 3 > kEvPool) {
+    b ^= 1;
+    int rc = drain_pool(h, b);
+    if (rc) return rc;
+    h->ev_cur = b;
+  }
+  hipEvent_t* e = h->ev_pool[b].data() + h->ev_used[b];
+  HIPCHK(h, hipEventRecord(e[0], h->stream));
+  hipError_t r = h->cfg.precision == 64 ? launch_particles<double>(h->c64, mode, h->stream)
+                                        : launch_particles<float>(h->c32, mode, h->stream);
+  if (r != hipSuccess) return hip_fail(h, r, "particle kernel launch");
+  HIPCHK(h, hipEventRecord(e[1], h->stream));
+  r = h->cfg.precision == 64 ? launch_tail<double>(h->c64, mode, h->stream)
+                             : launch_tail<float>(h->c32, mode, h->stream);
+  if (r != hipSuccess) return hip_fail(h, r, "tail kernel launch");
+  HIPCHK(h, hipEventRecord(e[2], h->stream));
+  h->ev_used[b] += 3;
+  return SLPIC_OK;
+}
+
 int launch_gen_any(slpic_t* h, int mode) {
-  hipError_t e = h->cfg.precision == 64 ? launch_gen<double>(h->c64, mode, h->stream)
-                                        : launch_gen<float>(h->c32, mode, h->stream);
-  if (e != hipSuccess) return hip_fail(h, e, "generation kernel launch");
+  if (h->profiling && mode == MODE_STEP) {
+    int rc = launch_timed(h, mode);
+    if (rc) return rc;
+  } else {
+    hipError_t e = launch_pair_any(h, mode);
+    if (e != hipSuccess) return hip_fail(h, e, "generation kernel launch");
+  }
   h->gen += 1;
   return SLPIC_OK;
+}
+
+void release_events(slpic_t* h) {
+  for (auto& P : h->ev_pool) {
+    for (hipEvent_t e : P) (void)hipEventDestroy(e);
+    P.clear();
+  }
+  h->ev_used[0] = h->ev_used[1] = 0;
 }
 
 Global read_global(slpic_t* h, hipError_t* e) {
@@ -624,13 +699,12 @@ int slpic_use_graph(slpic_t* h, int enable) {
 int slpic_step(slpic_t* h, int n_steps) {
   if (!h || n_steps < 0) return fail(h, SLPIC_INVALID_ARG, "bad step arguments");
   int done = 0;
-  if (h->use_graph && n_steps >= h->graph_period) {
+  if (h->use_graph && !h->profiling && n_steps >= h->graph_period) {
     if (!h->graph) {
       hipGraph_t gr;
       HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
       for (int k = 0; k < h->graph_period; ++k) {
-        hipError_t e = h->cfg.precision == 64 ? launch_gen<double>(h->c64, MODE_STEP, h->stream)
-                                              : launch_gen<float>(h->c32, MODE_STEP, h->stream);
+        hipError_t e = launch_pair_any(h, MODE_STEP);
         if (e != hipSuccess) {
           (void)hipStreamEndCapture(h->stream, &gr);
           return hip_fail(h, e, "graph capture");
@@ -652,6 +726,41 @@ int slpic_step(slpic_t* h, int n_steps) {
     if (rc) return rc;
     h->steps += 1;
   }
+  return SLPIC_OK;
+}
+
+int slpic_profile(slpic_t* h, int enable) {
+  if (!h) return SLPIC_INVALID_ARG;
+  if (enable && !h->profiling) {
+    for (auto& P : h->ev_pool) {
+      P.resize(kEvPool);
+      for (hipEvent_t& e : P) HIPCHK(h, hipEventCreate(&e));
+    }
+    h->ev_cur = 0;
+    h->ev_used[0] = h->ev_used[1] = 0;
+    h->t_gen_ms = h->t_tail_ms = 0;
+    h->t_steps = 0;
+    h->profiling = true;
+  } else if (!enable && h->profiling) {
+    int rc = drain_pool(h, h->ev_cur ^ 1);
+    if (!rc) rc = drain_pool(h, h->ev_cur);
+    release_events(h);
+    h->profiling = false;
+    if (rc) return rc;
+  }
+  return SLPIC_OK;
+}
+
+int slpic_kernel_times(slpic_t* h, double* gen_ms, double* tail_ms, int64_t* steps) {
+  if (!h || !gen_ms || !tail_ms || !steps) return fail(h, SLPIC_INVALID_ARG, "null timing output");
+  if (h->profiling) {
+    int rc = drain_pool(h, h->ev_cur ^ 1);
+    if (!rc) rc = drain_pool(h, h->ev_cur);
+    if (rc) return rc;
+  }
+  *gen_ms = h->t_gen_ms;
+  *tail_ms = h->t_tail_ms;
+  *steps = h->t_steps;
   return SLPIC_OK;
 }
 
@@ -695,6 +804,24 @@ int slpic_count(slpic_t* h, int inst, int species, int64_t* n) {
   int64_t t = 0;
   for (uint32_t v : c) t += v;
   *n = t;
+  return SLPIC_OK;
+}
+
+int slpic_partitions(slpic_t* h, int inst, int species, int32_t* parts, int64_t* cap_p,
+                     uint32_t* counts) {
+  if (!h || !parts || !cap_p || !counts || inst < 0 || inst >= h->n_inst ||
+      (species != 0 && species != 1))
+    return fail(h, SLPIC_INVALID_ARG, "bad partition arguments");
+  Global G;
+  uint32_t slot3, bsel;
+  int rc = current(h, G, slot3, bsel);
+  if (rc) return rc;
+  std::vector<uint32_t> c;
+  rc = part_counts(h, slot3, inst, species, c);
+  if (rc) return rc;
+  *parts = h->ip[inst].parts;
+  *cap_p = h->ip[inst].cap_p;
+  for (int p = 0; p < MAX_PART; ++p) counts[p] = p < (int)c.size() ? c[p] : 0u;
   return SLPIC_OK;
 }
 
@@ -768,6 +895,7 @@ void slpic_destroy(slpic_t* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  release_events(h);
   delete h;
 }
 

@@ -53,7 +53,7 @@ struct InstParams {
   int64_t n_target;
   int32_t cells, node;      // node: first node of the instance in node arrays
   int32_t limited;          // 0: plain PIC (beta == 1)
-  int32_t parts;            // output partitions P (tile j serves j mod P)
+  int32_t parts;            // partitions P, a power of two (tile j reads j mod P)
   uint32_t t_null_e, t_null_cx, t_see;
   uint32_t t_fixed[MAX_CHAN];
   uint32_t t_fixed_cx;

@@ -615,14 +615,32 @@ struct LaneOut {
 
 constexpr int QCAP = 2 * BLOCK;  // collision-queue slots per workgroup
 
-// What a workgroup is working on: one (instance, species) and the output
-// partition of its current tile.
+// What a workgroup is working on: one (instance, species), and the output
+// partition of its next emit.
 struct Work {
   int inst, sp, part;
   uint32_t step;
   int pop;
   int64_t pbase;
+  uint32_t emits;
 };
+
+// Output partition of a workgroup's next emit: an integer hash of
+// (workgroup, emit number, step), so that each partition receives an equal
+// share of a step's output in expectation whatever partition the markers
+// came from, and no fixed stride between tiles can map one input partition
+// to one output partition step after step.
+__device__ __forceinline__ void next_output(Work& W, const InstParams& P) {
+  uint32_t h = blockIdx.x * 0x9E3779B1u ^ (W.emits * 0x85EBCA77u + W.step * 0xC2B2AE3Du);
+  h ^= h >> 16;
+  h *= 0x7FEB352Du;
+  h ^= h >> 15;
+  h *= 0x846CA68Bu;
+  h ^= h >> 16;
+  W.part = (int)(h & (uint32_t)(P.parts - 1));  // parts is a power of two
+  W.pbase = P.seg + (int64_t)W.part * P.cap_p;
+  ++W.emits;
+}
 
 struct Shared {
   unsigned long long (*hist)[HWIN];
@@ -967,7 +985,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
   const uint32_t per = (n_tiles + (uint32_t)C.grid - 1) / (uint32_t)C.grid;
   const uint32_t t_begin = blockIdx.x * per, t_end = min(n_tiles, t_begin + per);
   DepWin win{-1, 0};
-  Work W{-1, -1, 0, 0u, POP_NONE, 0};
+  Work W{-1, -1, 0, 0u, POP_NONE, 0, 0u};
   uint32_t q_head = 0, q_count = 0;  // uniform over the workgroup
 
   // collide up to BLOCK queued candidates and emit the results
@@ -991,6 +1009,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
     __syncthreads();  // queue slots read before later appends reuse them
     q_head = (q_head + n) % QCAP;
     q_count -= n;
+    next_output(W, C.ip[W.inst]);
     emit<R, MODE>(C, W, win, S, o, ev, err, g, bsel);
   };
 
@@ -1031,8 +1050,6 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
       W.step = S0.step;
       W.pop = MODE == MODE_STEP ? S0.popmode : POP_NONE;
     }
-    W.part = part;
-    W.pbase = pbase;
     const Soa<R> in = C.buf[bsel][sp];
     const R v0 = (R)P.v0;
     const int limited = P.limited;
@@ -1128,6 +1145,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
         q_id[s] = m.id;
       }
     }
+    next_output(W, P);
     emit<R, MODE>(C, W, win, S, o, ev, err, g, bsel);  // has barriers: appends are done
     if (MODE == MODE_STEP) {
       q_count += s_qadd;
@@ -1183,14 +1201,20 @@ __global__ void k_philox_test(const uint32_t* ctr, uint32_t k0, uint32_t k1, int
 
 // ---------------------------------------------------------------- launchers
 template <typename R>
-hipError_t launch_gen(const Ctx<R>& C, int mode, hipStream_t s) {
-  if (mode == MODE_STEP) {
+hipError_t launch_particles(const Ctx<R>& C, int mode, hipStream_t s) {
+  if (mode == MODE_STEP)
     hipLaunchKernelGGL((k_gen<R, MODE_STEP>), dim3(C.grid), dim3(BLOCK), 0, s, C);
-    hipLaunchKernelGGL((k_tail<R, MODE_STEP>), dim3(C.n_inst), dim3(BLOCK), C.tail_lds, s, C);
-  } else {
+  else
     hipLaunchKernelGGL((k_gen<R, MODE_REFRESH>), dim3(C.grid), dim3(BLOCK), 0, s, C);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_tail(const Ctx<R>& C, int mode, hipStream_t s) {
+  if (mode == MODE_STEP)
+    hipLaunchKernelGGL((k_tail<R, MODE_STEP>), dim3(C.n_inst), dim3(BLOCK), C.tail_lds, s, C);
+  else
     hipLaunchKernelGGL((k_tail<R, MODE_REFRESH>), dim3(C.n_inst), dim3(BLOCK), C.tail_lds, s, C);
-  }
   return hipGetLastError();
 }
 
@@ -1210,8 +1234,10 @@ hipError_t occupancy_gen(int* blocks_per_cu) {
                                                       0);
 }
 
-template hipError_t launch_gen<float>(const Ctx<float>&, int, hipStream_t);
-template hipError_t launch_gen<double>(const Ctx<double>&, int, hipStream_t);
+template hipError_t launch_particles<float>(const Ctx<float>&, int, hipStream_t);
+template hipError_t launch_particles<double>(const Ctx<double>&, int, hipStream_t);
+template hipError_t launch_tail<float>(const Ctx<float>&, int, hipStream_t);
+template hipError_t launch_tail<double>(const Ctx<double>&, int, hipStream_t);
 template hipError_t launch_seed<float>(const Ctx<float>&, int, int, int64_t, double, uint32_t,
                                        hipStream_t);
 template hipError_t launch_seed<double>(const Ctx<double>&, int, int, int64_t, double, uint32_t,

@@ -163,3 +163,26 @@ def test_invalid_load_is_rejected(xs_argon):
     with pytest.raises(slpic.SlpicError):
         gpu.load(0, bad)
     assert gpu.count(0) == 10
+
+
+def test_long_batched_run_stays_within_capacity():
+    """A 64-instance sweep at 2% of full marker counts for 600 steps: more
+    tiles than workgroups, so each workgroup emits many times per step into
+    up to 16 output partitions per (instance, species).  The partition sizes
+    must stay balanced: the per-species capacity of 3-4 N_t is never hit
+    while population control holds each instance below about 2.4 N_t."""
+    xs = synth.argon_like()
+    w = configs.scaled(configs.c4(xs.sigma_total_max(), precision=32), 0.02)
+    gpu = slpic.Sim(w.instances, w.run, xs)
+    for _ in range(6):
+        gpu.step(100)
+        assert gpu.sync() == 0
+        for k, inst in enumerate(w.instances):
+            for sp in (0, 1):
+                c, cap_p = gpu.partitions(sp, k)
+                assert c.max() <= 0.75 * cap_p, (k, sp, c.tolist(), cap_p)
+    for k, inst in enumerate(w.instances):
+        n = gpu.count(0, k) + gpu.count(1, k)
+        assert n <= 2.5 * inst.n_target + 64, (k, n, inst.n_target)
+        h = gpu.history(gpu.steps_done() - 100, 100, inst=k)
+        assert np.all(h["n_e"] + h["n_i"] <= 2.5 * inst.n_target + 64), k
