@@ -18,7 +18,10 @@ template <typename R> hipError_t launch_particles(const Ctx<R>&, int, hipStream_
 template <typename R> hipError_t launch_tail(const Ctx<R>&, int, hipStream_t);
 template <typename R>
 hipError_t launch_seed(const Ctx<R>&, int, int, int64_t, double, uint32_t, hipStream_t);
-template <typename R> hipError_t occupancy_gen(int*);
+template <typename R> hipError_t occupancy_gen(int*, size_t);
+// dynamic LDS of the particle kernel: tile offsets of the (instance,
+// species) pairs
+inline size_t gen_lds_bytes(int n_inst) { return ((size_t)(2 * n_inst + 1) * 4 + 15) & ~size_t(15); }
 hipError_t launch_philox_test(const uint32_t*, uint32_t, uint32_t, int64_t, uint32_t*,
                               hipStream_t);
 }  // namespace slpic
@@ -340,6 +343,7 @@ void fill_ctx(slpic_t* h, Ctx<R>& C) {
   int maxc = 0;
   for (auto& I : h->inst) maxc = std::max(maxc, I.cells);
   C.tail_lds = (maxc + 1) * (int)sizeof(double);
+  C.gen_lds = (int)gen_lds_bytes(h->n_inst);
 }
 
 template <typename R>
@@ -615,7 +619,8 @@ int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess)
-    e = cfg->precision == 64 ? occupancy_gen<double>(&per_cu) : occupancy_gen<float>(&per_cu);
+    e = cfg->precision == 64 ? occupancy_gen<double>(&per_cu, gen_lds_bytes(n_inst))
+                             : occupancy_gen<float>(&per_cu, gen_lds_bytes(n_inst));
   if (e != hipSuccess) {
     int rc = hip_fail(nullptr, e, "device query");
     delete h;

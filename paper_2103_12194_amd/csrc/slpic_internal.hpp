@@ -14,7 +14,7 @@ constexpr int MAX_CHAN = 8;
 constexpr int NEV = 11;           // event counters per tile
 constexpr int RING = 4096;        // statistics rows kept per instance
 constexpr int MAX_PART = 16;      // output partitions per (instance, species)
-constexpr int NSLOT = 16;         // copies of each global deposit node
+constexpr int NSLOT = 4;          // copies of each global deposit node
 constexpr int HWIN = 1024;        // nodes in a workgroup's LDS deposit window
 
 // event counter slots (order of the public slpic_stats fields)
@@ -102,7 +102,7 @@ struct Ctx {
   InstState* st;             // [2][n_inst]
   uint32_t* counts;          // [3][n_inst][2][MAX_PART]
   unsigned long long* ev;    // [n_inst][NEV][NSLOT] event counters of a step
-  unsigned long long* acc;   // [2 species][total_nodes][NSLOT] fixed-point deposit
+  unsigned long long* acc;   // [2 species][NSLOT][total_nodes] fixed-point deposit
   R* E;                      // [2][total_nodes] field in kernel precision
   double* E64;               // [2][total_nodes]
   double* phi;               // [2][total_nodes]
@@ -123,6 +123,7 @@ struct Ctx {
   uint32_t flags, seed;
   int dep_shift;             // fraction bits of the fixed-point deposit
   int tail_lds;              // dynamic LDS bytes of the tail kernel
+  int gen_lds;               // dynamic LDS bytes of the particle kernel
 };
 
 }  // namespace slpic

@@ -255,6 +255,14 @@ __device__ __forceinline__ R beta_of(R v2, R v0, int limited) {
   return v > v0 ? v0 / v : R(1);
 }
 
+// the same with the fast square root and reciprocal in FP32 (deposit weights)
+template <typename R>
+__device__ __forceinline__ R beta_fast(R v2, R v0, int limited) {
+  if (!limited) return R(1);
+  const R v = Fm<R>::sqrt(v2);
+  return v > v0 ? Fm<R>::div(v0, v) : R(1);
+}
+
 // ---------------------------------------------------------------- collisions
 template <typename R>
 __device__ __forceinline__ R vs_cos(R eps, R u) {
@@ -432,24 +440,26 @@ __global__ void __launch_bounds__(BLOCK) k_tail(Ctx<R> C) {
   const double unit = 1.0 / (double)(1ull << C.dep_shift);
   const double qvol = QE * wj * unit / (P.area * P.dx);
 
-  // charge density at the nodes (strided: coalesced reads of the NSLOT
-  // copies), species totals; events and marker counts alongside
+  // charge density at the nodes (each of the NSLOT copies read with
+  // consecutive threads on consecutive nodes), species totals; events and
+  // marker counts alongside
   double se = 0.0, si = 0.0;
   {
-    unsigned long long* acc_e = C.acc + (size_t)node * NSLOT;
-    unsigned long long* acc_i = C.acc + ((size_t)C.total_nodes + node) * NSLOT;
+    const size_t tn = (size_t)C.total_nodes;
+    unsigned long long* acc_e = C.acc + node;
+    unsigned long long* acc_i = C.acc + (size_t)NSLOT * tn + node;
     double* rho = C.rho + (size_t)sn * C.total_nodes + node;
     for (int i = t; i <= N; i += BLOCK) {
       unsigned long long ae = 0ull, ai = 0ull;
 #pragma unroll
       for (int q = 0; q < NSLOT; ++q) {
-        ae += acc_e[(size_t)i * NSLOT + q];
-        ai += acc_i[(size_t)i * NSLOT + q];
+        ae += acc_e[q * tn + i];
+        ai += acc_i[q * tn + i];
       }
 #pragma unroll
       for (int q = 0; q < NSLOT; ++q) {
-        acc_e[(size_t)i * NSLOT + q] = 0ull;
-        acc_i[(size_t)i * NSLOT + q] = 0ull;
+        acc_e[q * tn + i] = 0ull;
+        acc_i[q * tn + i] = 0ull;
       }
       se += (double)ae;
       si += (double)ai;
@@ -575,33 +585,44 @@ __device__ __forceinline__ void dep_add(const unsigned long long* acc_base, unsi
     if (hi) atomicAdd(&hist[sp][r + 1], hi);
   } else {
     const int slot = blockIdx.x % NSLOT;
-    unsigned long long* a = acc + ((size_t)sp * total_nodes + node0 + cell) * NSLOT + slot;
+    unsigned long long* a = acc + ((size_t)sp * NSLOT + slot) * total_nodes + node0 + cell;
     if (lo) atomicAdd(a, lo);
-    if (hi) atomicAdd(a + NSLOT, hi);
+    if (hi) atomicAdd(a + 1, hi);
   }
 }
 
+// Adds the window and the event counts gathered since the last flush (per
+// wave, in registers) to global memory.  Called by all threads.
 template <typename R>
-__device__ void dep_flush(const Ctx<R>& C, unsigned long long (*hist)[HWIN], const DepWin& w,
-                          uint32_t* ev) {
+__device__ __forceinline__ void dep_flush(const Ctx<R>& C, unsigned long long (*hist)[HWIN], const DepWin& w,
+                          uint32_t* ev, uint32_t (&evacc)[NEV]) {
+  if ((threadIdx.x & (WAVE - 1)) == 0) {
+#pragma unroll
+    for (int q = 0; q < NEV; ++q)
+      if (evacc[q]) atomicAdd(&ev[q], evacc[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < NEV; ++q) evacc[q] = 0u;
   __syncthreads();
+  const int slot = blockIdx.x % NSLOT;
   if (threadIdx.x < NEV) {
     const uint32_t v = ev[threadIdx.x];
-    if (v) atomicAdd(C.ev + ((size_t)w.inst * NEV + threadIdx.x) * NSLOT + blockIdx.x % NSLOT,
+    if (v) atomicAdd(C.ev + ((size_t)w.inst * NEV + threadIdx.x) * NSLOT + slot,
                      (unsigned long long)v);
     ev[threadIdx.x] = 0u;
   }
   const InstParams& P = C.ip[w.inst];
   const int nn = min(HWIN, P.cells + 1 - w.anchor);
-  const int slot = blockIdx.x % NSLOT;
-  for (int sp = 0; sp < 2; ++sp)
+  for (int sp = 0; sp < 2; ++sp) {
+    unsigned long long* dst = C.acc + ((size_t)sp * NSLOT + slot) * C.total_nodes + P.node + w.anchor;
     for (int i = threadIdx.x; i < nn; i += BLOCK) {
       const unsigned long long v = hist[sp][i];
       if (v) {
-        atomicAdd(C.acc + ((size_t)sp * C.total_nodes + P.node + w.anchor + i) * NSLOT + slot, v);
+        atomicAdd(dst + i, v);
         hist[sp][i] = 0ull;
       }
     }
+  }
   __syncthreads();
 }
 
@@ -651,9 +672,13 @@ struct Shared {
 
 // Population control, charge deposit, event counts and stream compaction of
 // the markers each lane produced.  Called by all threads of the workgroup.
-template <typename R, int MODE>
-__device__ void emit(const Ctx<R>& C, const Work& W, const DepWin& win, const Shared& S,
-                     const LaneOut<R>& o, uint32_t ev, uint32_t err, uint32_t g, uint32_t bsel) {
+// QUEUE: outputs of collided candidates (collision events) rather than of a
+// tile (wall and emission events).  Event counts go to the wave's
+// accumulators evacc (equal in all lanes of a wave).
+template <typename R, int MODE, bool QUEUE>
+__device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWin& win, const Shared& S,
+                     const LaneOut<R>& o, uint32_t ev, uint32_t err, uint32_t g, uint32_t bsel,
+                     uint32_t (&evacc)[NEV]) {
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
   const InstParams& P = C.ip[W.inst];
   const int inst = W.inst, pop = W.pop;
@@ -706,39 +731,34 @@ __device__ void emit(const Ctx<R>& C, const Work& W, const DepWin& win, const Sh
     for (int q = 0; q < 2; ++q) {
       if (q >= o.ne || !(keep_e >> q & 1u)) continue;
       const Mk<R>& e = o.e[q];
-      const R b = beta_of(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
+      const R b = beta_fast(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
       const unsigned long long mul = clone_e[q] ? 2ull : 1ull;
       dep_add(C.acc, C.acc, S.hist, win, 0, P.node, C.total_nodes, e.cell,
               fixed_pt<R>(b * (R(1) - e.off), shift) * mul, fixed_pt<R>(b * e.off, shift) * mul);
     }
     if (o.ni && keep_i) {
       const Mk<R>& e = o.i1;
-      const R b = beta_of(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
+      const R b = beta_fast(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
       const unsigned long long mul = clone_i ? 2ull : 1ull;
       dep_add(C.acc, C.acc, S.hist, win, 1, P.node, C.total_nodes, e.cell,
               fixed_pt<R>(b * (R(1) - e.off), shift) * mul, fixed_pt<R>(b * e.off, shift) * mul);
     }
   }
 
-  // events
-  {
-    uint32_t add[NEV];
+  // events: wave totals by ballot; removed and split_added are in 0..3
+  if (__ballot(ev != 0u)) {
+    constexpr int q0 = QUEUE ? EV_ELASTIC : EV_ABS_E_CATH;
+    constexpr int q1 = QUEUE ? EV_ABS_E_CATH : EV_ROULETTE;
 #pragma unroll
-    for (int q = 0; q < NEV; ++q) add[q] = (uint32_t)__popcll(__ballot((ev >> q) & 1u));
-    int rem = removed, spl = split_added;
-    for (int d = WAVE / 2; d > 0; d >>= 1) {
-      rem += __shfl_xor(rem, d);
-      spl += __shfl_xor(spl, d);
-    }
-    add[EV_ROULETTE] = (uint32_t)rem;
-    add[EV_SPLIT] = (uint32_t)spl;
-    if (lane == 0) {
-#pragma unroll
-      for (int q = 0; q < NEV; ++q)
-        if (add[q]) atomicAdd(&S.ev[q], add[q]);
-    }
-    if (err) atomicOr(C.inst_err + inst, err);
+    for (int q = q0; q < q1; ++q) evacc[q] += (uint32_t)__popcll(__ballot((ev >> q) & 1u));
   }
+  if (pop != POP_NONE) {
+    const int x = pop == POP_ROULETTE ? removed : split_added;
+    const uint32_t n = (uint32_t)(__popcll(__ballot(x & 1)) + 2 * __popcll(__ballot(x & 2)));
+    evacc[EV_ROULETTE] += pop == POP_ROULETTE ? n : 0u;  // both slots written: constant indices
+    evacc[EV_SPLIT] += pop == POP_SPLIT ? n : 0u;
+  }
+  if (err) atomicOr(C.inst_err + inst, err);
 
   if (MODE != MODE_STEP) return;
   // compaction: wave prefix by bit-sliced ballots, one reservation per
@@ -915,7 +935,7 @@ __device__ void collide_ion(const Ctx<R>& C, const InstParams& P, int inst, uint
 
 template <typename R, int MODE>
 __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
-  __shared__ uint32_t s_prefix[2 * MAX_INST + 1];
+  extern __shared__ uint32_t s_prefix[];  // 2 n_inst + 1 tile offsets (dynamic)
   __shared__ unsigned long long s_hist[2][HWIN];
   __shared__ uint32_t s_gen;
   __shared__ uint32_t s_wave[BLOCK / WAVE][2];
@@ -987,6 +1007,9 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
   DepWin win{-1, 0};
   Work W{-1, -1, 0, 0u, POP_NONE, 0, 0u};
   uint32_t q_head = 0, q_count = 0;  // uniform over the workgroup
+  uint32_t evacc[NEV];                // event counts of this wave since the last flush
+#pragma unroll
+  for (int q = 0; q < NEV; ++q) evacc[q] = 0u;
 
   // collide up to BLOCK queued candidates and emit the results
   auto run_queue = [&](uint32_t n) {
@@ -1010,7 +1033,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
     q_head = (q_head + n) % QCAP;
     q_count -= n;
     next_output(W, C.ip[W.inst]);
-    emit<R, MODE>(C, W, win, S, o, ev, err, g, bsel);
+    emit<R, MODE, true>(C, W, win, S, o, ev, err, g, bsel, evacc);
   };
 
   for (uint32_t t = t_begin; t < t_end; ++t) {
@@ -1035,7 +1058,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
       if (inst != win.inst) {
         // flush the old deposit window, anchor the new one a quarter window
         // below the tile's first marker
-        if (win.inst >= 0) dep_flush(C, s_hist, win, s_ev);
+        if (win.inst >= 0) dep_flush(C, s_hist, win, s_ev, evacc);
         const uint32_t first = (j / (uint32_t)P.parts) * BLOCK;
         int c0 = first < n_in ? C.buf[bsel][sp].cell[pbase + first] : 0;
         int anchor = c0 - HWIN / 4;
@@ -1146,7 +1169,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
       }
     }
     next_output(W, P);
-    emit<R, MODE>(C, W, win, S, o, ev, err, g, bsel);  // has barriers: appends are done
+    emit<R, MODE, false>(C, W, win, S, o, ev, err, g, bsel, evacc);  // has barriers: appends are done
     if (MODE == MODE_STEP) {
       q_count += s_qadd;
       __syncthreads();
@@ -1157,7 +1180,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
   }
   while (q_count > 0) run_queue(q_count < (uint32_t)BLOCK ? q_count : (uint32_t)BLOCK);
   __syncthreads();
-  if (win.inst >= 0) dep_flush(C, s_hist, win, s_ev);
+  if (win.inst >= 0) dep_flush(C, s_hist, win, s_ev, evacc);
 }
 
 // ---------------------------------------------------------------- seeding
@@ -1203,9 +1226,9 @@ __global__ void k_philox_test(const uint32_t* ctr, uint32_t k0, uint32_t k1, int
 template <typename R>
 hipError_t launch_particles(const Ctx<R>& C, int mode, hipStream_t s) {
   if (mode == MODE_STEP)
-    hipLaunchKernelGGL((k_gen<R, MODE_STEP>), dim3(C.grid), dim3(BLOCK), 0, s, C);
+    hipLaunchKernelGGL((k_gen<R, MODE_STEP>), dim3(C.grid), dim3(BLOCK), C.gen_lds, s, C);
   else
-    hipLaunchKernelGGL((k_gen<R, MODE_REFRESH>), dim3(C.grid), dim3(BLOCK), 0, s, C);
+    hipLaunchKernelGGL((k_gen<R, MODE_REFRESH>), dim3(C.grid), dim3(BLOCK), C.gen_lds, s, C);
   return hipGetLastError();
 }
 
@@ -1229,9 +1252,9 @@ hipError_t launch_seed(const Ctx<R>& C, int inst, int mode, int64_t n, double si
 }
 
 template <typename R>
-hipError_t occupancy_gen(int* blocks_per_cu) {
+hipError_t occupancy_gen(int* blocks_per_cu, size_t dyn_lds) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_gen<R, MODE_STEP>, BLOCK,
-                                                      0);
+                                                      dyn_lds);
 }
 
 template hipError_t launch_particles<float>(const Ctx<float>&, int, hipStream_t);
@@ -1242,8 +1265,8 @@ template hipError_t launch_seed<float>(const Ctx<float>&, int, int, int64_t, dou
                                        hipStream_t);
 template hipError_t launch_seed<double>(const Ctx<double>&, int, int, int64_t, double, uint32_t,
                                         hipStream_t);
-template hipError_t occupancy_gen<float>(int*);
-template hipError_t occupancy_gen<double>(int*);
+template hipError_t occupancy_gen<float>(int*, size_t);
+template hipError_t occupancy_gen<double>(int*, size_t);
 
 hipError_t launch_philox_test(const uint32_t* ctr, uint32_t k0, uint32_t k1, int64_t n,
                               uint32_t* out, hipStream_t s) {
