@@ -21,24 +21,12 @@
 namespace slpic {
 
 // ---------------------------------------------------------------- math
-__device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
-__device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float m_log(float x) { return logf(x); }
-__device__ __forceinline__ double m_log(double x) { return log(x); }
-__device__ __forceinline__ float m_log1p(float x) { return log1pf(x); }
-__device__ __forceinline__ double m_log1p(double x) { return log1p(x); }
-__device__ __forceinline__ float m_expm1(float x) { return expm1f(x); }
-__device__ __forceinline__ double m_expm1(double x) { return expm1(x); }
-__device__ __forceinline__ float m_asinh(float x) { return asinhf(x); }
-__device__ __forceinline__ double m_asinh(double x) { return asinh(x); }
 __device__ __forceinline__ float m_atan(float x) { return atanf(x); }
 __device__ __forceinline__ double m_atan(double x) { return atan(x); }
 __device__ __forceinline__ float m_tan(float x) { return tanf(x); }
 __device__ __forceinline__ double m_tan(double x) { return tan(x); }
 __device__ __forceinline__ float m_floor(float x) { return floorf(x); }
 __device__ __forceinline__ double m_floor(double x) { return floor(x); }
-__device__ __forceinline__ void m_sincospi(float x, float* s, float* c) { sincospif(x, s, c); }
-__device__ __forceinline__ void m_sincospi(double x, double* s, double* c) { sincospi(x, s, c); }
 __device__ __forceinline__ bool m_finite(float x) { return isfinite(x); }
 __device__ __forceinline__ bool m_finite(double x) { return isfinite(x); }
 template <typename R> __device__ __forceinline__ R one_below();
@@ -49,6 +37,58 @@ template <> __device__ __forceinline__ double one_below<double>() { return 0x1.f
 constexpr double QE = 1.602176634e-19;
 constexpr double ME = 9.1093837015e-31;
 constexpr double MAR = 39.948 * 1.66053906660e-27;
+
+// Arithmetic of the particle kernels.  The FP64 instantiation uses the
+// correctly rounded library functions and true division.  The FP32 one uses
+// the hardware square root, reciprocal, base-2 logarithm and exponential and
+// sine/cosine (about one ulp each; sine and cosine take revolutions), with
+// short Taylor series where a hardware form would lose relative accuracy
+// (log1p and expm1 of small arguments, asinh near 0).  That keeps every
+// FP32 quantity within a few 1e-7 relative of its exact value, far inside
+// the FP32 budget of 1e-5.
+template <typename R> struct Fm;
+template <> struct Fm<double> {
+  static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+  static __device__ __forceinline__ double div(double x, double y) { return x / y; }
+  static __device__ __forceinline__ double asinh(double x) { return ::asinh(x); }
+  static __device__ __forceinline__ double log(double x) { return ::log(x); }
+  static __device__ __forceinline__ double log1p(double x) { return ::log1p(x); }
+  static __device__ __forceinline__ double expm1(double x) { return ::expm1(x); }
+  // sin and cos of 2 pi u
+  static __device__ __forceinline__ void sincos2pi(double u, double* s, double* c) {
+    ::sincospi(2.0 * u, s, c);
+  }
+};
+template <> struct Fm<float> {
+  static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+  static __device__ __forceinline__ float div(float x, float y) { return x * __builtin_amdgcn_rcpf(y); }
+  static __device__ __forceinline__ float log(float x) { return __builtin_amdgcn_logf(x) * 0.69314718f; }
+  // asinh for x >= 0: series below 1/16, else ln 2 * log2(x + sqrt(x^2 + 1))
+  static __device__ __forceinline__ float asinh(float x) {
+    if (x < 0.0625f) {
+      const float x2 = x * x;
+      return x * (1.0f - x2 * (0.16666667f - x2 * 0.075f));
+    }
+    return 0.69314718f * __builtin_amdgcn_logf(x + __builtin_amdgcn_sqrtf(x * x + 1.0f));
+  }
+  // log(1 + x) for x >= 0: series below 2^-5 (truncation below 1e-8
+  // relative), else the logarithm of the rounded 1 + x (2e-6 at most)
+  static __device__ __forceinline__ float log1p(float x) {
+    if (x < 0.03125f)
+      return x * (1.0f - x * (0.5f - x * (0.33333334f - x * (0.25f - x * 0.2f))));
+    return log(1.0f + x);
+  }
+  // exp(y) - 1 for y >= 0: series below 2^-5, else exp(y) - 1 (2e-6 at most)
+  static __device__ __forceinline__ float expm1(float y) {
+    if (y < 0.03125f)
+      return y * (1.0f + y * 0.5f * (1.0f + y * 0.33333334f * (1.0f + y * 0.25f * (1.0f + y * 0.2f))));
+    return __builtin_amdgcn_exp2f(y * 1.44269504f) - 1.0f;
+  }
+  static __device__ __forceinline__ void sincos2pi(float u, float* s, float* c) {
+    *s = __builtin_amdgcn_sinf(u);
+    *c = __builtin_amdgcn_cosf(u);
+  }
+};
 
 // ---------------------------------------------------------------- Philox
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
@@ -93,39 +133,16 @@ __device__ __forceinline__ uint64_t child(uint32_t lo, uint32_t hi) {
 template <typename R>
 __device__ __forceinline__ void normals3(U4 r, R sigma, R& a, R& b, R& c) {
   R s0, c0, s1, c1;
-  const R r0 = m_sqrt(R(-2) * m_log(unif<R>(r.x)));
-  const R r1 = m_sqrt(R(-2) * m_log(unif<R>(r.z)));
-  m_sincospi(R(2) * unif<R>(r.y), &s0, &c0);
-  m_sincospi(R(2) * unif<R>(r.w), &s1, &c1);
+  const R r0 = Fm<R>::sqrt(R(-2) * Fm<R>::log(unif<R>(r.x)));
+  const R r1 = Fm<R>::sqrt(R(-2) * Fm<R>::log(unif<R>(r.z)));
+  Fm<R>::sincos2pi(unif<R>(r.y), &s0, &c0);
+  Fm<R>::sincos2pi(unif<R>(r.w), &s1, &c1);
   a = sigma * r0 * c0;
   b = sigma * r0 * s0;
   c = sigma * r1 * c1;
 }
 
 // ---------------------------------------------------------------- flight
-// Arithmetic of the flight solve.  The FP64 instantiation uses the
-// correctly rounded library functions; the FP32 one uses the hardware
-// square root, reciprocal and base-2 logarithm (about one ulp each), which
-// keeps the flight within a few 1e-7 relative, far inside the FP32 budget.
-template <typename R> struct Fm;
-template <> struct Fm<double> {
-  static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
-  static __device__ __forceinline__ double div(double x, double y) { return x / y; }
-  static __device__ __forceinline__ double asinh(double x) { return ::asinh(x); }
-};
-template <> struct Fm<float> {
-  static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-  static __device__ __forceinline__ float div(float x, float y) { return x * __builtin_amdgcn_rcpf(y); }
-  // asinh for x >= 0: series below 1/16, else ln 2 * log2(x + sqrt(x^2 + 1))
-  static __device__ __forceinline__ float asinh(float x) {
-    if (x < 0.0625f) {
-      const float x2 = x * x;
-      return x * (1.0f - x2 * (0.16666667f - x2 * 0.075f));
-    }
-    return 0.69314718f * __builtin_amdgcn_logf(x + __builtin_amdgcn_sqrtf(x * x + 1.0f));
-  }
-};
-
 // Integral of sqrt(u^2 + c^2) over [p, p + len], p >= 0, in a form without
 // cancellation for short intervals (q = p + len, W(u) = sqrt(u^2 + c^2)):
 //   q W(q) - p W(p) = len (q + p)(q^2 + p^2 + c^2) / (q W(q) + p W(p)),
@@ -183,7 +200,7 @@ __device__ void flight(R vx, R c, R a, R dt, R v0, int limited, R& disp, R& vx1,
     tau = dt;  // beta == 1 along the whole flight
     dv = a * dt;
   } else if (a == R(0)) {
-    tau = dt * v0 / Fm<R>::sqrt(w0sq);
+    tau = Fm<R>::div(dt * v0, Fm<R>::sqrt(w0sq));
     dv = R(0);
   } else {
     // reflect so that a > 0, unknown delta = s1 - s0 in (0, |a| dt]:
@@ -238,24 +255,16 @@ __device__ void flight(R vx, R c, R a, R dt, R v0, int limited, R& disp, R& vx1,
       delta = dn;
       if (hi - lo <= tol * hi) break;
     }
-    tau = delta / at;
+    tau = Fm<R>::div(delta, at);
     dv = sg * delta;
   }
   disp = tau * (vx + R(0.5) * dv);
   vx1 = vx + dv;
   turns = (vx * dv < R(0)) && ((vx < R(0) ? -vx : vx) < (dv < R(0) ? -dv : dv));
-  turn_disp = turns ? -vx * vx / (R(2) * a) : R(0);
+  turn_disp = turns ? Fm<R>::div(-vx * vx, R(2) * a) : R(0);
 }
 
-// beta of Eq. (11) as min(1, v0/|v|)
-template <typename R>
-__device__ __forceinline__ R beta_of(R v2, R v0, int limited) {
-  if (!limited) return R(1);
-  const R v = m_sqrt(v2);
-  return v > v0 ? v0 / v : R(1);
-}
-
-// the same with the fast square root and reciprocal in FP32 (deposit weights)
+// beta of Eq. (11) as min(1, v0/|v|) (deposit weights)
 template <typename R>
 __device__ __forceinline__ R beta_fast(R v2, R v0, int limited) {
   if (!limited) return R(1);
@@ -269,7 +278,7 @@ __device__ __forceinline__ R vs_cos(R eps, R u) {
   // Vahedi-Surendra: cos chi = (2 + eps - 2 (1 + eps)^u) / eps
   //                          = 1 - 2 expm1(u log1p(eps)) / eps
   if (!(eps > R(0))) return R(1) - R(2) * u;
-  return R(1) - R(2) * m_expm1(u * m_log1p(eps)) / eps;
+  return R(1) - Fm<R>::div(R(2) * Fm<R>::expm1(u * Fm<R>::log1p(eps)), eps);
 }
 
 // Turn unit vector (hx, hy, hz) by chi (cos given) and azimuth 2 pi u; the
@@ -282,13 +291,13 @@ __device__ __forceinline__ void turn(R hx, R hy, R hz, R cosx, R u, R& ox, R& oy
   if (ay < ax && ay <= az) { e1x = -hz; e1y = R(0); e1z = hx; }       // axis y
   else if (az < ax && az < ay) { e1x = hy; e1y = -hx; e1z = R(0); }  // axis z
   else { e1x = R(0); e1y = hz; e1z = -hy; }                          // axis x
-  const R n = m_sqrt(e1x * e1x + e1y * e1y + e1z * e1z);
-  e1x /= n; e1y /= n; e1z /= n;
+  const R n = Fm<R>::sqrt(e1x * e1x + e1y * e1y + e1z * e1z);
+  e1x = Fm<R>::div(e1x, n); e1y = Fm<R>::div(e1y, n); e1z = Fm<R>::div(e1z, n);
   const R e2x = hy * e1z - hz * e1y, e2y = hz * e1x - hx * e1z, e2z = hx * e1y - hy * e1x;
   R sn = R(1) - cosx * cosx;
-  sn = sn > R(0) ? m_sqrt(sn) : R(0);
+  sn = sn > R(0) ? Fm<R>::sqrt(sn) : R(0);
   R sp, cp;
-  m_sincospi(R(2) * u, &sp, &cp);
+  Fm<R>::sincos2pi(u, &sp, &cp);
   ox = cosx * hx + sn * (cp * e1x + sp * e2x);
   oy = cosx * hy + sn * (cp * e1y + sp * e2y);
   oz = cosx * hz + sn * (cp * e1z + sp * e2z);
@@ -296,8 +305,8 @@ __device__ __forceinline__ void turn(R hx, R hy, R hz, R cosx, R u, R& ox, R& oy
 
 template <typename R>
 __device__ __forceinline__ void unit3(R vx, R vy, R vz, R& hx, R& hy, R& hz) {
-  const R s = m_sqrt(vx * vx + vy * vy + vz * vz);
-  if (s > R(0)) { hx = vx / s; hy = vy / s; hz = vz / s; }
+  const R s = Fm<R>::sqrt(vx * vx + vy * vy + vz * vz);
+  if (s > R(0)) { hx = Fm<R>::div(vx, s); hy = Fm<R>::div(vy, s); hz = Fm<R>::div(vz, s); }
   else { hx = R(1); hy = R(0); hz = R(0); }
 }
 
@@ -313,11 +322,11 @@ __device__ __forceinline__ int select_channel(const Ctx<R>& C, R eps, R scale, R
   if (!(eps > C.xs_e[0])) { i = 0; t = R(0); }
   else if (!(eps < C.xs_e[n - 1])) { i = n - 2; t = R(1); }
   else {
-    i = (int)((m_log(eps) - C.log_emin) * C.inv_dlog);
+    i = (int)((Fm<R>::log(eps) - C.log_emin) * C.inv_dlog);
     i = i < 0 ? 0 : (i > n - 2 ? n - 2 : i);
     if (eps < C.xs_e[i] && i > 0) --i;
     else if (!(eps < C.xs_e[i + 1]) && i < n - 2) ++i;
-    t = (eps - C.xs_e[i]) / (C.xs_e[i + 1] - C.xs_e[i]);
+    t = Fm<R>::div(eps - C.xs_e[i], C.xs_e[i + 1] - C.xs_e[i]);
   }
   const R* a = C.xs_sig + (size_t)i * C.n_chan;
   const R* b = a + C.n_chan;
@@ -634,9 +643,10 @@ struct LaneOut {
   int ne, ni;   // how many of e[] / i1 are set
 };
 
-constexpr int QCAP = 2 * BLOCK;  // collision-queue slots per workgroup
+constexpr int NWAVE = BLOCK / WAVE;
+constexpr int QW = 2 * WAVE;  // collision-queue slots per wave
 
-// What a workgroup is working on: one (instance, species), and the output
+// What a wave is working on: one (instance, species), and the output
 // partition of its next emit.
 struct Work {
   int inst, sp, part;
@@ -646,13 +656,14 @@ struct Work {
   uint32_t emits;
 };
 
-// Output partition of a workgroup's next emit: an integer hash of
-// (workgroup, emit number, step), so that each partition receives an equal
-// share of a step's output in expectation whatever partition the markers
-// came from, and no fixed stride between tiles can map one input partition
-// to one output partition step after step.
+// Output partition of a wave's next emit: an integer hash of (wave, emit
+// number, step), so that each partition receives an equal share of a step's
+// output in expectation whatever partition the markers came from, and no
+// fixed stride between tiles can map one input partition to one output
+// partition step after step.
 __device__ __forceinline__ void next_output(Work& W, const InstParams& P) {
-  uint32_t h = blockIdx.x * 0x9E3779B1u ^ (W.emits * 0x85EBCA77u + W.step * 0xC2B2AE3Du);
+  const uint32_t wid = blockIdx.x * (uint32_t)NWAVE + threadIdx.x / WAVE;
+  uint32_t h = wid * 0x9E3779B1u ^ (W.emits * 0x85EBCA77u + W.step * 0xC2B2AE3Du);
   h ^= h >> 16;
   h *= 0x7FEB352Du;
   h ^= h >> 15;
@@ -663,23 +674,18 @@ __device__ __forceinline__ void next_output(Work& W, const InstParams& P) {
   ++W.emits;
 }
 
-struct Shared {
-  unsigned long long (*hist)[HWIN];
-  uint32_t* ev;
-  uint32_t (*wave)[2];
-  uint32_t* base;
-};
-
 // Population control, charge deposit, event counts and stream compaction of
-// the markers each lane produced.  Called by all threads of the workgroup.
-// QUEUE: outputs of collided candidates (collision events) rather than of a
-// tile (wall and emission events).  Event counts go to the wave's
-// accumulators evacc (equal in all lanes of a wave).
+// the markers each lane of one wave produced.  Called by all lanes of the
+// wave, independently of the other waves.  QUEUE: outputs of collided
+// candidates (collision events) rather than of a tile (wall and emission
+// events).  Event counts go to the wave's accumulators evacc (equal in all
+// lanes).
 template <typename R, int MODE, bool QUEUE>
-__device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWin& win, const Shared& S,
-                     const LaneOut<R>& o, uint32_t ev, uint32_t err, uint32_t g, uint32_t bsel,
-                     uint32_t (&evacc)[NEV]) {
-  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
+__device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWin& win,
+                                     unsigned long long (*hist)[HWIN], const LaneOut<R>& o,
+                                     uint32_t ev, uint32_t err, uint32_t g, uint32_t bsel,
+                                     uint32_t (&evacc)[NEV]) {
+  const int lane = threadIdx.x & (WAVE - 1);
   const InstParams& P = C.ip[W.inst];
   const int inst = W.inst, pop = W.pop;
   const uint32_t step = W.step;
@@ -733,14 +739,14 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
       const Mk<R>& e = o.e[q];
       const R b = beta_fast(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
       const unsigned long long mul = clone_e[q] ? 2ull : 1ull;
-      dep_add(C.acc, C.acc, S.hist, win, 0, P.node, C.total_nodes, e.cell,
+      dep_add(C.acc, C.acc, hist, win, 0, P.node, C.total_nodes, e.cell,
               fixed_pt<R>(b * (R(1) - e.off), shift) * mul, fixed_pt<R>(b * e.off, shift) * mul);
     }
     if (o.ni && keep_i) {
       const Mk<R>& e = o.i1;
       const R b = beta_fast(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
       const unsigned long long mul = clone_i ? 2ull : 1ull;
-      dep_add(C.acc, C.acc, S.hist, win, 1, P.node, C.total_nodes, e.cell,
+      dep_add(C.acc, C.acc, hist, win, 1, P.node, C.total_nodes, e.cell,
               fixed_pt<R>(b * (R(1) - e.off), shift) * mul, fixed_pt<R>(b * e.off, shift) * mul);
     }
   }
@@ -761,36 +767,24 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
   if (err) atomicOr(C.inst_err + inst, err);
 
   if (MODE != MODE_STEP) return;
-  // compaction: wave prefix by bit-sliced ballots, one reservation per
-  // workgroup and species on the partition's counter
+  // compaction: prefix within the wave by bit-sliced ballots, one
+  // reservation per wave and species on the partition's counter
   const unsigned long long lt = (1ull << lane) - 1ull;
   const unsigned long long be0 = __ballot(cnt_e & 1), be1 = __ballot(cnt_e & 2),
                            be2 = __ballot(cnt_e & 4);
   const unsigned long long bi0 = __ballot(cnt_i & 1), bi1 = __ballot(cnt_i & 2);
   const uint32_t pre_e = __popcll(be0 & lt) + 2 * __popcll(be1 & lt) + 4 * __popcll(be2 & lt);
   const uint32_t pre_i = __popcll(bi0 & lt) + 2 * __popcll(bi1 & lt);
+  const uint32_t te = __popcll(be0) + 2 * __popcll(be1) + 4 * __popcll(be2);
+  const uint32_t ti = __popcll(bi0) + 2 * __popcll(bi1);
+  uint32_t base_e = 0u, base_i = 0u;
   if (lane == 0) {
-    S.wave[wave][0] = __popcll(be0) + 2 * __popcll(be1) + 4 * __popcll(be2);
-    S.wave[wave][1] = __popcll(bi0) + 2 * __popcll(bi1);
+    if (te) base_e = atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 0, W.part), te);
+    if (ti) base_i = atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 1, W.part), ti);
   }
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t te = 0, ti = 0;
-    for (int w = 0; w < BLOCK / WAVE; ++w) {
-      const uint32_t a = S.wave[w][0], b = S.wave[w][1];
-      S.wave[w][0] = te;
-      S.wave[w][1] = ti;
-      te += a;
-      ti += b;
-    }
-    S.base[0] = te ? atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 0, W.part), te) : 0u;
-    S.base[1] = ti ? atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 1, W.part), ti) : 0u;
-  }
-  __syncthreads();
   const Soa<R> oe = C.buf[1 - bsel][0], oi = C.buf[1 - bsel][1];
-  uint32_t pe = S.base[0] + S.wave[wave][0] + pre_e;
-  uint32_t pi = S.base[1] + S.wave[wave][1] + pre_i;
-  __syncthreads();  // S.wave / S.base are reused by the next call
+  uint32_t pe = __builtin_amdgcn_readfirstlane(base_e) + pre_e;
+  uint32_t pi = __builtin_amdgcn_readfirstlane(base_i) + pre_i;
   uint32_t werr = 0;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -848,7 +842,7 @@ __device__ void collide_electron(const Ctx<R>& C, const InstParams& P, int inst,
     for (int q = 0; q < C.n_chan; ++q)
       if (ch < 0 && u < P.t_fixed[q]) ch = q;
   } else {
-    const R sp0 = m_sqrt(v2);
+    const R sp0 = Fm<R>::sqrt(v2);
     const R v0 = (R)P.v0;
     const R slow = P.limited ? (sp0 < v0 ? sp0 : v0) : sp0;
     const R numax = (R)P.nu_max_e;
@@ -865,14 +859,14 @@ __device__ void collide_electron(const Ctx<R>& C, const InstParams& P, int inst,
       const R cx = vs_cos(eps, unif<R>(r.z));
       const R e1 = eps * (R(1) - R(2.0 * ME / MAR) * (R(1) - cx));
       turn(hx, hy, hz, cx, unif<R>(r.w), ox, oy, oz);
-      const R sp1 = m_sqrt(e1 * (R)(2.0 * QE / ME));
+      const R sp1 = Fm<R>::sqrt(e1 * (R)(2.0 * QE / ME));
       m.vx = sp1 * ox; m.vy = sp1 * oy; m.vz = sp1 * oz;
       ev |= 1u << EV_ELASTIC;
     } else if (kind == 1) {  // excitation, isotropic
       R e1 = eps - thr;
       e1 = e1 > R(0) ? e1 : R(0);
       turn(hx, hy, hz, R(1) - R(2) * unif<R>(r.z), unif<R>(r.w), ox, oy, oz);
-      const R sp1 = m_sqrt(e1 * (R)(2.0 * QE / ME));
+      const R sp1 = Fm<R>::sqrt(e1 * (R)(2.0 * QE / ME));
       m.vx = sp1 * ox; m.vy = sp1 * oy; m.vz = sp1 * oz;
       ev |= 1u << EV_EXCIT;
     } else {  // ionization: share eps - I, spawn e- and Ar+
@@ -886,10 +880,10 @@ __device__ void collide_electron(const Ctx<R>& C, const InstParams& P, int inst,
       R esc = eav - eej;
       if (C.flags & 1u) { eej = R(0); esc = R(0); }
       turn(hx, hy, hz, vs_cos(esc, unif<R>(r.z)), unif<R>(r.w), ox, oy, oz);
-      const R sps = m_sqrt(esc * (R)(2.0 * QE / ME));
+      const R sps = Fm<R>::sqrt(esc * (R)(2.0 * QE / ME));
       R jx, jy, jz;
       turn(hx, hy, hz, vs_cos(eej, unif<R>(q.y)), unif<R>(q.z), jx, jy, jz);
-      const R spj = m_sqrt(eej * (R)(2.0 * QE / ME));
+      const R spj = Fm<R>::sqrt(eej * (R)(2.0 * QE / ME));
       m.vx = sps * ox; m.vy = sps * oy; m.vz = sps * oz;
       Mk<R> e2 = m;
       e2.vx = spj * jx; e2.vy = spj * jy; e2.vz = spj * jz;
@@ -916,7 +910,7 @@ __device__ void collide_ion(const Ctx<R>& C, const InstParams& P, int inst, uint
   if (!C.fixed) {
     const U4 r = draw(m.id, step, CH_CX, C.seed, inst);
     const R v2 = m.vx * m.vx + m.vy * m.vy + m.vz * m.vz;
-    const R sp1 = m_sqrt(v2);
+    const R sp1 = Fm<R>::sqrt(v2);
     const R v0 = (R)P.v0;
     const R slow = P.limited ? (sp1 < v0 ? sp1 : v0) : sp1;
     const R nu = (R)P.n_g * (R)P.sigma_cx * slow;
@@ -938,27 +932,23 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
   extern __shared__ uint32_t s_prefix[];  // 2 n_inst + 1 tile offsets (dynamic)
   __shared__ unsigned long long s_hist[2][HWIN];
   __shared__ uint32_t s_gen;
-  __shared__ uint32_t s_wave[BLOCK / WAVE][2];
-  __shared__ uint32_t s_base[2];
   __shared__ uint32_t s_ev[NEV];
   __shared__ double s_scan[4];
-  // collision queue (ring): candidates of the current (instance, species)
-  __shared__ int32_t q_cell[QCAP];
-  __shared__ R q_off[QCAP], q_vx[QCAP], q_vy[QCAP], q_vz[QCAP];
-  __shared__ uint64_t q_id[QCAP];
-  __shared__ uint32_t s_qadd;
+  // collision queues (rings), one per wave: candidates of the wave's
+  // current (instance, species)
+  __shared__ int32_t q_cell[NWAVE][QW];
+  __shared__ R q_off[NWAVE][QW], q_vx[NWAVE][QW], q_vy[NWAVE][QW], q_vz[NWAVE][QW];
+  __shared__ uint64_t q_id[NWAVE][QW];
 
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   if (tid == 0) {
     const unsigned long long ticket = atomicAdd(&C.g->wgc, 1ull);
     s_gen = (uint32_t)(ticket / (unsigned long long)C.grid);
-    s_qadd = 0u;
   }
   if (tid < NEV) s_ev[tid] = 0;
   for (int i = tid; i < 2 * HWIN; i += BLOCK) s_hist[i / HWIN][i % HWIN] = 0ull;
   __syncthreads();
   const uint32_t g = s_gen;
-  const Shared S{s_hist, s_ev, s_wave, s_base};
 
   // tile space of this generation: electrons of instance 0, ions of
   // instance 0, electrons of instance 1, ...; an (instance, species) with P
@@ -1001,39 +991,47 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
   const uint32_t bsel = C.g->bufsel[g % 2u];
 
   // each workgroup takes a contiguous run of tiles, so that (for markers in
-  // cell order) its deposits stay inside one LDS window
+  // cell order) its deposits stay inside one LDS window.  Wave w of the
+  // workgroup takes markers [64 w, 64 w + 64) of every tile and runs on its
+  // own: compaction, collision queue and output reservations are per wave,
+  // and the waves meet only to flush the deposit window when the instance
+  // changes (all four change at the same tile).
   const uint32_t per = (n_tiles + (uint32_t)C.grid - 1) / (uint32_t)C.grid;
   const uint32_t t_begin = blockIdx.x * per, t_end = min(n_tiles, t_begin + per);
   DepWin win{-1, 0};
   Work W{-1, -1, 0, 0u, POP_NONE, 0, 0u};
-  uint32_t q_head = 0, q_count = 0;  // uniform over the workgroup
+  uint32_t q_head = 0, q_count = 0;  // uniform over the wave
   uint32_t evacc[NEV];                // event counts of this wave since the last flush
 #pragma unroll
   for (int q = 0; q < NEV; ++q) evacc[q] = 0u;
+  const unsigned long long lt = (1ull << lane) - 1ull;
 
-  // collide up to BLOCK queued candidates and emit the results
+  // collide up to WAVE queued candidates and emit the results
   auto run_queue = [&](uint32_t n) {
     LaneOut<R> o;
     o.ne = o.ni = 0;
     uint32_t ev = 0, err = 0;
-    if ((uint32_t)tid < n) {
-      const uint32_t s = (q_head + tid) % QCAP;
+    // the appends of other lanes land before these reads (one wave: LDS
+    // operations complete in order; the fence keeps the compiler's order)
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if ((uint32_t)lane < n) {
+      const uint32_t s = (q_head + (uint32_t)lane) % QW;
       Mk<R> m;
-      m.cell = q_cell[s];
-      m.off = q_off[s];
-      m.vx = q_vx[s];
-      m.vy = q_vy[s];
-      m.vz = q_vz[s];
-      m.id = q_id[s];
+      m.cell = q_cell[wv][s];
+      m.off = q_off[wv][s];
+      m.vx = q_vx[wv][s];
+      m.vy = q_vy[wv][s];
+      m.vz = q_vz[wv][s];
+      m.id = q_id[wv][s];
       const InstParams& P = C.ip[W.inst];
       if (W.sp == 0) collide_electron(C, P, W.inst, W.step, m, o, ev, err);
       else collide_ion(C, P, W.inst, W.step, m, o, ev, err);
     }
-    __syncthreads();  // queue slots read before later appends reuse them
-    q_head = (q_head + n) % QCAP;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // reads before reuse
+    q_head = (q_head + n) % QW;
     q_count -= n;
     next_output(W, C.ip[W.inst]);
-    emit<R, MODE, true>(C, W, win, S, o, ev, err, g, bsel, evacc);
+    emit<R, MODE, true>(C, W, win, s_hist, o, ev, err, g, bsel, evacc);
   };
 
   for (uint32_t t = t_begin; t < t_end; ++t) {
@@ -1049,12 +1047,12 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
     const uint32_t j = t - s_prefix[k];
     const int part = (int)(j % (uint32_t)P.parts);
     const uint32_t n_in = C.counts[cidx(C.n_inst, g % 3u, inst, sp, part)];
-    const uint32_t idx = (j / (uint32_t)P.parts) * BLOCK + tid;
+    const uint32_t idx = (j / (uint32_t)P.parts) * BLOCK + (uint32_t)tid;
     const bool valid = idx < n_in;
     const int64_t pbase = P.seg + (int64_t)part * P.cap_p;
     if (inst != W.inst || sp != W.sp) {
       // new (instance, species): collide what is queued for the old one
-      while (q_count > 0) run_queue(q_count < (uint32_t)BLOCK ? q_count : (uint32_t)BLOCK);
+      while (q_count > 0) run_queue(q_count < (uint32_t)WAVE ? q_count : (uint32_t)WAVE);
       if (inst != win.inst) {
         // flush the old deposit window, anchor the new one a quarter window
         // below the tile's first marker
@@ -1102,7 +1100,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
       const R e0 = E[m.cell], e1 = E[m.cell + 1];
       const R Ep = e0 + m.off * (e1 - e0);
       const R a = (R)(sp == 0 ? P.qm_e : P.qm_i) * Ep;
-      const R c = m_sqrt(m.vy * m.vy + m.vz * m.vz);
+      const R c = Fm<R>::sqrt(m.vy * m.vy + m.vz * m.vz);
       R disp, vx1, tdisp;
       bool turns;
       flight<R>(m.vx, c, a, (R)P.dt, v0, limited, disp, vx1, turns, tdisp);
@@ -1158,28 +1156,24 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
       }
     }
     if (MODE == MODE_STEP) {
+      // append the wave's candidates to its queue
+      const unsigned long long bc = __ballot(cand);
       if (cand) {
-        const uint32_t s = (q_head + q_count + atomicAdd(&s_qadd, 1u)) % QCAP;
-        q_cell[s] = m.cell;
-        q_off[s] = m.off;
-        q_vx[s] = m.vx;
-        q_vy[s] = m.vy;
-        q_vz[s] = m.vz;
-        q_id[s] = m.id;
+        const uint32_t s = (q_head + q_count + (uint32_t)__popcll(bc & lt)) % QW;
+        q_cell[wv][s] = m.cell;
+        q_off[wv][s] = m.off;
+        q_vx[wv][s] = m.vx;
+        q_vy[wv][s] = m.vy;
+        q_vz[wv][s] = m.vz;
+        q_id[wv][s] = m.id;
       }
+      q_count += (uint32_t)__popcll(bc);
     }
     next_output(W, P);
-    emit<R, MODE, false>(C, W, win, S, o, ev, err, g, bsel, evacc);  // has barriers: appends are done
-    if (MODE == MODE_STEP) {
-      q_count += s_qadd;
-      __syncthreads();
-      if (tid == 0) s_qadd = 0u;
-      __syncthreads();  // the reset lands before the next tile's appends
-      if (q_count >= (uint32_t)BLOCK) run_queue((uint32_t)BLOCK);
-    }
+    emit<R, MODE, false>(C, W, win, s_hist, o, ev, err, g, bsel, evacc);
+    if (MODE == MODE_STEP && q_count >= (uint32_t)WAVE) run_queue((uint32_t)WAVE);
   }
-  while (q_count > 0) run_queue(q_count < (uint32_t)BLOCK ? q_count : (uint32_t)BLOCK);
-  __syncthreads();
+  while (q_count > 0) run_queue(q_count < (uint32_t)WAVE ? q_count : (uint32_t)WAVE);
   if (win.inst >= 0) dep_flush(C, s_hist, win, s_ev, evacc);
 }
 
