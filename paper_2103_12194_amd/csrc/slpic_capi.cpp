@@ -861,10 +861,13 @@ int slpic_read_stats(slpic_t* h, int inst, int64_t first_step, int n, slpic_stat
   HIPCHK(h, hipStreamSynchronize(h->stream));
   if (first_step + n > h->steps || first_step + RING < h->steps)
     return fail(h, SLPIC_INVALID_ARG, "requested steps are not in the statistics ring");
-  for (int k = 0; k < n; ++k) {
+  // at most two contiguous pieces of the ring
+  for (int k = 0; k < n;) {
     const int64_t slot = (first_step + k) % RING;
+    const int run = (int)std::min<int64_t>(n - k, RING - slot);
     HIPCHK(h, hipMemcpy(rows + k, h->ws + h->L.ring + sizeof(StatsRow) * ((size_t)inst * RING + slot),
-                        sizeof(StatsRow), hipMemcpyDeviceToHost));
+                        sizeof(StatsRow) * run, hipMemcpyDeviceToHost));
+    k += run;
   }
   return SLPIC_OK;
 }
