@@ -155,6 +155,20 @@ int slpic_sync(slpic_t* h);
  * launches (0).  Default 0. */
 int slpic_use_graph(slpic_t* h, int enable);
 
+/* Launch shape.  The particle kernel runs on a grid of workgroups that each
+ * take a contiguous run of 256-marker tiles; results do not depend on the
+ * grid (random numbers are keyed by marker id and step, deposits are exact
+ * fixed-point sums), only the time does.  slpic_autotune times trial_steps
+ * steps (after one untimed step) on each candidate grid -- a quarter, half
+ * and all of the compute units, and 1 .. the resident maximum workgroups per
+ * compute unit -- keeps the fastest and writes it to *grid (host, may be
+ * NULL).  The trial steps are ordinary steps of the simulation and count in
+ * slpic_steps_done.  Synchronizes; drops a captured graph. */
+int slpic_autotune(slpic_t* h, int trial_steps, int* grid);
+
+/* Current particle-kernel grid (host output). */
+int slpic_grid(slpic_t* h, int* grid);
+
 /* Kernel timing.  enable != 0 starts recording HIP events on the handle's
  * stream before the particle kernel, between it and the per-instance tail
  * kernel, and after the tail kernel of every following step (steps are then

@@ -73,7 +73,8 @@ EXPORTS = ["slpic_workspace_bytes", "slpic_create", "slpic_step", "slpic_sync",
            "slpic_read_markers", "slpic_read_fields", "slpic_read_stats",
            "slpic_scalars", "slpic_steps_done", "slpic_last_error",
            "slpic_destroy", "slpic_philox_device", "slpic_profile",
-           "slpic_kernel_times", "slpic_partitions"]
+           "slpic_kernel_times", "slpic_partitions", "slpic_autotune",
+           "slpic_grid"]
 
 
 def lib():
@@ -104,6 +105,8 @@ def lib():
         L.slpic_last_error.argtypes = [vp]
         L.slpic_destroy.argtypes = [vp]
         L.slpic_profile.argtypes = [vp, i32]
+        L.slpic_autotune.argtypes = [vp, i32, P(i32)]
+        L.slpic_grid.argtypes = [vp, P(i32)]
         L.slpic_partitions.argtypes = [vp, i32, i32, P(C.c_int32), P(i64), vp]
         L.slpic_kernel_times.argtypes = [vp, P(C.c_double), P(C.c_double), P(i64)]
         L.slpic_philox_device.argtypes = [vp, C.c_uint32, C.c_uint32, i64, vp, vp]
@@ -222,6 +225,18 @@ class Sim:
 
     def use_graph(self, enable=True):
         _check(lib().slpic_use_graph(self.h, 1 if enable else 0), self.h)
+
+    def autotune(self, trial_steps=4):
+        """Pick the fastest particle-kernel grid by timing trial steps (they
+        are real steps); returns the grid."""
+        g = C.c_int()
+        _check(lib().slpic_autotune(self.h, int(trial_steps), C.byref(g)), self.h)
+        return int(g.value)
+
+    def grid(self):
+        g = C.c_int()
+        _check(lib().slpic_grid(self.h, C.byref(g)), self.h)
+        return int(g.value)
 
     def profile(self, enable=True):
         """Record per-kernel HIP events around the following steps."""

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -261,6 +262,7 @@ struct slpic_handle {
   Ctx<float> c32;
   Ctx<double> c64;
   int grid = 0;
+  int cus = 0, occ_per_cu = 0;  // compute units; resident particle workgroups per CU
   uint64_t gen = 0;      // generation launches issued
   int64_t steps = 0;
   bool use_graph = false;
@@ -627,6 +629,8 @@ int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst
     return rc;
   }
   h->grid = std::max(1, std::min(cus * std::max(per_cu, 1), h->L.max_tiles));
+  h->cus = cus;
+  h->occ_per_cu = std::max(per_cu, 1);
   int lds_max = 0;
   if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     lds_max = 65536;
@@ -732,6 +736,75 @@ int slpic_step(slpic_t* h, int n_steps) {
     h->steps += 1;
   }
   return SLPIC_OK;
+}
+
+// Changes the particle-kernel grid between steps.  The kernels derive the
+// generation from the workgroup counter (generation x grid before every
+// launch pair), so the counter is rewritten for the new grid; a captured
+// graph holds the old grid and is dropped.
+static int set_grid(slpic_t* h, int grid) {
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  const unsigned long long wgc = (unsigned long long)h->gen * (unsigned long long)grid;
+  HIPCHK(h, hipMemcpy(h->ws + h->L.glob + offsetof(Global, wgc), &wgc, sizeof(wgc),
+                      hipMemcpyHostToDevice));
+  h->grid = grid;
+  h->c32.grid = grid;
+  h->c64.grid = grid;
+  if (h->graph) {
+    (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  return SLPIC_OK;
+}
+
+int slpic_grid(slpic_t* h, int* grid) {
+  if (!h || !grid) return fail(h, SLPIC_INVALID_ARG, "null grid output");
+  *grid = h->grid;
+  return SLPIC_OK;
+}
+
+int slpic_autotune(slpic_t* h, int trial_steps, int* grid) {
+  if (!h || trial_steps < 1 || h->profiling) return fail(h, SLPIC_INVALID_ARG, "bad autotune arguments");
+  std::vector<int> cand;
+  auto add = [&](int g) {
+    g = std::max(1, std::min(g, h->L.max_tiles));
+    if (std::find(cand.begin(), cand.end(), g) == cand.end()) cand.push_back(g);
+  };
+  for (int q = 4; q >= 1; q /= 2) add(h->cus / q);
+  for (int pc = 1; pc <= h->occ_per_cu; ++pc) add(h->cus * pc);
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  hipError_t er = hipEventCreate(&e1);
+  if (er != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(h, er, "hipEventCreate");
+  }
+  int best = h->grid, rc = SLPIC_OK;
+  float best_ms = 0.0f;
+  for (size_t c = 0; c < cand.size() && rc == SLPIC_OK; ++c) {
+    rc = set_grid(h, cand[c]);
+    // one untimed step on the new grid, then the timed ones
+    for (int k = 0; k <= trial_steps && rc == SLPIC_OK; ++k) {
+      if (k == 1 && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(h, SLPIC_HIP_ERROR, "event");
+      if (rc == SLPIC_OK) rc = launch_gen_any(h, MODE_STEP);
+      if (rc == SLPIC_OK) h->steps += 1;
+    }
+    float ms = 0.0f;
+    if (rc == SLPIC_OK && (hipEventRecord(e1, h->stream) != hipSuccess ||
+                           hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = fail(h, SLPIC_HIP_ERROR, "autotune timing");
+    if (rc == SLPIC_OK && (c == 0 || ms < best_ms)) {
+      best_ms = ms;
+      best = cand[c];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  rc = set_grid(h, best);
+  if (rc == SLPIC_OK && grid) *grid = best;
+  return rc;
 }
 
 int slpic_profile(slpic_t* h, int enable) {

@@ -186,3 +186,56 @@ def test_long_batched_run_stays_within_capacity():
         assert n <= 2.5 * inst.n_target + 64, (k, n, inst.n_target)
         h = gpu.history(gpu.steps_done() - 100, 100, inst=k)
         assert np.all(h["n_e"] + h["n_i"] <= 2.5 * inst.n_target + 64), k
+
+
+def test_graph_replays_match_eager_steps(xs_argon):
+    """Steps replayed from the captured 16-step graph equal eagerly launched
+    steps (FP64: bit-exact statistics and markers), replay after replay, with
+    reads and synchronizations between the replays."""
+    inst = _c1_small(n_seed=3000, n_target=2500)
+    run = configs.Run(precision=64)
+    eager = slpic.Sim([inst], run, xs_argon)
+    graph = slpic.Sim([inst], run, xs_argon)
+    graph.use_graph(True)
+    for rep in range(4):
+        eager.step(16)
+        graph.step(16)  # one replay of the graph
+        assert eager.sync() == 0 and graph.sync() == 0
+        first = eager.steps_done() - 16
+        he, hg = eager.history(first, 16), graph.history(first, 16)
+        for k in STAT_INT + ["w_e", "w_i", "w_j"]:
+            assert np.array_equal(he[k], hg[k]), (rep, k)
+        for sp in (0, 1):
+            compare_populations(graph.read(sp), eager.read(sp), 0.0, 0.0,
+                                graph.scalars()["v0"], label=f"replay {rep} sp {sp}")
+        assert np.array_equal(eager.fields()[2], graph.fields()[2])
+
+
+def test_autotuned_grid_changes_timing_not_results(xs_argon):
+    """The autotuner steps the simulation on several grids; the markers and
+    statistics must equal those of a run that never changed its grid."""
+    insts = [_c1_small(n_seed=2000, n_target=1500),
+             configs.Instance(d=0.02, p_torr=0.5, V=250.0, cells=130,
+                              gamma_se=0.1, seed_mode=configs.SEED_CATHODE,
+                              n_seed=400, n_target=0, capacity=20000)]
+    run = configs.Run(precision=64)
+    a = slpic.Sim(insts, run, xs_argon)
+    b = slpic.Sim(insts, run, xs_argon)
+    g0 = a.grid()
+    g = a.autotune(2)
+    assert g == a.grid() and 1 <= g
+    n = a.steps_done()
+    assert n >= 6
+    b.step(n)
+    a.step(10)
+    b.step(10)
+    assert a.sync() == 0 and b.sync() == 0
+    for k, x in enumerate(insts):
+        ha = a.history(a.steps_done() - 16, 16, inst=k)
+        hb = b.history(b.steps_done() - 16, 16, inst=k)
+        for key in STAT_INT + ["w_e", "w_i", "w_j"]:
+            assert np.array_equal(ha[key], hb[key]), (k, key)
+        for sp in (0, 1):
+            compare_populations(a.read(sp, k), b.read(sp, k), 0.0, 0.0,
+                                a.scalars(k)["v0"], label=f"inst {k} sp {sp}")
+    print("default grid", g0, "autotuned", g)
