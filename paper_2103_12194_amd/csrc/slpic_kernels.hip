@@ -119,6 +119,14 @@ __device__ __forceinline__ U4 draw(uint64_t id, uint32_t step, uint32_t ch, uint
   return philox((uint32_t)id, (uint32_t)(id >> 32), step, ch, seed, inst);
 }
 
+// the same stream out of line, for draws on rare paths (population
+// control, emission, ionization products, charge exchange): keeps one copy
+// of the ten rounds in the code instead of one per call site
+__device__ __noinline__ U4 draw_cold(uint64_t id, uint32_t step, uint32_t ch, uint32_t seed,
+                                     uint32_t inst) {
+  return draw(id, step, ch, seed, inst);
+}
+
 // u = (2 (r >> 9) + 1) 2^-24: exact in FP32 and FP64, never 0 or 1
 template <typename R>
 __device__ __forceinline__ R unif(uint32_t r) {
@@ -212,9 +220,14 @@ __device__ void flight(R vx, R c, R a, R dt, R v0, int limited, R& disp, R& vx1,
     const R w0 = Fm<R>::sqrt(w0sq);
     R lo = R(0), hi = rhs, delta;
     if (w0 > v0) {
-      // speed-limited start: path length w0 d + s0 d^2 / (2 w0) = v0 rhs
+      // speed-limited start: the path length in s, integral of W = |v| over
+      // [s0, s0 + d], is w0 d + s0 d^2 / (2 w0) + c^2 d^3 / (6 w0^3) + ...;
+      // solve the quadratic, then one Newton step adds the cubic term
       const R disc = w0 * w0 + R(2) * s0 * v0 * Fm<R>::div(rhs, w0);
       delta = disc > R(0) ? Fm<R>::div(R(2) * v0 * rhs, w0 + Fm<R>::sqrt(disc)) : R(-1);
+      const R iw = Fm<R>::div(R(1), w0);
+      const R cub = c * c * iw * iw * iw * (R(1) / R(6)) * delta * delta * delta;
+      delta -= Fm<R>::div(cub, w0 + s0 * iw * delta);
     } else {
       // slow start: the c = 0 motion (beta = 1 up to v0, then v0 ds = s ds)
       const R as = s0 < R(0) ? -s0 : s0;
@@ -228,7 +241,8 @@ __device__ void flight(R vx, R c, R a, R dt, R v0, int limited, R& disp, R& vx1,
     // Halley iteration on f(delta) = time_span - rhs, f' = max(1, W/v0),
     // f'' = s / (v0 W) where W > v0, kept inside the bracket [lo, hi]
     const R tol = sizeof(R) == 4 ? R(1e-7) : R(1e-16);
-    const R quick = sizeof(R) == 4 ? R(3e-4) : R(1e-8);  // error after a step ~ step^2
+    // a Halley step of relative size e leaves an error of order e^3
+    const R quick = sizeof(R) == 4 ? R(2e-3) : R(1e-8);
     for (int it = 0; it < 40; ++it) {
       const R f = time_span(s0, delta, c, inv_v0, ss) - rhs;
       if (f > R(0)) hi = delta;
@@ -600,25 +614,22 @@ __device__ __forceinline__ void dep_add(const unsigned long long* acc_base, unsi
   }
 }
 
-// Adds the window and the event counts gathered since the last flush (per
-// wave, in registers) to global memory.  Called by all threads.
+// Adds the window and the event counts gathered since the last flush (one
+// LDS row per wave) to global memory.  Called by all threads.
 template <typename R>
 __device__ __forceinline__ void dep_flush(const Ctx<R>& C, unsigned long long (*hist)[HWIN], const DepWin& w,
-                          uint32_t* ev, uint32_t (&evacc)[NEV]) {
-  if ((threadIdx.x & (WAVE - 1)) == 0) {
-#pragma unroll
-    for (int q = 0; q < NEV; ++q)
-      if (evacc[q]) atomicAdd(&ev[q], evacc[q]);
-  }
-#pragma unroll
-  for (int q = 0; q < NEV; ++q) evacc[q] = 0u;
+                          uint32_t (*evw)[NEV]) {
   __syncthreads();
   const int slot = blockIdx.x % NSLOT;
   if (threadIdx.x < NEV) {
-    const uint32_t v = ev[threadIdx.x];
+    uint32_t v = 0u;
+#pragma unroll
+    for (int q = 0; q < BLOCK / WAVE; ++q) {
+      v += evw[q][threadIdx.x];
+      evw[q][threadIdx.x] = 0u;
+    }
     if (v) atomicAdd(C.ev + ((size_t)w.inst * NEV + threadIdx.x) * NSLOT + slot,
                      (unsigned long long)v);
-    ev[threadIdx.x] = 0u;
   }
   const InstParams& P = C.ip[w.inst];
   const int nn = min(HWIN, P.cells + 1 - w.anchor);
@@ -678,13 +689,12 @@ __device__ __forceinline__ void next_output(Work& W, const InstParams& P) {
 // the markers each lane of one wave produced.  Called by all lanes of the
 // wave, independently of the other waves.  QUEUE: outputs of collided
 // candidates (collision events) rather than of a tile (wall and emission
-// events).  Event counts go to the wave's accumulators evacc (equal in all
-// lanes).
+// events).  Event counts go to the wave's row evw of LDS counters.
 template <typename R, int MODE, bool QUEUE>
 __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWin& win,
                                      unsigned long long (*hist)[HWIN], const LaneOut<R>& o,
                                      uint32_t ev, uint32_t err, uint32_t g, uint32_t bsel,
-                                     uint32_t (&evacc)[NEV]) {
+                                     uint32_t* evw) {
   const int lane = threadIdx.x & (WAVE - 1);
   const InstParams& P = C.ip[W.inst];
   const int inst = W.inst, pop = W.pop;
@@ -700,13 +710,13 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
   for (int j = 0; j < 2; ++j) {
     if (j >= o.ne) continue;
     if (pop == POP_ROULETTE) {
-      const U4 r = draw(o.e[j].id, step, CH_ROULETTE, C.seed, inst);
+      const U4 r = draw_cold(o.e[j].id, step, CH_ROULETTE, C.seed, inst);
       if ((r.x >> 9) < (1u << 22)) { keep_e |= 1u << j; ++cnt_e; }
     } else {
       keep_e |= 1u << j;
       ++cnt_e;
       if (pop == POP_SPLIT) {
-        const U4 r = draw(o.e[j].id, step, CH_CHILD | (1u << 8), C.seed, inst);
+        const U4 r = draw_cold(o.e[j].id, step, CH_CHILD | (1u << 8), C.seed, inst);
         clone_e[j] = child(r.x, r.y);
         ++cnt_e;
       }
@@ -714,13 +724,13 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
   }
   if (o.ni) {
     if (pop == POP_ROULETTE) {
-      const U4 r = draw(o.i1.id, step, CH_ROULETTE, C.seed, inst);
+      const U4 r = draw_cold(o.i1.id, step, CH_ROULETTE, C.seed, inst);
       if ((r.x >> 9) < (1u << 22)) { keep_i = 1; ++cnt_i; }
     } else {
       keep_i = 1;
       ++cnt_i;
       if (pop == POP_SPLIT) {
-        const U4 r = draw(o.i1.id, step, CH_CHILD | (1u << 8), C.seed, inst);
+        const U4 r = draw_cold(o.i1.id, step, CH_CHILD | (1u << 8), C.seed, inst);
         clone_i = child(r.x, r.y);
         ++cnt_i;
       }
@@ -756,13 +766,15 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
     constexpr int q0 = QUEUE ? EV_ELASTIC : EV_ABS_E_CATH;
     constexpr int q1 = QUEUE ? EV_ABS_E_CATH : EV_ROULETTE;
 #pragma unroll
-    for (int q = q0; q < q1; ++q) evacc[q] += (uint32_t)__popcll(__ballot((ev >> q) & 1u));
+    for (int q = q0; q < q1; ++q) {
+      const uint32_t n = (uint32_t)__popcll(__ballot((ev >> q) & 1u));
+      if (lane == 0 && n) atomicAdd(&evw[q], n);
+    }
   }
   if (pop != POP_NONE) {
     const int x = pop == POP_ROULETTE ? removed : split_added;
     const uint32_t n = (uint32_t)(__popcll(__ballot(x & 1)) + 2 * __popcll(__ballot(x & 2)));
-    evacc[EV_ROULETTE] += pop == POP_ROULETTE ? n : 0u;  // both slots written: constant indices
-    evacc[EV_SPLIT] += pop == POP_SPLIT ? n : 0u;
+    if (lane == 0 && n) atomicAdd(&evw[pop == POP_ROULETTE ? EV_ROULETTE : EV_SPLIT], n);
   }
   if (err) atomicOr(C.inst_err + inst, err);
 
@@ -855,36 +867,39 @@ __device__ void collide_electron(const Ctx<R>& C, const InstParams& P, int inst,
     const R thr = C.xs_thr[ch];
     R hx, hy, hz, ox, oy, oz;
     unit3(m.vx, m.vy, m.vz, hx, hy, hz);
-    if (kind == 0) {  // elastic, Vahedi-Surendra angle
-      const R cx = vs_cos(eps, unif<R>(r.z));
-      const R e1 = eps * (R(1) - R(2.0 * ME / MAR) * (R(1) - cx));
-      turn(hx, hy, hz, cx, unif<R>(r.w), ox, oy, oz);
-      const R sp1 = Fm<R>::sqrt(e1 * (R)(2.0 * QE / ME));
-      m.vx = sp1 * ox; m.vy = sp1 * oy; m.vz = sp1 * oz;
-      ev |= 1u << EV_ELASTIC;
-    } else if (kind == 1) {  // excitation, isotropic
-      R e1 = eps - thr;
-      e1 = e1 > R(0) ? e1 : R(0);
-      turn(hx, hy, hz, R(1) - R(2) * unif<R>(r.z), unif<R>(r.w), ox, oy, oz);
-      const R sp1 = Fm<R>::sqrt(e1 * (R)(2.0 * QE / ME));
-      m.vx = sp1 * ox; m.vy = sp1 * oy; m.vz = sp1 * oz;
-      ev |= 1u << EV_EXCIT;
-    } else {  // ionization: share eps - I, spawn e- and Ar+
-      const U4 q = draw(m.id, step, CH_IONIZ, C.seed, inst);
-      const U4 b = draw(m.id, step, CH_IONBIRTH, C.seed, inst);
-      const U4 cid = draw(m.id, step, CH_CHILD, C.seed, inst);
+    // ionization: share eps - I between the scattered and the ejected
+    // electron (only ionizing lanes draw)
+    const bool ioniz = kind == 2;
+    R eej = R(0), esc = R(0);
+    U4 q = U4{0u, 0u, 0u, 0u};
+    if (ioniz) {
+      q = draw_cold(m.id, step, CH_IONIZ, C.seed, inst);
       R eav = eps - thr;
       eav = eav > R(0) ? eav : R(0);
       const R B = (R)C.ion_B;
-      R eej = B * m_tan(unif<R>(q.x) * m_atan(eav / (R(2) * B)));
-      R esc = eav - eej;
+      eej = B * m_tan(unif<R>(q.x) * m_atan(eav / (R(2) * B)));
+      esc = eav - eej;
       if (C.flags & 1u) { eej = R(0); esc = R(0); }
-      turn(hx, hy, hz, vs_cos(esc, unif<R>(r.z)), unif<R>(r.w), ox, oy, oz);
-      const R sps = Fm<R>::sqrt(esc * (R)(2.0 * QE / ME));
+    }
+    // the primary leaves by one rotation whatever the channel: the
+    // Vahedi-Surendra angle at its energy for elastic scattering and
+    // ionization, isotropic for excitation
+    const R cx = kind == 1 ? R(1) - R(2) * unif<R>(r.z) : vs_cos(kind == 0 ? eps : esc, unif<R>(r.z));
+    R e1;
+    if (kind == 0) e1 = eps * (R(1) - R(2.0 * ME / MAR) * (R(1) - cx));
+    else if (kind == 1) e1 = eps - thr > R(0) ? eps - thr : R(0);
+    else e1 = esc;
+    turn(hx, hy, hz, cx, unif<R>(r.w), ox, oy, oz);
+    const R sp1 = Fm<R>::sqrt(e1 * (R)(2.0 * QE / ME));
+    m.vx = sp1 * ox; m.vy = sp1 * oy; m.vz = sp1 * oz;
+    ev |= 1u << (kind == 0 ? EV_ELASTIC : (kind == 1 ? EV_EXCIT : EV_IONIZ));
+    if (ioniz) {
+      // the ejected electron and the ion at the primary's position
+      const U4 b = draw_cold(m.id, step, CH_IONBIRTH, C.seed, inst);
+      const U4 cid = draw_cold(m.id, step, CH_CHILD, C.seed, inst);
       R jx, jy, jz;
       turn(hx, hy, hz, vs_cos(eej, unif<R>(q.y)), unif<R>(q.z), jx, jy, jz);
       const R spj = Fm<R>::sqrt(eej * (R)(2.0 * QE / ME));
-      m.vx = sps * ox; m.vy = sps * oy; m.vz = sps * oz;
       Mk<R> e2 = m;
       e2.vx = spj * jx; e2.vy = spj * jy; e2.vz = spj * jz;
       e2.id = child(cid.x, cid.y);
@@ -894,7 +909,6 @@ __device__ void collide_electron(const Ctx<R>& C, const InstParams& P, int inst,
       o.e[1] = e2;
       o.i1 = i2;
       o.ni = 1;
-      ev |= 1u << EV_IONIZ;
     }
   }
   o.e[0] = m;
@@ -919,7 +933,7 @@ __device__ void collide_ion(const Ctx<R>& C, const InstParams& P, int inst, uint
     hit = unif<R>(r.y) * numax < nu;
   }
   if (hit) {
-    const U4 b = draw(m.id, step, CH_CX | (1u << 8), C.seed, inst);
+    const U4 b = draw_cold(m.id, step, CH_CX | (1u << 8), C.seed, inst);
     normals3<R>(b, (R)P.vth_i, m.vx, m.vy, m.vz);
     ev |= 1u << EV_CX;
   }
@@ -932,7 +946,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
   extern __shared__ uint32_t s_prefix[];  // 2 n_inst + 1 tile offsets (dynamic)
   __shared__ unsigned long long s_hist[2][HWIN];
   __shared__ uint32_t s_gen;
-  __shared__ uint32_t s_ev[NEV];
+  __shared__ uint32_t s_evw[NWAVE][NEV];
   __shared__ double s_scan[4];
   // collision queues (rings), one per wave: candidates of the wave's
   // current (instance, species)
@@ -945,7 +959,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
     const unsigned long long ticket = atomicAdd(&C.g->wgc, 1ull);
     s_gen = (uint32_t)(ticket / (unsigned long long)C.grid);
   }
-  if (tid < NEV) s_ev[tid] = 0;
+  if (tid < NWAVE * NEV) s_evw[tid / NEV][tid % NEV] = 0u;
   for (int i = tid; i < 2 * HWIN; i += BLOCK) s_hist[i / HWIN][i % HWIN] = 0ull;
   __syncthreads();
   const uint32_t g = s_gen;
@@ -1001,9 +1015,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
   DepWin win{-1, 0};
   Work W{-1, -1, 0, 0u, POP_NONE, 0, 0u};
   uint32_t q_head = 0, q_count = 0;  // uniform over the wave
-  uint32_t evacc[NEV];                // event counts of this wave since the last flush
-#pragma unroll
-  for (int q = 0; q < NEV; ++q) evacc[q] = 0u;
+  uint32_t* evw = s_evw[wv];          // event counts of this wave since the last flush
   const unsigned long long lt = (1ull << lane) - 1ull;
 
   // collide up to WAVE queued candidates and emit the results
@@ -1031,7 +1043,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
     q_head = (q_head + n) % QW;
     q_count -= n;
     next_output(W, C.ip[W.inst]);
-    emit<R, MODE, true>(C, W, win, s_hist, o, ev, err, g, bsel, evacc);
+    emit<R, MODE, true>(C, W, win, s_hist, o, ev, err, g, bsel, evw);
   };
 
   for (uint32_t t = t_begin; t < t_end; ++t) {
@@ -1056,7 +1068,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
       if (inst != win.inst) {
         // flush the old deposit window, anchor the new one a quarter window
         // below the tile's first marker
-        if (win.inst >= 0) dep_flush(C, s_hist, win, s_ev, evacc);
+        if (win.inst >= 0) dep_flush(C, s_hist, win, s_evw);
         const uint32_t first = (j / (uint32_t)P.parts) * BLOCK;
         int c0 = first < n_in ? C.buf[bsel][sp].cell[pbase + first] : 0;
         int anchor = c0 - HWIN / 4;
@@ -1124,7 +1136,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
         if (sp == 1) {
           // ion-induced secondary emission (Sec. IV): an electron at rest at
           // the cathode with probability gamma_se
-          const U4 r = draw(m.id, step, CH_SEE, C.seed, inst);
+          const U4 r = draw_cold(m.id, step, CH_SEE, C.seed, inst);
           if ((r.x >> 9) < P.t_see) {
             ev |= 1u << EV_SEE;
             Mk<R> e;
@@ -1170,11 +1182,11 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
       q_count += (uint32_t)__popcll(bc);
     }
     next_output(W, P);
-    emit<R, MODE, false>(C, W, win, s_hist, o, ev, err, g, bsel, evacc);
+    emit<R, MODE, false>(C, W, win, s_hist, o, ev, err, g, bsel, evw);
     if (MODE == MODE_STEP && q_count >= (uint32_t)WAVE) run_queue((uint32_t)WAVE);
   }
   while (q_count > 0) run_queue(q_count < (uint32_t)WAVE ? q_count : (uint32_t)WAVE);
-  if (win.inst >= 0) dep_flush(C, s_hist, win, s_ev, evacc);
+  if (win.inst >= 0) dep_flush(C, s_hist, win, s_evw);
 }
 
 // ---------------------------------------------------------------- seeding
