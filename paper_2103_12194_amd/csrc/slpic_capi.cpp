@@ -364,6 +364,8 @@ int upload_tables(slpic_t* h, Ctx<R>& C, const slpic_xs* xs) {
   C.n_grid = ng;
   C.fixed = xs->fixed_prob ? 1 : 0;
   C.log_emin = (R)std::log(xs->energies[0]);
+  C.e_lo = (R)xs->energies[0];
+  C.e_hi = (R)xs->energies[ng - 1];
   C.inv_dlog = (R)((ng - 1) / std::log(xs->energies[ng - 1] / xs->energies[0]));
   HIPCHK(h, hipMemcpyAsync((void*)C.xs_e, e.data(), sizeof(R) * ng, hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, hipMemcpyAsync((void*)C.xs_sig, sig.data(), sizeof(R) * sig.size(), hipMemcpyHostToDevice,

@@ -116,6 +116,7 @@ struct Ctx {
   const R* xs_thr;           // [n_chan]
   const int32_t* xs_kind;    // [n_chan]
   R log_emin, inv_dlog;      // log-uniform grid index
+  R e_lo, e_hi;              // first and last node energies
   double ion_B;
   int n_chan, n_grid;
   int n_inst, total_nodes, grid, max_tiles;

@@ -330,23 +330,30 @@ __device__ __forceinline__ void unit3(R vx, R vy, R vz, R& hx, R& hy, R& hz) {
 // threshold.  Returns -1 for a null collision; cum receives the full sum.
 template <typename R>
 __device__ __forceinline__ int select_channel(const Ctx<R>& C, R eps, R scale, R target, R& cum) {
-  const int n = C.n_grid;
+  const int n = C.n_grid, nc = C.n_chan;
+  // segment [i, i+1] holding eps: the log-uniform estimate ic is off by at
+  // most one node, so the energies of nodes ic-1 .. ic+2 are loaded together
+  // and the segment is picked from them
   int i;
   R t;
-  if (!(eps > C.xs_e[0])) { i = 0; t = R(0); }
-  else if (!(eps < C.xs_e[n - 1])) { i = n - 2; t = R(1); }
+  if (!(eps > C.e_lo)) { i = 0; t = R(0); }
+  else if (!(eps < C.e_hi)) { i = n - 2; t = R(1); }
   else {
-    i = (int)((Fm<R>::log(eps) - C.log_emin) * C.inv_dlog);
-    i = i < 0 ? 0 : (i > n - 2 ? n - 2 : i);
-    if (eps < C.xs_e[i] && i > 0) --i;
-    else if (!(eps < C.xs_e[i + 1]) && i < n - 2) ++i;
-    t = Fm<R>::div(eps - C.xs_e[i], C.xs_e[i + 1] - C.xs_e[i]);
+    int ic = (int)((Fm<R>::log(eps) - C.log_emin) * C.inv_dlog);
+    ic = ic < 0 ? 0 : (ic > n - 2 ? n - 2 : ic);
+    const int im = ic > 0 ? ic - 1 : 0, ip = ic + 2 < n ? ic + 2 : n - 1;
+    const R em = C.xs_e[im], e0 = C.xs_e[ic], e1 = C.xs_e[ic + 1], ep = C.xs_e[ip];
+    R el = e0, eh = e1;
+    i = ic;
+    if (eps < e0 && ic > 0) { i = ic - 1; el = em; eh = e0; }
+    else if (!(eps < e1) && ic < n - 2) { i = ic + 1; el = e1; eh = ep; }
+    t = Fm<R>::div(eps - el, eh - el);
   }
-  const R* a = C.xs_sig + (size_t)i * C.n_chan;
-  const R* b = a + C.n_chan;
+  const R* a = C.xs_sig + (size_t)i * nc;
+  const R* b = a + nc;
   int ch = -1;
   R sum = R(0);
-  for (int k = 0; k < C.n_chan; ++k) {
+  for (int k = 0; k < nc; ++k) {
     const R v = eps < C.xs_thr[k] ? R(0) : a[k] + t * (b[k] - a[k]);
     sum += scale * v;
     if (ch < 0 && target < sum) ch = k;
@@ -1089,7 +1096,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
     const uint32_t step = W.step;
 
     Mk<R> m;
-    if (valid) {
+    if (idx < (uint32_t)P.cap_p) {  // inside the partition: no wait for n_in
       const int64_t s = pbase + idx;
       m.cell = in.cell[s];
       m.off = in.off[s];
@@ -1107,9 +1114,11 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
       if (sp == 0) { o.e[0] = m; o.ne = 1; }
       else { o.i1 = m; o.ni = 1; }
     } else if (valid) {
-      // gather at x^n and fly
+      // gather at x^n and fly; the null-collision draw does not depend on the
+      // field and overlaps the gather
       const R* E = C.E + (size_t)(g % 2u) * C.total_nodes + P.node;
       const R e0 = E[m.cell], e1 = E[m.cell + 1];
+      const U4 rn = draw(m.id, step, sp == 0 ? (uint32_t)CH_COLL : (uint32_t)CH_CX, C.seed, inst);
       const R Ep = e0 + m.off * (e1 - e0);
       const R a = (R)(sp == 0 ? P.qm_e : P.qm_i) * Ep;
       const R c = Fm<R>::sqrt(m.vy * m.vy + m.vz * m.vz);
@@ -1155,8 +1164,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
         m.off = f;
         m.vx = vx1;
         // null-collision test: candidates go to the queue
-        const U4 r = draw(m.id, step, sp == 0 ? (uint32_t)CH_COLL : (uint32_t)CH_CX, C.seed, inst);
-        const uint32_t u = r.x >> 9;
+        const uint32_t u = rn.x >> 9;
         uint32_t tcand;
         if (C.fixed) tcand = sp == 0 ? (C.n_chan > 0 ? P.t_fixed[C.n_chan - 1] : 0u) : P.t_fixed_cx;
         else tcand = sp == 0 ? P.t_null_e : (P.sigma_cx > 0.0 ? P.t_null_cx : 0u);
