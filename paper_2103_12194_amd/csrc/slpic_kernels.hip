@@ -1053,17 +1053,36 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
     emit<R, MODE, true>(C, W, win, s_hist, o, ev, err, g, bsel, evw);
   };
 
-  for (uint32_t t = t_begin; t < t_end; ++t) {
-    // (instance, species) of the tile
-    int lo = 0, hi = nk;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (s_prefix[mid] <= t) lo = mid;
-      else hi = mid;
+  // position of tile t: (instance, species) index k, tile j within it.  The
+  // cursor finds the first tile by bisection and then only moves forward.
+  int kc = -1;
+  uint32_t kbeg = 0, kend = 0;
+  auto locate = [&](uint32_t t, int& k, uint32_t& j) {
+    if (kc < 0) {
+      int lo = 0, hi = nk;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_prefix[mid] <= t) lo = mid;
+        else hi = mid;
+      }
+      kc = lo;
+      kbeg = s_prefix[kc];
+      kend = s_prefix[kc + 1];
     }
-    const int k = lo, inst = k >> 1, sp = k & 1;
+    while (t >= kend) {
+      ++kc;
+      kbeg = kend;
+      kend = s_prefix[kc + 1];
+    }
+    k = kc;
+    j = t - kbeg;
+  };
+  for (uint32_t t = t_begin; t < t_end; ++t) {
+    int k;
+    uint32_t j;
+    locate(t, k, j);
+    const int inst = k >> 1, sp = k & 1;
     const InstParams& P = C.ip[inst];
-    const uint32_t j = t - s_prefix[k];
     const int part = (int)(j % (uint32_t)P.parts);
     const uint32_t n_in = C.counts[cidx(C.n_inst, g % 3u, inst, sp, part)];
     const uint32_t idx = (j / (uint32_t)P.parts) * BLOCK + (uint32_t)tid;
