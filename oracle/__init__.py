@@ -20,6 +20,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 ELECTRON, ION = 0, 1
 FLAG_PRODUCTS_AT_REST = 1
+FLAG_SEE_ENERGY = 2
 STAT_NAMES = ["step", "n_e", "n_i", "w_e", "w_i", "w_j", "elastic",
               "excitation", "ionization", "cx", "abs_e_cathode",
               "abs_e_anode", "abs_i_cathode", "abs_i_anode", "see",
@@ -96,6 +97,8 @@ def lib():
         L.or_vs_cos_chi.argtypes = [C.c_double, C.c_double]
         L.or_ejected_energy.restype = C.c_double
         L.or_ejected_energy.argtypes = [C.c_double] * 3
+        L.or_see_yield.restype = C.c_double
+        L.or_see_yield.argtypes = [C.c_double]
         _lib = L
     return _lib
 
@@ -149,6 +152,11 @@ def vs_cos_chi(eps, u):
 
 def ejected_energy(eps_av, B, u):
     return lib().or_ejected_energy(float(eps_av), float(B), float(u))
+
+
+def see_yield(eps_ion):
+    """Secondary electrons per ion at the cathode, Eq. (17)."""
+    return lib().or_see_yield(float(eps_ion))
 
 
 def scatter(kind, v_in, eps_out, u_chi, u_phi, vs_eps):

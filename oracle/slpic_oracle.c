@@ -290,6 +290,13 @@ double or_ejected_energy(double eps_av, double B, double u) {
   return B * tan(u * atan(eps_av / (2.0 * B)));
 }
 
+/* Ion-induced secondary emission yield of Eq. (17) (Sec. IV): 0.09 at
+ * 700 eV, growing as the 0.05 power of the impact energy below and as the
+ * 0.72 power above. */
+double or_see_yield(double eps) {
+  return 0.09 * pow(eps / 700.0, eps < 700.0 ? 0.05 : 0.72);
+}
+
 /* Turn unit vector vh by polar angle chi and azimuth phi.  The azimuth is
  * measured in the frame e1 = normalize(vh x a), e2 = vh x e1, where a is the
  * coordinate axis along which |vh| has its smallest component (ties go to the
@@ -726,14 +733,24 @@ static int one_step(or_sim* s) {
   }
   for (int64_t k = 0; k < s->i.n && !rc; ++k) {
     marker m = s->i.a[k];
+    const double x0 = m.x, vx0 = m.vx, a0 = QE / MAR * gather(s, m.x);
     int w = push(s, &m, QE / MAR);
     if (w == 1) {
       /* ion-induced secondary emission at the cathode (Sec. IV): an electron
-       * at rest at x = 0 with probability gamma_se */
+       * at rest at x = 0 with probability gamma_se, or with the yield of
+       * Eq. (17) at the impact energy.  v_x^2 - 2 a x is constant along the
+       * flight (in proper time the orbit is the PIC parabola), so the ion
+       * reaches x = 0 with v_x^2 = vx0^2 - 2 a x0. */
       s->stats[OR_ST_ABS_I_CATH] += 1;
       uint32_t r[4];
       draw_raw(s, m.id, step, OR_CH_SEE, 0, r);
-      if (unif(r[0]) < s->p.gamma_se) {
+      double gam = s->p.gamma_se;
+      if (s->p.flags & OR_FLAG_SEE_ENERGY) {
+        const double vx2 = fmax(vx0 * vx0 - 2.0 * a0 * x0, 0.0);
+        gam = or_see_yield(0.5 * MAR * (vx2 + m.vy * m.vy + m.vz * m.vz) / QE);
+        note_margin(s, &m, fabs(unif(r[0]) - gam));
+      }
+      if (unif(r[0]) < gam) {
         marker ne = {0.0, 0.0, 0.0, 0.0, m.tie, child_id(r[2], r[3])};
         rc = push_back(&born_e, &ne);
         s->stats[OR_ST_SEE] += 1;

@@ -39,9 +39,11 @@ enum {
   OR_NSTAT
 };
 
-/* test flags: OR_FLAG_PRODUCTS_AT_REST leaves both electrons of an
- * ionization at rest (the closed-form Townsend test gas) */
-enum { OR_FLAG_PRODUCTS_AT_REST = 1 };
+/* flags: OR_FLAG_PRODUCTS_AT_REST leaves both electrons of an ionization at
+ * rest (the closed-form Townsend test gas); OR_FLAG_SEE_ENERGY takes the
+ * ion-induced emission probability from the ion's impact energy by Eq. (17)
+ * (Sec. IV) instead of the constant gamma_se */
+enum { OR_FLAG_PRODUCTS_AT_REST = 1, OR_FLAG_SEE_ENERGY = 2 };
 
 /* error bits */
 enum { OR_ERR_NU_BOUND = 1, OR_ERR_NONFINITE = 2, OR_ERR_ALLOC = 4 };
@@ -118,6 +120,8 @@ void or_scatter(int kind, const double v_in[3], double eps_out_eV,
                 double u_chi, double u_phi, double vs_eps_eV, double v_out[3]);
 double or_vs_cos_chi(double eps_eV, double u);
 double or_ejected_energy(double eps_avail_eV, double B_eV, double u);
+/* Eq. (17): secondary electrons per ion hitting the cathode with energy eps */
+double or_see_yield(double eps_ion_eV);
 
 #ifdef __cplusplus
 }

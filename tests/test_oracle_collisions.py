@@ -321,6 +321,44 @@ def test_secondary_emission_probability():
     assert np.all(e["vx"] == 0) and np.all(e["id"] >> np.uint64(63) == 1)
 
 
+def test_energy_dependent_secondary_emission_follows_eq17():
+    # Ions released at rest at height x0 in the vacuum field reach the cathode
+    # with e E x0 (plus any perpendicular energy they carry): the fraction
+    # that emits must follow Eq. (17) at that energy, within binomial error,
+    # and be told apart from the constant gamma_se = 0.09 path.
+    xs = xsec.fixed_event([0.0, 0.0, 0.0])
+    V, cells, n = 1000.0, 16, 60000
+    inst = _gap(V=V, cells=cells, gamma=0.09)
+    inst.capacity = 4 * n
+    dx = inst.d / cells
+    v_perp_2k = math.sqrt(2 * QE * 2000.0 / M_AR)
+    for cell, off, vperp, extra in ((0, 0.8, 0.0, 0.0), (14, 0.4, 0.0, 0.0),
+                                    (0, 0.8, v_perp_2k, 2000.0)):
+        sim = oracle.Sim(inst, configs.Run(precision=64, area=1e30), xs,
+                         flags=oracle.FLAG_SEE_ENERGY)
+        ions = {"cell": np.full(n, cell, np.int32), "off": np.full(n, off),
+                "vx": np.zeros(n), "vy": np.full(n, vperp), "vz": np.zeros(n),
+                "id": np.arange(n, dtype=np.uint64) + np.uint64(1 << 40)}
+        sim.load(oracle.ION, ions)
+        hits = see = 0
+        for _ in range(400):
+            sim.step(1)
+            st = sim.stats()
+            hits += st["abs_i_cathode"]
+            see += st["see"]
+            if sim.count(oracle.ION) == 0:
+                break
+        assert hits == n
+        eps = V * (cell + off) * dx / inst.d + extra
+        g = oracle.see_yield(eps)
+        sd = math.sqrt(g * (1 - g) / n)
+        assert abs(see / n - g) < 4 * sd, (eps, see / n, g, sd)
+        assert abs(g - 0.09) > 6 * sd, eps   # the constant yield is rejected
+    # the two branches of Eq. (17) meet at 700 eV
+    assert oracle.see_yield(700.0) == pytest.approx(0.09, rel=1e-15)
+    assert oracle.see_yield(700.0 * (1 - 1e-12)) == pytest.approx(0.09, rel=1e-12)
+
+
 def test_seeded_maxwellian_first_cell(xs_argon):
     inst = _gap(seed_mode=configs.SEED_MAXWELL_CELL0, n_seed=20000)
     sim = oracle.Sim(inst, configs.Run(kTe_seed_eV=1.0), xs_argon)
