@@ -55,8 +55,13 @@ enum { SLPIC_ELASTIC = 0, SLPIC_EXCITATION = 1, SLPIC_IONIZATION = 2 };
 enum { SLPIC_SEED_NONE = 0, SLPIC_SEED_CATHODE = 1, SLPIC_SEED_MAXWELL_CELL0 = 2 };
 enum { SLPIC_ELECTRON = 0, SLPIC_ION = 1 };
 /* SLPIC_FLAG_PRODUCTS_AT_REST: both electrons of an ionization leave at rest
- * (a closed-form Townsend test gas, not physical argon) */
-enum { SLPIC_FLAG_PRODUCTS_AT_REST = 1 };
+ * (a closed-form Townsend test gas, not physical argon).
+ * SLPIC_FLAG_SEE_ENERGY: an ion reaching the cathode emits an electron with
+ * the probability of Eq. (17) (Sec. IV) at its impact energy,
+ * 0.09 (eps/700 eV)^0.05 below 700 eV and 0.09 (eps/700 eV)^0.72 above,
+ * instead of the constant gamma_se; at most one electron per ion (the yield
+ * stays below 1 up to about 20 keV). */
+enum { SLPIC_FLAG_PRODUCTS_AT_REST = 1, SLPIC_FLAG_SEE_ENERGY = 2 };
 
 /* Settings shared by all instances of a handle. */
 typedef struct slpic_config {

@@ -18,6 +18,7 @@ ELECTRON, ION = 0, 1
 ELASTIC, EXCITATION, IONIZATION = 0, 1, 2
 SEED_NONE, SEED_CATHODE, SEED_MAXWELL_CELL0 = 0, 1, 2
 FLAG_PRODUCTS_AT_REST = 1
+FLAG_SEE_ENERGY = 2
 
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "WORKSPACE_TOO_SMALL",
           -3: "CAPACITY_EXCEEDED", -4: "NONFINITE_STATE", -5: "HIP_ERROR",

@@ -140,6 +140,8 @@ std::string validate(const slpic_config* cfg, const slpic_instance* inst, int n_
   if (!(cfg->cfl > 0 && cfg->cfl <= 1)) return "cfl must be in (0, 1]";
   if (!(cfg->ion_B_eV > 0)) return "ion_B_eV must be > 0";
   if (cfg->resort_period < 0) return "resort_period must be >= 0";
+  if (cfg->flags & ~(uint32_t)(SLPIC_FLAG_PRODUCTS_AT_REST | SLPIC_FLAG_SEE_ENERGY))
+    return "unknown flags";
   if (xs->n_chan < 0 || xs->n_chan > MAX_CHAN) return "n_chan must be in 0..8";
   if (xs->n_grid < 2 || !xs->energies) return "n_grid must be >= 2";
   if (xs->n_chan > 0 && (!xs->sigma || !xs->threshold_eV || !xs->kind)) return "missing tables";

@@ -54,6 +54,7 @@ template <> struct Fm<double> {
   static __device__ __forceinline__ double log(double x) { return ::log(x); }
   static __device__ __forceinline__ double log1p(double x) { return ::log1p(x); }
   static __device__ __forceinline__ double expm1(double x) { return ::expm1(x); }
+  static __device__ __forceinline__ double pow(double x, double y) { return ::pow(x, y); }
   // sin and cos of 2 pi u
   static __device__ __forceinline__ void sincos2pi(double u, double* s, double* c) {
     ::sincospi(2.0 * u, s, c);
@@ -83,6 +84,10 @@ template <> struct Fm<float> {
     if (y < 0.03125f)
       return y * (1.0f + y * 0.5f * (1.0f + y * 0.33333334f * (1.0f + y * 0.25f * (1.0f + y * 0.2f))));
     return __builtin_amdgcn_exp2f(y * 1.44269504f) - 1.0f;
+  }
+  // x^y = 2^(y log2 x) for x > 0 (relative error ~1e-7 for |y log2 x| < 10)
+  static __device__ __forceinline__ float pow(float x, float y) {
+    return __builtin_amdgcn_exp2f(y * __builtin_amdgcn_logf(x));
   }
   static __device__ __forceinline__ void sincos2pi(float u, float* s, float* c) {
     *s = __builtin_amdgcn_sinf(u);
@@ -276,6 +281,13 @@ __device__ void flight(R vx, R c, R a, R dt, R v0, int limited, R& disp, R& vx1,
   vx1 = vx + dv;
   turns = (vx * dv < R(0)) && ((vx < R(0) ? -vx : vx) < (dv < R(0) ? -dv : dv));
   turn_disp = turns ? Fm<R>::div(-vx * vx, R(2) * a) : R(0);
+}
+
+// secondary electrons per ion reaching the cathode with energy eps [eV],
+// Eq. (17) (Sec. IV)
+template <typename R>
+__device__ __forceinline__ R see_yield(R eps) {
+  return R(0.09) * Fm<R>::pow(eps * R(1.0 / 700.0), eps < R(700) ? R(0.05) : R(0.72));
 }
 
 // beta of Eq. (11) as min(1, v0/|v|) (deposit weights)
@@ -1163,9 +1175,21 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
         ev |= 1u << (sp == 0 ? EV_ABS_E_CATH : EV_ABS_I_CATH);
         if (sp == 1) {
           // ion-induced secondary emission (Sec. IV): an electron at rest at
-          // the cathode with probability gamma_se
+          // the cathode with probability gamma_se, or with the yield of
+          // Eq. (17) at the impact energy; v_x^2 - 2 a x is constant along
+          // the flight, so the ion reaches x = 0 with v_x^2 = vx^2 - 2 a x
           const U4 r = draw_cold(m.id, step, CH_SEE, C.seed, inst);
-          if ((r.x >> 9) < P.t_see) {
+          bool see;
+          if (C.flags & 2u) {
+            const R x0 = ((R)m.cell + m.off) * (R)P.dx;
+            R vx2 = m.vx * m.vx - R(2) * a * x0;
+            vx2 = vx2 > R(0) ? vx2 : R(0);
+            const R eps = R(0.5 * MAR / QE) * (vx2 + m.vy * m.vy + m.vz * m.vz);
+            see = unif<R>(r.x) < see_yield<R>(eps);
+          } else {
+            see = (r.x >> 9) < P.t_see;
+          }
+          if (see) {
             ev |= 1u << EV_SEE;
             Mk<R> e;
             e.cell = 0;

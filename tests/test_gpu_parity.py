@@ -55,23 +55,32 @@ def test_fp64_seeding_and_initial_field(xs_argon):
         assert sg[k] == pytest.approx(so[k], rel=1e-15), k
 
 
-@pytest.mark.parametrize("steps", [60])
-def test_fp64_full_physics_matches_oracle_step_by_step(xs_argon, steps):
+@pytest.mark.parametrize("flags", [0, slpic.FLAG_SEE_ENERGY])
+def test_fp64_full_physics_matches_oracle_step_by_step(xs_argon, flags, steps=60):
+    """60 steps of full physics (flags: constant gamma_se, or Eq. (17))."""
     inst = _c1_small()
     run = configs.Run(precision=64)
-    gpu = slpic.Sim([inst], run, xs_argon)
-    ref = oracle.Sim(inst, run, xs_argon)
+    gpu = slpic.Sim([inst], run, xs_argon, flags=flags)
+    ref = oracle.Sim(inst, run, xs_argon, flags=flags)
+    # ions near the cathode, some faster than the 700 eV knee of Eq. (17),
+    # so that emission happens within the run
+    ions = synth.markers.ions(11, 3000, inst.cells, cell_hi=8, e_beam_hi=1500.0)
+    gpu.load(1, ions)
+    ref.load(1, ions)
     v0 = gpu.scalars()["v0"]
+    see = 0
     for n in range(steps):
         gpu.step(1)
         ref.step(1)
         sg, so = gpu.stats(), ref.stats()
+        see += so["see"]
         for k in STAT_INT:
             assert sg[k] == so[k], (n, k, sg[k], so[k])
         assert sg["w_j"] == so["w_j"]
         assert sg["w_e"] == pytest.approx(so["w_e"], rel=1e-9)
         assert sg["w_i"] == pytest.approx(so["w_i"], rel=1e-9, abs=1e-9)
     assert gpu.sync() == 0
+    assert see > 0, "no secondary emission in the run"
     for sp in (0, 1):
         w = compare_populations(gpu.read(sp), ref.read(sp), 1e-12 * inst.cells,
                                 1e-12, v0, label=f"species {sp}")
@@ -80,15 +89,16 @@ def test_fp64_full_physics_matches_oracle_step_by_step(xs_argon, steps):
     assert np.allclose(E_g, E_o, rtol=1e-11)
 
 
-def test_fp32_single_step_from_loaded_state(xs_argon):
+@pytest.mark.parametrize("flags", [0, slpic.FLAG_SEE_ENERGY])
+def test_fp32_single_step_from_loaded_state(xs_argon, flags):
     cells = 64
     inst = configs.Instance(d=0.01, p_torr=3.0, V=300.0, cells=cells,
                             gamma_se=0.3, seed_mode=configs.SEED_NONE,
                             capacity=40000)
     e, i = synth.markers.mixed(7, 9000, 4100, cells)
     run32, run64 = configs.Run(precision=32), configs.Run(precision=64)
-    gpu = slpic.Sim([inst], run32, xs_argon)
-    ref = oracle.Sim(inst, run64, xs_argon)
+    gpu = slpic.Sim([inst], run32, xs_argon, flags=flags)
+    ref = oracle.Sim(inst, run64, xs_argon, flags=flags)
     for sim in (gpu, ref):
         sim.load(0, e)
         sim.load(1, i)
@@ -101,6 +111,7 @@ def test_fp32_single_step_from_loaded_state(xs_argon):
                                 v0, tie_tol=1e-4, label=f"species {sp}")
         print("fp32 single step", sp, w)
     sg, so = gpu.stats(), ref.stats()
+    assert so["see"] > 0
     for k in STAT_INT:
         assert abs(sg[k] - so[k]) <= 3, (k, sg[k], so[k])
 
