@@ -129,6 +129,44 @@ def argon_like(n=N_GRID, sigma_cx=SIGMA_CX):
     )
 
 
+# three excitation channels in the place of the lumped one (the paper's
+# argon set has five channels: elastic, three excitations, ionization);
+# synthetic thresholds near argon's 4s, 4p and higher manifolds, with peaks
+# summing to the lumped excitation's
+EX3_THRESHOLDS_EV = (11.55, 13.0, 14.1)
+EX3_PEAK_SHARES = (0.45, 0.35, 0.20)
+
+
+def _excitation_shape_at(e, threshold):
+    x = e / threshold
+    out = np.zeros_like(e)
+    m = x > 1.0
+    out[m] = (1.0 - 1.0 / x[m]) * np.log(x[m]) / x[m]
+    return out
+
+
+def argon_five(n=N_GRID, sigma_cx=SIGMA_CX):
+    """Five-channel synthetic argon: elastic, three excitations, ionization."""
+    e = log_grid(n)
+    shapes = [_elastic_shape(e)]
+    peaks = [PEAK_EL]
+    for thr, share in zip(EX3_THRESHOLDS_EV, EX3_PEAK_SHARES):
+        shapes.append(_excitation_shape_at(e, thr))
+        peaks.append(PEAK_EX * share)
+    shapes.append(_ionization_shape(e))
+    peaks.append(PEAK_IZ)
+    sig = np.stack([s * (p / s.max()) for s, p in zip(shapes, peaks)])
+    return CrossSections(
+        energies=e,
+        sigma=sig,
+        threshold_eV=np.array([0.0, *EX3_THRESHOLDS_EV, I_IZ_EV]),
+        kind=np.array([ELASTIC, EXCITATION, EXCITATION, EXCITATION, IONIZATION],
+                      dtype=np.int32),
+        sigma_cx=float(sigma_cx),
+        meta={"name": "argon_five", "peaks_m2": peaks},
+    )
+
+
 def constant(sig_by_kind, thresholds, n=N_GRID, sigma_cx=0.0):
     """Energy-independent channels (closed-form test gases).
 

@@ -158,6 +158,36 @@ def test_fixed_event_channel_frequencies():
     assert st["n_i"] == n + st["ionization"]
 
 
+def test_five_channel_gas_picks_each_excitation_by_its_cross_section():
+    # A 20 eV beam in a field-free gap collides once per step with
+    # probability P_null; channel k is taken with probability
+    # P_null n_g sigma_k(eps) min(v, v0) / nu'_max.  The three excitations
+    # are told apart by the energy they leave (20 eV minus the threshold);
+    # sigma_k(20 eV) comes from the tables by linear interpolation in energy.
+    xs = synth.argon_five()
+    n, eps = 200000, 20.0
+    v = math.sqrt(2 * QE * eps / ME)
+    inst = _gap(V=0.0, v_limit=1e4)
+    inst.capacity = 3 * n
+    sim = oracle.Sim(inst, configs.Run(precision=64, area=1e30), xs)
+    sim.load(oracle.ELECTRON, _beam(n, v, 64, 30))
+    sim.step(1)
+    sc = sim.scalars()
+    p_null = -math.expm1(-sc["nu_max_e"] * sc["dt"])
+    scale = p_null * sc["n_g"] * min(v, sc["v0"]) / sc["nu_max_e"]
+    sig = [np.interp(eps, xs.energies, xs.sigma[k]) for k in range(5)]
+    out = sim.read(oracle.ELECTRON)
+    e_out = 0.5 * ME * (out["vx"] ** 2 + out["vy"] ** 2 + out["vz"] ** 2) / QE
+    for k in (1, 2, 3):
+        want = n * scale * sig[k]
+        got = np.count_nonzero(np.abs(e_out - (eps - xs.threshold_eV[k])) < 1e-9)
+        assert abs(got - want) < 4 * math.sqrt(want), (k, got, want)
+    st = sim.stats()
+    for key, ks in (("elastic", [0]), ("excitation", [1, 2, 3]), ("ionization", [4])):
+        want = n * scale * sum(sig[k] for k in ks)
+        assert abs(st[key] - want) < 4 * math.sqrt(want), (key, st[key], want)
+
+
 def _surviving_beam_fraction(v_limit, steps, speed=1e6, sigma=4e-20,
                              pic_cfl=0.02):
     xs = xsec.constant([(xsec.ELASTIC, sigma)], [0.0])
