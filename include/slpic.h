@@ -35,6 +35,7 @@ extern "C" {
 #endif
 
 #define SLPIC_ABI_VERSION 1
+#define SLPIC_MAX_PARTITIONS 16
 
 typedef enum slpic_status {
   SLPIC_OK = 0,
@@ -69,7 +70,9 @@ typedef struct slpic_config {
                             64: FP64 throughout */
   uint32_t seed;         /* Philox key word 0 (word 1 = instance index) */
   uint32_t flags;        /* SLPIC_FLAG_* */
-  int32_t resort_period; /* steps between cell sorts of the markers, 0 = off */
+  int32_t resort_period; /* cell sort of the markers before every step whose
+                            count of completed steps is a multiple of it
+                            (step 0 included); 0 = off (see slpic_sort) */
   double T_gas;          /* neutral temperature [K], > 0 */
   double area;           /* electrode area [m^2], > 0 */
   double w_j0;           /* initial flux weight w_j of every marker, > 0 */
@@ -151,6 +154,15 @@ int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst
  * without waiting.  Errors raised on the device are reported by slpic_sync. */
 int slpic_step(slpic_t* h, int n_steps);
 
+/* Sort the markers of every instance and species by cell now (enqueued on the
+ * handle's stream, returns without waiting).  Partition p of an (instance,
+ * species) with n markers then holds the p-th run of ceil(n / partitions)
+ * markers in cell order; within a cell the order is unspecified.  Results of
+ * later steps do not depend on marker order.  SLPIC_INVALID_ARG if the
+ * device's shared memory per block cannot hold the sort's per-cell tables
+ * (about 8 bytes per cell of the largest instance). */
+int slpic_sort(slpic_t* h);
+
 /* Wait for the stream; return the first device error raised since the last
  * call (SLPIC_CAPACITY_EXCEEDED, SLPIC_NONFINITE_STATE,
  * SLPIC_NU_BOUND_EXCEEDED) or SLPIC_OK. */
@@ -199,9 +211,10 @@ int slpic_load_markers(slpic_t* h, int inst, int species, int64_t n,
 int slpic_count(slpic_t* h, int inst, int species, int64_t* n);
 
 /* Storage diagnostics: markers of one species of one instance are kept in
- * *parts output partitions of *cap_p slots each (the capacity split for
- * spreading compaction counters); counts (host, 16 entries) receives each
- * partition's occupancy, zero past *parts.  Synchronizes. */
+ * *parts (at most SLPIC_MAX_PARTITIONS) output partitions of *cap_p slots
+ * each (the capacity split for spreading compaction counters); counts (host,
+ * SLPIC_MAX_PARTITIONS entries) receives each partition's occupancy, zero
+ * past *parts.  Synchronizes. */
 int slpic_partitions(slpic_t* h, int inst, int species, int32_t* parts, int64_t* cap_p,
                      uint32_t* counts);
 

@@ -19,6 +19,7 @@ ELASTIC, EXCITATION, IONIZATION = 0, 1, 2
 SEED_NONE, SEED_CATHODE, SEED_MAXWELL_CELL0 = 0, 1, 2
 FLAG_PRODUCTS_AT_REST = 1
 FLAG_SEE_ENERGY = 2
+MAX_PARTITIONS = 16   # SLPIC_MAX_PARTITIONS
 
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "WORKSPACE_TOO_SMALL",
           -3: "CAPACITY_EXCEEDED", -4: "NONFINITE_STATE", -5: "HIP_ERROR",
@@ -75,7 +76,7 @@ EXPORTS = ["slpic_workspace_bytes", "slpic_create", "slpic_step", "slpic_sync",
            "slpic_scalars", "slpic_steps_done", "slpic_last_error",
            "slpic_destroy", "slpic_philox_device", "slpic_profile",
            "slpic_kernel_times", "slpic_partitions", "slpic_autotune",
-           "slpic_grid"]
+           "slpic_grid", "slpic_sort"]
 
 
 def lib():
@@ -107,6 +108,7 @@ def lib():
         L.slpic_destroy.argtypes = [vp]
         L.slpic_profile.argtypes = [vp, i32]
         L.slpic_autotune.argtypes = [vp, i32, P(i32)]
+        L.slpic_sort.argtypes = [vp]
         L.slpic_grid.argtypes = [vp, P(i32)]
         L.slpic_partitions.argtypes = [vp, i32, i32, P(C.c_int32), P(i64), vp]
         L.slpic_kernel_times.argtypes = [vp, P(C.c_double), P(C.c_double), P(i64)]
@@ -234,6 +236,10 @@ class Sim:
         _check(lib().slpic_autotune(self.h, int(trial_steps), C.byref(g)), self.h)
         return int(g.value)
 
+    def sort(self):
+        """Sort every instance's markers by cell (enqueued)."""
+        _check(lib().slpic_sort(self.h), self.h)
+
     def grid(self):
         g = C.c_int()
         _check(lib().slpic_grid(self.h, C.byref(g)), self.h)
@@ -271,7 +277,7 @@ class Sim:
     def partitions(self, species, inst=0):
         """(occupancy of each output partition, slots per partition)."""
         parts, cap = C.c_int32(), C.c_int64()
-        out = np.zeros(16, np.uint32)
+        out = np.zeros(MAX_PARTITIONS, np.uint32)
         _check(lib().slpic_partitions(self.h, inst, species, C.byref(parts),
                                       C.byref(cap), _p(out)), self.h)
         return out[:parts.value].copy(), int(cap.value)

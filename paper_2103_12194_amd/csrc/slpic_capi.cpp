@@ -23,6 +23,12 @@ template <typename R> hipError_t occupancy_gen(int*, size_t);
 // dynamic LDS of the particle kernel: tile offsets of the (instance,
 // species) pairs
 inline size_t gen_lds_bytes(int n_inst) { return ((size_t)(2 * n_inst + 1) * 4 + 15) & ~size_t(15); }
+// dynamic LDS of the cell sort's count (arrays = 1) and scatter (2) kernels:
+// the tile offsets, then arrays of max_cells words
+inline size_t sort_lds_bytes(int n_inst, int max_cells, int arrays) {
+  return ((size_t)(2 * n_inst + 1 + 3) & ~size_t(3)) * 4 + (size_t)arrays * max_cells * 4;
+}
+template <typename R> hipError_t launch_sort(const Ctx<R>&, hipStream_t);
 hipError_t launch_philox_test(const uint32_t*, uint32_t, uint32_t, int64_t, uint32_t*,
                               hipStream_t);
 }  // namespace slpic
@@ -53,7 +59,7 @@ uint32_t prob_threshold(double P) {
 }
 
 struct Layout {
-  size_t ip, st, counts, ev, acc, E, E64, phi, rho, scratch, ring, inst_err,
+  size_t ip, st, counts, ev, acc, E, E64, phi, rho, scratch, ring, inst_err, sort_hist, sort_cur,
       glob, xs_e, xs_sig, xs_thr, xs_kind;
   size_t part[2][2][6];  // [buffer][species][array]
   size_t total;
@@ -69,6 +75,8 @@ struct Layout {
 // the random spread of emits over partitions stays small against a
 // partition's capacity.  Each partition gets an equal share of the capacity
 // plus one tile of slack.
+static_assert(MAX_PART == SLPIC_MAX_PARTITIONS, "partition cap of the public header");
+
 int partitions_for(int64_t cap) {
   int p = 1;
   while (p < MAX_PART && (int64_t)p * 2 * 32 * BLOCK <= cap) p *= 2;
@@ -107,7 +115,7 @@ bool make_layout(const slpic_config* cfg, const slpic_instance* inst, int n_inst
   };
   L.ip = take(sizeof(InstParams) * n_inst);
   L.st = take(sizeof(InstState) * 2 * n_inst);
-  L.counts = take(sizeof(uint32_t) * 3 * 2 * MAX_PART * (size_t)n_inst);
+  L.counts = take(sizeof(uint32_t) * CSTRIDE * 3 * 2 * MAX_PART * (size_t)n_inst);
   L.ev = take(sizeof(unsigned long long) * NEV * NSLOT * (size_t)n_inst);
   L.acc = take(sizeof(unsigned long long) * 2 * NSLOT * (size_t)nodes);
   L.E = take(rs * 2 * nodes);
@@ -117,6 +125,8 @@ bool make_layout(const slpic_config* cfg, const slpic_instance* inst, int n_inst
   L.scratch = take(8 * (size_t)nodes);
   L.ring = take(sizeof(StatsRow) * RING * (size_t)n_inst);
   L.inst_err = take(sizeof(uint32_t) * n_inst);
+  L.sort_hist = take(sizeof(uint32_t) * 2 * (size_t)nodes);
+  L.sort_cur = take(sizeof(uint32_t) * 2 * (size_t)nodes);
   L.glob = take(sizeof(Global));
   const int ng = xs->n_grid, nc = std::max(xs->n_chan, 1);
   L.xs_e = take(rs * ng);
@@ -270,6 +280,8 @@ struct slpic_handle {
   bool use_graph = false;
   int graph_period = 16;
   hipGraphExec_t graph = nullptr;
+  int graph_phase = 0;   // steps mod resort_period when the graph was captured
+  int lds_max = 0;       // shared memory per block of the device
   // kernel timing: events before the particle kernel, between the two
   // kernels and after the tail kernel of each profiled step, in two pools
   // so that one can be read back while the other fills
@@ -324,6 +336,8 @@ void fill_ctx(slpic_t* h, Ctx<R>& C) {
   C.scratch = reinterpret_cast<double*>(w + L.scratch);
   C.ring = reinterpret_cast<StatsRow*>(w + L.ring);
   C.inst_err = reinterpret_cast<uint32_t*>(w + L.inst_err);
+  C.sort_hist = reinterpret_cast<uint32_t*>(w + L.sort_hist);
+  C.sort_cur = reinterpret_cast<uint32_t*>(w + L.sort_cur);
   C.g = reinterpret_cast<Global*>(w + L.glob);
   C.xs_e = reinterpret_cast<const R*>(w + L.xs_e);
   C.xs_sig = reinterpret_cast<const R*>(w + L.xs_sig);
@@ -348,6 +362,9 @@ void fill_ctx(slpic_t* h, Ctx<R>& C) {
   for (auto& I : h->inst) maxc = std::max(maxc, I.cells);
   C.tail_lds = (maxc + 1) * (int)sizeof(double);
   C.gen_lds = (int)gen_lds_bytes(h->n_inst);
+  C.max_cells = maxc;
+  C.sort_lds1 = (int)sort_lds_bytes(h->n_inst, maxc, 1);
+  C.sort_lds2 = (int)sort_lds_bytes(h->n_inst, maxc, 2);
 }
 
 template <typename R>
@@ -432,7 +449,26 @@ int launch_timed(slpic_t* h, int mode) {
   return SLPIC_OK;
 }
 
+// a cell sort runs before every step whose number of completed steps is a
+// multiple of resort_period (the seeded state included)
+bool sort_due(const slpic_t* h, int64_t steps_done) {
+  return h->cfg.resort_period > 0 && steps_done % h->cfg.resort_period == 0;
+}
+
+int sort_phase(const slpic_t* h) {
+  return h->cfg.resort_period > 0 ? (int)(h->steps % h->cfg.resort_period) : 0;
+}
+
+hipError_t launch_sort_any(slpic_t* h) {
+  return h->cfg.precision == 64 ? launch_sort<double>(h->c64, h->stream)
+                                : launch_sort<float>(h->c32, h->stream);
+}
+
 int launch_gen_any(slpic_t* h, int mode) {
+  if (mode == MODE_STEP && sort_due(h, h->steps)) {
+    hipError_t e = launch_sort_any(h);
+    if (e != hipSuccess) return hip_fail(h, e, "cell sort launch");
+  }
   if (h->profiling && mode == MODE_STEP) {
     int rc = launch_timed(h, mode);
     if (rc) return rc;
@@ -482,7 +518,7 @@ template <>
 Soa<double> buffer_of<double>(slpic_t* h, uint32_t bsel, int sp) { return h->c64.buf[bsel][sp]; }
 
 size_t count_offset(slpic_t* h, uint32_t slot3, int inst, int sp, int p) {
-  return h->L.counts + sizeof(uint32_t) * ((((size_t)slot3 * h->n_inst + inst) * 2 + sp) * MAX_PART + p);
+  return h->L.counts + sizeof(uint32_t) * CSTRIDE * ((((size_t)slot3 * h->n_inst + inst) * 2 + sp) * MAX_PART + p);
 }
 
 // Markers are spread over the instance's P partitions: marker k of a loaded
@@ -536,10 +572,10 @@ int load_impl(slpic_t* h, int inst, int sp, int64_t n, const int32_t* cell, cons
 }
 
 int part_counts(slpic_t* h, uint32_t slot3, int inst, int sp, std::vector<uint32_t>& c) {
-  c.assign(MAX_PART, 0u);
-  HIPCHK(h, hipMemcpy(c.data(), h->ws + count_offset(h, slot3, inst, sp, 0), sizeof(uint32_t) * MAX_PART,
-                      hipMemcpyDeviceToHost));
-  c.resize(h->ip[inst].parts);
+  const int P = h->ip[inst].parts;
+  c.assign(P, 0u);
+  HIPCHK(h, hipMemcpy2D(c.data(), sizeof(uint32_t), h->ws + count_offset(h, slot3, inst, sp, 0),
+                        sizeof(uint32_t) * CSTRIDE, sizeof(uint32_t), P, hipMemcpyDeviceToHost));
   return SLPIC_OK;
 }
 
@@ -644,6 +680,13 @@ int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst
     delete h;
     return fail(nullptr, SLPIC_INVALID_ARG, "too many cells for the device's shared memory per block");
   }
+  h->lds_max = lds_max;
+  if (cfg->resort_period > 0 && sort_lds_bytes(n_inst, maxc, 2) + 64 > (size_t)lds_max) {
+    delete h;
+    return fail(nullptr, SLPIC_INVALID_ARG,
+                "the cell sort needs more shared memory per block than the device has "
+                "(fewer cells, or resort_period 0)");
+  }
   fill_ctx(h, h->c32);
   fill_ctx(h, h->c64);
   int rc = cfg->precision == 64 ? upload_tables(h, h->c64, xs) : upload_tables(h, h->c32, xs);
@@ -655,14 +698,14 @@ int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst
   const Layout& L = h->L;
   // constant and initial state: generation 0, buffer 0, seeds in counts[0]
   std::vector<InstState> st(2 * n_inst);
-  std::vector<uint32_t> counts(3 * 2 * MAX_PART * (size_t)n_inst, 0u);
+  std::vector<uint32_t> counts((size_t)CSTRIDE * 3 * 2 * MAX_PART * n_inst, 0u);
   for (int i = 0; i < n_inst; ++i) {
     st[i] = InstState{cfg->w_j0, 0u, POP_NONE};
     st[n_inst + i] = st[i];
     const int64_t ns = inst[i].seed_mode != SLPIC_SEED_NONE ? inst[i].n_seed : 0;
     const int P = L.parts[i];
     for (int p = 0; p < P; ++p)  // seed k sits in partition k mod P
-      counts[(size_t)i * 2 * MAX_PART + p] = (uint32_t)(ns / P + (p < ns % P ? 1 : 0));
+      counts[((size_t)i * 2 * MAX_PART + p) * CSTRIDE] = (uint32_t)(ns / P + (p < ns % P ? 1 : 0));
   }
   Global G;
   std::memset(&G, 0, sizeof(G));
@@ -675,6 +718,7 @@ int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst
   if (e == hipSuccess) e = up(L.glob, &G, sizeof(G));
   if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.ev, 0, sizeof(unsigned long long) * NEV * NSLOT * n_inst, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.acc, 0, sizeof(unsigned long long) * 2 * NSLOT * L.total_nodes, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.sort_hist, 0, sizeof(uint32_t) * 2 * L.total_nodes, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.inst_err, 0, sizeof(uint32_t) * n_inst, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.ring, 0, sizeof(StatsRow) * RING * n_inst, h->stream);
   for (int i = 0; i < n_inst && e == hipSuccess; ++i) {
@@ -712,32 +756,38 @@ int slpic_use_graph(slpic_t* h, int enable) {
 int slpic_step(slpic_t* h, int n_steps) {
   if (!h || n_steps < 0) return fail(h, SLPIC_INVALID_ARG, "bad step arguments");
   int done = 0;
-  if (h->use_graph && !h->profiling && n_steps >= h->graph_period) {
-    if (!h->graph) {
-      hipGraph_t gr;
-      HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-      for (int k = 0; k < h->graph_period; ++k) {
-        hipError_t e = launch_pair_any(h, MODE_STEP);
-        if (e != hipSuccess) {
-          (void)hipStreamEndCapture(h->stream, &gr);
-          return hip_fail(h, e, "graph capture");
+  while (done < n_steps) {
+    // graph replay needs a whole period and, with cell sorts, the same
+    // position in the sort cycle as at capture (the sorts are in the graph)
+    const bool graph = h->use_graph && !h->profiling && n_steps - done >= h->graph_period &&
+                       (!h->graph || h->graph_phase == sort_phase(h));
+    if (graph) {
+      if (!h->graph) {
+        hipGraph_t gr;
+        HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < h->graph_period; ++k) {
+          hipError_t e = sort_due(h, h->steps + k) ? launch_sort_any(h) : hipSuccess;
+          if (e == hipSuccess) e = launch_pair_any(h, MODE_STEP);
+          if (e != hipSuccess) {
+            (void)hipStreamEndCapture(h->stream, &gr);
+            return hip_fail(h, e, "graph capture");
+          }
         }
+        HIPCHK(h, hipStreamEndCapture(h->stream, &gr));
+        HIPCHK(h, hipGraphInstantiate(&h->graph, gr, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(gr);
+        h->graph_phase = sort_phase(h);
       }
-      HIPCHK(h, hipStreamEndCapture(h->stream, &gr));
-      HIPCHK(h, hipGraphInstantiate(&h->graph, gr, nullptr, nullptr, 0));
-      (void)hipGraphDestroy(gr);
-    }
-    while (n_steps - done >= h->graph_period) {
       HIPCHK(h, hipGraphLaunch(h->graph, h->stream));
       h->gen += h->graph_period;
       h->steps += h->graph_period;
       done += h->graph_period;
+    } else {
+      int rc = launch_gen_any(h, MODE_STEP);
+      if (rc) return rc;
+      h->steps += 1;
+      done += 1;
     }
-  }
-  for (; done < n_steps; ++done) {
-    int rc = launch_gen_any(h, MODE_STEP);
-    if (rc) return rc;
-    h->steps += 1;
   }
   return SLPIC_OK;
 }
@@ -843,6 +893,16 @@ int slpic_kernel_times(slpic_t* h, double* gen_ms, double* tail_ms, int64_t* ste
   *gen_ms = h->t_gen_ms;
   *tail_ms = h->t_tail_ms;
   *steps = h->t_steps;
+  return SLPIC_OK;
+}
+
+int slpic_sort(slpic_t* h) {
+  if (!h) return SLPIC_INVALID_ARG;
+  if (h->cfg.resort_period <= 0 &&
+      sort_lds_bytes(h->n_inst, h->c32.max_cells, 2) + 64 > (size_t)h->lds_max)
+    return fail(h, SLPIC_INVALID_ARG, "the cell sort needs more shared memory per block than the device has");
+  hipError_t e = launch_sort_any(h);
+  if (e != hipSuccess) return hip_fail(h, e, "cell sort launch");
   return SLPIC_OK;
 }
 

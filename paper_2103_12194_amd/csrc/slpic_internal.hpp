@@ -14,6 +14,10 @@ constexpr int MAX_CHAN = 8;
 constexpr int NEV = 11;           // event counters per tile
 constexpr int RING = 4096;        // statistics rows kept per instance
 constexpr int MAX_PART = 16;      // output partitions per (instance, species)
+constexpr int CSTRIDE = 64;       // uint32 slots between compaction counters:
+                                  // one 256-byte line each, so that the
+                                  // reservations of one (instance, species)
+                                  // spread over memory channels
 constexpr int NSLOT = 4;          // copies of each global deposit node
 constexpr int HWIN = 1024;        // nodes in a workgroup's LDS deposit window
 
@@ -100,7 +104,7 @@ struct Ctx {
   const InstParams* ip;
   Soa<R> buf[2][2];          // [buffer][species]
   InstState* st;             // [2][n_inst]
-  uint32_t* counts;          // [3][n_inst][2][MAX_PART]
+  uint32_t* counts;          // [3][n_inst][2][MAX_PART], CSTRIDE apart
   unsigned long long* ev;    // [n_inst][NEV][NSLOT] event counters of a step
   unsigned long long* acc;   // [2 species][NSLOT][total_nodes] fixed-point deposit
   R* E;                      // [2][total_nodes] field in kernel precision
@@ -125,6 +129,10 @@ struct Ctx {
   int dep_shift;             // fraction bits of the fixed-point deposit
   int tail_lds;              // dynamic LDS bytes of the tail kernel
   int gen_lds;               // dynamic LDS bytes of the particle kernel
+  uint32_t* sort_hist;       // [2][total_nodes] cell counts of the cell sort
+  uint32_t* sort_cur;        // [2][total_nodes] cursors of the cell sort
+  int max_cells;             // largest cell count of the batch
+  int sort_lds1, sort_lds2;  // dynamic LDS bytes of the sort's count and scatter
 };
 
 }  // namespace slpic

@@ -290,6 +290,22 @@ __device__ __forceinline__ R see_yield(R eps) {
   return R(0.09) * Fm<R>::pow(eps * R(1.0 / 700.0), eps < R(700) ? R(0.05) : R(0.72));
 }
 
+// Eq. (17) yield of an ion that reaches the cathode during this step from
+// its state m at the start of the step: v_x^2 - 2 a x is constant along the
+// flight, so at x = 0, v_x^2 = vx^2 - 2 a x with a gathered at x (the
+// field is gathered again here, out of line on this rare path, so that the
+// particle kernel keeps no extra registers for it)
+template <typename R>
+struct Mk;
+template <typename R>
+__device__ __noinline__ R impact_yield(const R* E, R qm, R dx, const Mk<R> m) {
+  const R a = qm * (E[m.cell] + m.off * (E[m.cell + 1] - E[m.cell]));
+  const R x0 = ((R)m.cell + m.off) * dx;
+  R vx2 = m.vx * m.vx - R(2) * a * x0;
+  vx2 = vx2 > R(0) ? vx2 : R(0);
+  return see_yield<R>(R(0.5 * MAR / QE) * (vx2 + m.vy * m.vy + m.vz * m.vz));
+}
+
 // beta of Eq. (11) as min(1, v0/|v|) (deposit weights)
 template <typename R>
 __device__ __forceinline__ R beta_fast(R v2, R v0, int limited) {
@@ -409,7 +425,7 @@ constexpr double EPS0 = 8.8541878128e-12;
 
 
 __device__ __forceinline__ size_t cidx(int n_inst, uint32_t slot, int inst, int sp, int p) {
-  return (((size_t)slot * n_inst + inst) * 2 + sp) * MAX_PART + p;
+  return ((((size_t)slot * n_inst + inst) * 2 + sp) * MAX_PART + p) * CSTRIDE;
 }
 
 // Exclusive prefix sums of NV values over the 256 threads of a workgroup:
@@ -664,6 +680,81 @@ __device__ __forceinline__ void dep_flush(const Ctx<R>& C, unsigned long long (*
   }
   __syncthreads();
 }
+
+// Tile space of generation g: electrons of instance 0, ions of instance 0,
+// electrons of instance 1, ...; an (instance, species) with P partitions
+// gets P * T tiles, T = max_p ceil(n_p / BLOCK), and tile j reads chunk
+// j mod T of partition j / T (partitions in order, so that the tiles of a
+// cell-sorted (instance, species) follow its cells).  Fills s_prefix[k] with
+// the first tile of pair k = 2 instance + species (k = 0 .. 2 n_inst).
+// Called by all threads; ends with a barrier.
+template <typename R>
+__device__ void tile_prefix(const Ctx<R>& C, uint32_t g, uint32_t* s_prefix, double* s_scan) {
+  const int tid = threadIdx.x, nk = 2 * C.n_inst;
+  // per (instance, species): the largest partition count, read with one
+  // thread per (instance, species, partition) so the loads overlap
+  for (int k = tid; k <= nk; k += BLOCK) s_prefix[k] = 0u;
+  __syncthreads();
+  for (int q = tid; q < nk * MAX_PART; q += BLOCK) {
+    const int k = q / MAX_PART, p = q % MAX_PART;
+    if (p < C.ip[k >> 1].parts) {
+      const uint32_t n = C.counts[cidx(C.n_inst, g % 3u, k >> 1, k & 1, p)];
+      if (n) atomicMax(&s_prefix[k + 1], n);
+    }
+  }
+  __syncthreads();
+  const int per = (nk + BLOCK - 1) / BLOCK;
+  uint32_t loc = 0;
+  for (int k = tid * per; k < min(nk, (tid + 1) * per); ++k) {
+    const uint32_t mx = s_prefix[k + 1];
+    const uint32_t tl = ((mx + BLOCK - 1) / BLOCK) * (uint32_t)C.ip[k >> 1].parts;
+    s_prefix[k + 1] = tl;
+    loc += tl;
+  }
+  double v1[1] = {(double)loc}, ex1[1], tot1[1];
+  block_scan<1>(v1, ex1, tot1, s_scan);
+  uint32_t run = (uint32_t)ex1[0];
+  if (tid == 0) s_prefix[0] = 0;
+  __syncthreads();
+  for (int k = tid * per; k < min(nk, (tid + 1) * per); ++k) {
+    run += s_prefix[k + 1];
+    s_prefix[k + 1] = run;
+  }
+  __syncthreads();
+}
+
+// Position of tiles in the tile space: a cursor that finds its first tile by
+// bisection and then only moves forward.  For tile t it gives the pair k,
+// the tile's partition, and the first marker slot of its chunk.
+struct TileCursor {
+  int kc = -1;
+  uint32_t kbeg = 0, kend = 0;
+  __device__ void locate(const uint32_t* s_prefix, int nk, uint32_t t) {
+    if (kc < 0) {
+      int lo = 0, hi = nk;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_prefix[mid] <= t) lo = mid;
+        else hi = mid;
+      }
+      kc = lo;
+      kbeg = s_prefix[kc];
+      kend = s_prefix[kc + 1];
+    }
+    while (t >= kend) {
+      ++kc;
+      kbeg = kend;
+      kend = s_prefix[kc + 1];
+    }
+  }
+  // partition and first slot of tile t (after locate(t)) for P partitions
+  __device__ void place(uint32_t t, int parts, int& part, uint32_t& first) const {
+    const uint32_t per_part = (kend - kbeg) / (uint32_t)parts;  // tiles per partition
+    const uint32_t j = t - kbeg;
+    part = (int)(j / per_part);
+    first = (j % per_part) * BLOCK;
+  }
+};
 
 // ---------------------------------------------------------------- main kernel
 template <typename R>
@@ -983,43 +1074,8 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
   __syncthreads();
   const uint32_t g = s_gen;
 
-  // tile space of this generation: electrons of instance 0, ions of
-  // instance 0, electrons of instance 1, ...; an (instance, species) with P
-  // partitions gets P * max_p ceil(n_p / BLOCK) tiles, tile j serving
-  // partition j mod P
   const int nk = 2 * C.n_inst;
-  {
-    // per (instance, species): the largest partition count, read with one
-    // thread per (instance, species, partition) so the loads overlap
-    for (int k = tid; k <= nk; k += BLOCK) s_prefix[k] = 0u;
-    __syncthreads();
-    for (int q = tid; q < nk * MAX_PART; q += BLOCK) {
-      const int k = q / MAX_PART, p = q % MAX_PART;
-      if (p < C.ip[k >> 1].parts) {
-        const uint32_t n = C.counts[cidx(C.n_inst, g % 3u, k >> 1, k & 1, p)];
-        if (n) atomicMax(&s_prefix[k + 1], n);
-      }
-    }
-    __syncthreads();
-    const int per = (nk + BLOCK - 1) / BLOCK;
-    uint32_t loc = 0;
-    for (int k = tid * per; k < min(nk, (tid + 1) * per); ++k) {
-      const uint32_t mx = s_prefix[k + 1];
-      const uint32_t tl = ((mx + BLOCK - 1) / BLOCK) * (uint32_t)C.ip[k >> 1].parts;
-      s_prefix[k + 1] = tl;
-      loc += tl;
-    }
-    double v1[1] = {(double)loc}, ex1[1], tot1[1];
-    block_scan<1>(v1, ex1, tot1, s_scan);
-    uint32_t run = (uint32_t)ex1[0];
-    if (tid == 0) s_prefix[0] = 0;
-    __syncthreads();
-    for (int k = tid * per; k < min(nk, (tid + 1) * per); ++k) {
-      run += s_prefix[k + 1];
-      s_prefix[k + 1] = run;
-    }
-    __syncthreads();
-  }
+  tile_prefix(C, g, s_prefix, s_scan);
   const uint32_t n_tiles = s_prefix[nk];
   const uint32_t bsel = C.g->bufsel[g % 2u];
 
@@ -1065,39 +1121,16 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
     emit<R, MODE, true>(C, W, win, s_hist, o, ev, err, g, bsel, evw);
   };
 
-  // position of tile t: (instance, species) index k, tile j within it.  The
-  // cursor finds the first tile by bisection and then only moves forward.
-  int kc = -1;
-  uint32_t kbeg = 0, kend = 0;
-  auto locate = [&](uint32_t t, int& k, uint32_t& j) {
-    if (kc < 0) {
-      int lo = 0, hi = nk;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (s_prefix[mid] <= t) lo = mid;
-        else hi = mid;
-      }
-      kc = lo;
-      kbeg = s_prefix[kc];
-      kend = s_prefix[kc + 1];
-    }
-    while (t >= kend) {
-      ++kc;
-      kbeg = kend;
-      kend = s_prefix[kc + 1];
-    }
-    k = kc;
-    j = t - kbeg;
-  };
+  TileCursor cur;
   for (uint32_t t = t_begin; t < t_end; ++t) {
-    int k;
-    uint32_t j;
-    locate(t, k, j);
-    const int inst = k >> 1, sp = k & 1;
+    cur.locate(s_prefix, nk, t);
+    const int k = cur.kc, inst = k >> 1, sp = k & 1;
     const InstParams& P = C.ip[inst];
-    const int part = (int)(j % (uint32_t)P.parts);
+    int part;
+    uint32_t first;
+    cur.place(t, P.parts, part, first);
     const uint32_t n_in = C.counts[cidx(C.n_inst, g % 3u, inst, sp, part)];
-    const uint32_t idx = (j / (uint32_t)P.parts) * BLOCK + (uint32_t)tid;
+    const uint32_t idx = first + (uint32_t)tid;
     const bool valid = idx < n_in;
     const int64_t pbase = P.seg + (int64_t)part * P.cap_p;
     if (inst != W.inst || sp != W.sp) {
@@ -1107,7 +1140,6 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
         // flush the old deposit window, anchor the new one a quarter window
         // below the tile's first marker
         if (win.inst >= 0) dep_flush(C, s_hist, win, s_evw);
-        const uint32_t first = (j / (uint32_t)P.parts) * BLOCK;
         int c0 = first < n_in ? C.buf[bsel][sp].cell[pbase + first] : 0;
         int anchor = c0 - HWIN / 4;
         const int top = P.cells + 1 - HWIN;
@@ -1179,16 +1211,10 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
           // Eq. (17) at the impact energy; v_x^2 - 2 a x is constant along
           // the flight, so the ion reaches x = 0 with v_x^2 = vx^2 - 2 a x
           const U4 r = draw_cold(m.id, step, CH_SEE, C.seed, inst);
-          bool see;
-          if (C.flags & 2u) {
-            const R x0 = ((R)m.cell + m.off) * (R)P.dx;
-            R vx2 = m.vx * m.vx - R(2) * a * x0;
-            vx2 = vx2 > R(0) ? vx2 : R(0);
-            const R eps = R(0.5 * MAR / QE) * (vx2 + m.vy * m.vy + m.vz * m.vz);
-            see = unif<R>(r.x) < see_yield<R>(eps);
-          } else {
-            see = (r.x >> 9) < P.t_see;
-          }
+          const bool see = (C.flags & 2u)
+                               ? unif<R>(r.x) < impact_yield<R>(C.E + (size_t)(g % 2u) * C.total_nodes + P.node,
+                                                               (R)P.qm_i, (R)P.dx, m)
+                               : (r.x >> 9) < P.t_see;
           if (see) {
             ev |= 1u << EV_SEE;
             Mk<R> e;
@@ -1238,6 +1264,204 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
   }
   while (q_count > 0) run_queue(q_count < (uint32_t)WAVE ? q_count : (uint32_t)WAVE);
   if (win.inst >= 0) dep_flush(C, s_hist, win, s_evw);
+}
+
+// ---------------------------------------------------------------- cell sort
+// Counting sort of every (instance, species) by cell, between two steps.
+// It moves markers without changing them, and nothing in a step depends on
+// the order of the markers (random draws are keyed by marker id and step,
+// deposits are exact fixed-point sums), so a sorted run equals an unsorted
+// one bit for bit.  Markers go to the other buffer in cell order: partition
+// p of a pair with n markers takes ranks [p q, (p + 1) q), q = ceil(n / P),
+// so the partition-ordered tiles of the next step follow the cells.  Within
+// a cell the order is that of the atomic cursors (the sort is not stable).
+//
+// Dynamic LDS of the three tile-walking kernels: the tile offsets, then one
+// (count) or two (scatter) arrays of max_cells words.
+
+// generation and buffer of the state the sort works on (set by the tail)
+template <typename R>
+__device__ __forceinline__ void sort_state(const Ctx<R>& C, uint32_t& g, uint32_t& bsel) {
+  g = C.g->cur_gen;
+  bsel = C.g->bufsel[g % 2u];
+}
+
+template <typename R>
+__device__ __forceinline__ uint32_t pair_count(const Ctx<R>& C, uint32_t g, int inst, int sp) {
+  uint32_t n = 0;
+  for (int p = 0; p < C.ip[inst].parts; ++p) n += C.counts[cidx(C.n_inst, g % 3u, inst, sp, p)];
+  return n;
+}
+
+// 1: per-cell marker counts of every pair, in LDS per workgroup and pair
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_sort_count(Ctx<R> C) {
+  extern __shared__ uint32_t s_dyn[];
+  __shared__ double s_scan[4];
+  const int nk = 2 * C.n_inst, tid = threadIdx.x;
+  uint32_t* s_prefix = s_dyn;
+  uint32_t* s_hist = s_dyn + ((nk + 1 + 3) & ~3);
+  uint32_t g, bsel;
+  sort_state(C, g, bsel);
+  for (int i = tid; i < C.max_cells; i += BLOCK) s_hist[i] = 0u;
+  tile_prefix(C, g, s_prefix, s_scan);
+  const uint32_t n_tiles = s_prefix[nk];
+  const uint32_t per = (n_tiles + (uint32_t)C.grid - 1) / (uint32_t)C.grid;
+  const uint32_t t_begin = blockIdx.x * per, t_end = min(n_tiles, t_begin + per);
+  TileCursor cur;
+  int k_open = -1;
+  auto flush = [&]() {
+    __syncthreads();
+    const InstParams& P = C.ip[k_open >> 1];
+    uint32_t* dst = C.sort_hist + (size_t)(k_open & 1) * C.total_nodes + P.node;
+    for (int c = tid; c < P.cells; c += BLOCK) {
+      const uint32_t v = s_hist[c];
+      if (v) {
+        atomicAdd(dst + c, v);
+        s_hist[c] = 0u;
+      }
+    }
+    __syncthreads();
+  };
+  for (uint32_t t = t_begin; t < t_end; ++t) {
+    cur.locate(s_prefix, nk, t);
+    if (cur.kc != k_open) {
+      if (k_open >= 0) flush();
+      k_open = cur.kc;
+    }
+    const int inst = cur.kc >> 1, sp = cur.kc & 1;
+    const InstParams& P = C.ip[inst];
+    int part;
+    uint32_t first;
+    cur.place(t, P.parts, part, first);
+    const uint32_t idx = first + (uint32_t)tid;
+    if (idx < C.counts[cidx(C.n_inst, g % 3u, inst, sp, part)])
+      atomicAdd(&s_hist[C.buf[bsel][sp].cell[P.seg + (int64_t)part * P.cap_p + idx]], 1u);
+  }
+  if (k_open >= 0) flush();
+}
+
+// 2: one workgroup per pair: exclusive prefix sums of the counts become the
+// cursors of the scatter; the counts are cleared for the next sort
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_sort_scan(Ctx<R> C) {
+  __shared__ double s_scan[4];
+  const int k = blockIdx.x, inst = k >> 1, sp = k & 1, tid = threadIdx.x;
+  const InstParams& P = C.ip[inst];
+  uint32_t* hist = C.sort_hist + (size_t)sp * C.total_nodes + P.node;
+  uint32_t* cursor = C.sort_cur + (size_t)sp * C.total_nodes + P.node;
+  const int chunk = (P.cells + BLOCK - 1) / BLOCK;
+  const int c0 = tid * chunk, c1 = min(P.cells, c0 + chunk);
+  uint32_t loc = 0;
+  for (int c = c0; c < c1; ++c) loc += hist[c];
+  double v1[1] = {(double)loc}, ex1[1], tot1[1];
+  block_scan<1>(v1, ex1, tot1, s_scan);
+  uint32_t run = (uint32_t)ex1[0];
+  for (int c = c0; c < c1; ++c) {
+    const uint32_t v = hist[c];
+    cursor[c] = run;
+    run += v;
+    hist[c] = 0u;
+  }
+}
+
+// 3: each workgroup counts its markers of a pair per cell, reserves one
+// range per cell on the pair's cursors, then places every marker at
+// rank = reserved start + local order, in the other buffer
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_sort_scatter(Ctx<R> C) {
+  extern __shared__ uint32_t s_dyn[];
+  __shared__ double s_scan[4];
+  const int nk = 2 * C.n_inst, tid = threadIdx.x;
+  uint32_t* s_prefix = s_dyn;
+  uint32_t* s_cnt = s_dyn + ((nk + 1 + 3) & ~3);
+  uint32_t* s_base = s_cnt + C.max_cells;
+  uint32_t g, bsel;
+  sort_state(C, g, bsel);
+  for (int i = tid; i < C.max_cells; i += BLOCK) s_cnt[i] = 0u;
+  tile_prefix(C, g, s_prefix, s_scan);
+  const uint32_t n_tiles = s_prefix[nk];
+  const uint32_t per = (n_tiles + (uint32_t)C.grid - 1) / (uint32_t)C.grid;
+  const uint32_t t_begin = blockIdx.x * per, t_end = min(n_tiles, t_begin + per);
+  // the workgroup's tiles, one pair at a time
+  uint32_t t = t_begin;
+  while (t < t_end) {
+    TileCursor cur;
+    cur.locate(s_prefix, nk, t);
+    const int k = cur.kc, inst = k >> 1, sp = k & 1;
+    const uint32_t run_end = min(t_end, cur.kend);
+    const InstParams& P = C.ip[inst];
+    const Soa<R> in = C.buf[bsel][sp], out = C.buf[1u - bsel][sp];
+    const uint32_t n = pair_count(C, g, inst, sp);
+    const uint32_t q = (n + (uint32_t)P.parts - 1) / (uint32_t)P.parts;
+    // pass A: counts per cell
+    for (uint32_t u = t; u < run_end; ++u) {
+      int part;
+      uint32_t first;
+      cur.place(u, P.parts, part, first);
+      const uint32_t idx = first + (uint32_t)tid;
+      if (idx < C.counts[cidx(C.n_inst, g % 3u, inst, sp, part)])
+        atomicAdd(&s_cnt[in.cell[P.seg + (int64_t)part * P.cap_p + idx]], 1u);
+    }
+    __syncthreads();
+    uint32_t* cursor = C.sort_cur + (size_t)sp * C.total_nodes + P.node;
+    for (int c = tid; c < P.cells; c += BLOCK) {
+      const uint32_t v = s_cnt[c];
+      if (v) s_base[c] = atomicAdd(cursor + c, v);
+      s_cnt[c] = 0u;
+    }
+    __syncthreads();
+    // pass B: place
+    for (uint32_t u = t; u < run_end; ++u) {
+      int part;
+      uint32_t first;
+      cur.place(u, P.parts, part, first);
+      const uint32_t idx = first + (uint32_t)tid;
+      if (idx < C.counts[cidx(C.n_inst, g % 3u, inst, sp, part)]) {
+        const int64_t s = P.seg + (int64_t)part * P.cap_p + idx;
+        const int32_t cell = in.cell[s];
+        const uint32_t rank = s_base[cell] + atomicAdd(&s_cnt[cell], 1u);
+        const int64_t d = P.seg + (int64_t)(rank / q) * P.cap_p + rank % q;
+        out.cell[d] = cell;
+        out.off[d] = in.off[s];
+        out.vx[d] = in.vx[s];
+        out.vy[d] = in.vy[s];
+        out.vz[d] = in.vz[s];
+        out.id[d] = in.id[s];
+      }
+    }
+    __syncthreads();
+    for (int c = tid; c < P.cells; c += BLOCK) s_cnt[c] = 0u;
+    __syncthreads();
+    t = run_end;
+  }
+}
+
+// 4: one thread per pair: the new partition counts, then the buffer switch
+template <typename R>
+__global__ void k_sort_commit(Ctx<R> C) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t g, bsel;
+  sort_state(C, g, bsel);
+  if (k < 2 * C.n_inst) {
+    const int inst = k >> 1, sp = k & 1;
+    const InstParams& P = C.ip[inst];
+    const uint32_t n = pair_count(C, g, inst, sp);
+    const uint32_t q = (n + (uint32_t)P.parts - 1) / (uint32_t)P.parts;
+    for (int p = 0; p < P.parts; ++p) {
+      const uint32_t lo = (uint32_t)p * q;
+      C.counts[cidx(C.n_inst, g % 3u, inst, sp, p)] = lo < n ? min(q, n - lo) : 0u;
+    }
+  }
+  // every thread has read the counts above before one of them switches the
+  // buffer: the switch is made by a second launch (see launch_sort)
+}
+
+template <typename R>
+__global__ void k_sort_switch(Ctx<R> C) {
+  uint32_t g, bsel;
+  sort_state(C, g, bsel);
+  C.g->bufsel[g % 2u] = 1u - bsel;
 }
 
 // ---------------------------------------------------------------- seeding
@@ -1299,6 +1523,17 @@ hipError_t launch_tail(const Ctx<R>& C, int mode, hipStream_t s) {
 }
 
 template <typename R>
+hipError_t launch_sort(const Ctx<R>& C, hipStream_t s) {
+  hipLaunchKernelGGL((k_sort_count<R>), dim3(C.grid), dim3(BLOCK), C.sort_lds1, s, C);
+  hipLaunchKernelGGL((k_sort_scan<R>), dim3(2 * C.n_inst), dim3(BLOCK), 0, s, C);
+  hipLaunchKernelGGL((k_sort_scatter<R>), dim3(C.grid), dim3(BLOCK), C.sort_lds2, s, C);
+  hipLaunchKernelGGL((k_sort_commit<R>), dim3((2 * C.n_inst + BLOCK - 1) / BLOCK), dim3(BLOCK), 0,
+                     s, C);
+  hipLaunchKernelGGL((k_sort_switch<R>), dim3(1), dim3(1), 0, s, C);
+  return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_seed(const Ctx<R>& C, int inst, int mode, int64_t n, double sigma_v,
                        uint32_t bsel, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -1317,6 +1552,8 @@ hipError_t occupancy_gen(int* blocks_per_cu, size_t dyn_lds) {
 template hipError_t launch_particles<float>(const Ctx<float>&, int, hipStream_t);
 template hipError_t launch_particles<double>(const Ctx<double>&, int, hipStream_t);
 template hipError_t launch_tail<float>(const Ctx<float>&, int, hipStream_t);
+template hipError_t launch_sort<float>(const Ctx<float>&, hipStream_t);
+template hipError_t launch_sort<double>(const Ctx<double>&, hipStream_t);
 template hipError_t launch_tail<double>(const Ctx<double>&, int, hipStream_t);
 template hipError_t launch_seed<float>(const Ctx<float>&, int, int, int64_t, double, uint32_t,
                                        hipStream_t);

@@ -62,7 +62,7 @@ class Run:
     area: float = 1.0        # electrode area [m^2]
     w_j0: float = 1.0        # initial flux weight
     cfl: float = 0.5         # v0 dt / dx
-    resort_period: int = 16
+    resort_period: int = 0   # cell sort every n steps (0 = never)
     ion_B_eV: float = 10.0   # ionization energy-sharing parameter
     kTe_seed_eV: float = 1.0
 

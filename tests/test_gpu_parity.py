@@ -273,3 +273,46 @@ def test_autotuned_grid_changes_timing_not_results(xs_argon):
             compare_populations(a.read(sp, k), b.read(sp, k), 0.0, 0.0,
                                 a.scalars(k)["v0"], label=f"inst {k} sp {sp}")
     print("default grid", g0, "autotuned", g)
+
+
+def test_cell_sort_orders_markers_and_keeps_results(xs_argon):
+    """Sorting every 4 steps gives the same FP64 steps as never sorting, and
+    an explicit sort leaves every (instance, species) in cell order across
+    its partitions with each marker unchanged."""
+    insts = [_c1_small(n_seed=6000, n_target=4000),
+             configs.Instance(d=0.02, p_torr=0.5, V=250.0, cells=130,
+                              gamma_se=0.1, seed_mode=configs.SEED_MAXWELL_CELL0,
+                              n_seed=3000, n_target=0, capacity=40000)]
+    a = slpic.Sim(insts, configs.Run(precision=64, resort_period=4), xs_argon)
+    b = slpic.Sim(insts, configs.Run(precision=64, resort_period=0), xs_argon)
+    a.step(23)
+    b.step(23)
+    assert a.sync() == 0 and b.sync() == 0
+    for k in range(len(insts)):
+        ha, hb = a.history(0, 23, inst=k), b.history(0, 23, inst=k)
+        for key in STAT_INT + ["w_e", "w_i", "w_j"]:
+            assert np.array_equal(ha[key], hb[key]), (k, key)
+        for sp in (0, 1):
+            compare_populations(a.read(sp, k), b.read(sp, k), 0.0, 0.0,
+                                a.scalars(k)["v0"], label=f"inst {k} sp {sp}")
+    before = [[b.read(sp, k) for sp in (0, 1)] for k in range(len(insts))]
+    b.sort()
+    assert b.sync() == 0
+    total = 0
+    for k in range(len(insts)):
+        for sp in (0, 1):
+            after = b.read(sp, k)
+            assert after["cell"].size == before[k][sp]["cell"].size, (k, sp)
+            total += after["cell"].size
+            print("sorted", k, sp, after["cell"].size)
+            assert np.all(np.diff(after["cell"]) >= 0), (k, sp)
+            compare_populations(after, before[k][sp], 0.0, 0.0,
+                                b.scalars(k)["v0"], label=f"sorted inst {k} sp {sp}")
+    assert total > 0
+    # and the sorted state steps on like the unsorted one
+    a.step(5)
+    b.step(5)
+    for k in range(len(insts)):
+        for sp in (0, 1):
+            compare_populations(a.read(sp, k), b.read(sp, k), 0.0, 0.0,
+                                a.scalars(k)["v0"], label=f"after inst {k} sp {sp}")
