@@ -95,6 +95,12 @@ template <> struct Fm<float> {
   }
 };
 
+// Per-instance parameters do not change while a kernel runs: reading them
+// through the constant address space lets the compiler use scalar loads
+// (held in scalar registers, reloaded cheaply) instead of vector loads.
+using IP = const __attribute__((address_space(4))) InstParams;
+__device__ __forceinline__ IP& param(const InstParams* ip, int i) { return ((IP*)ip)[i]; }
+
 // ---------------------------------------------------------------- Philox
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
 // multiplies on words 0 and 2, with the Weyl-sequence key schedule.
@@ -428,6 +434,16 @@ __device__ __forceinline__ size_t cidx(int n_inst, uint32_t slot, int inst, int 
   return ((((size_t)slot * n_inst + inst) * 2 + sp) * MAX_PART + p) * CSTRIDE;
 }
 
+// Marker count of an input partition of generation g.  Nothing writes the
+// input slot of the count ring while the particle kernel runs (reservations
+// go to slot g + 1), so it is read through the constant address space, with
+// a scalar load.
+__device__ __forceinline__ uint32_t count_in(const uint32_t* counts, int n_inst, uint32_t g,
+                                             int inst, int sp, int p) {
+  using CU = const __attribute__((address_space(4))) uint32_t;
+  return ((CU*)counts)[cidx(n_inst, g % 3u, inst, sp, p)];
+}
+
 // Exclusive prefix sums of NV values over the 256 threads of a workgroup:
 // wave-level shuffles, then one exchange of the four wave totals through
 // LDS (sh holds 4 NV doubles).  ex[] receives the prefixes, tot[] the sums.
@@ -480,7 +496,7 @@ __global__ void __launch_bounds__(BLOCK) k_tail(Ctx<R> C) {
   __shared__ uint32_t s_bs;
   const int inst = blockIdx.x, t = threadIdx.x;
   const uint32_t g = (uint32_t)(C.g->wgc / (unsigned long long)C.grid) - 1u;
-  const InstParams& P = C.ip[inst];
+  IP& P = param(C.ip, inst);
   const int N = P.cells, node = P.node;
   const uint32_t sn = (g + 1) % 2u;
   if (t < NEV) s_ev[t] = 0ull;
@@ -666,7 +682,7 @@ __device__ __forceinline__ void dep_flush(const Ctx<R>& C, unsigned long long (*
     if (v) atomicAdd(C.ev + ((size_t)w.inst * NEV + threadIdx.x) * NSLOT + slot,
                      (unsigned long long)v);
   }
-  const InstParams& P = C.ip[w.inst];
+  IP& P = param(C.ip, w.inst);
   const int nn = min(HWIN, P.cells + 1 - w.anchor);
   for (int sp = 0; sp < 2; ++sp) {
     unsigned long long* dst = C.acc + ((size_t)sp * NSLOT + slot) * C.total_nodes + P.node + w.anchor;
@@ -697,7 +713,7 @@ __device__ void tile_prefix(const Ctx<R>& C, uint32_t g, uint32_t* s_prefix, dou
   __syncthreads();
   for (int q = tid; q < nk * MAX_PART; q += BLOCK) {
     const int k = q / MAX_PART, p = q % MAX_PART;
-    if (p < C.ip[k >> 1].parts) {
+    if (p < param(C.ip, k >> 1).parts) {
       const uint32_t n = C.counts[cidx(C.n_inst, g % 3u, k >> 1, k & 1, p)];
       if (n) atomicMax(&s_prefix[k + 1], n);
     }
@@ -707,7 +723,7 @@ __device__ void tile_prefix(const Ctx<R>& C, uint32_t g, uint32_t* s_prefix, dou
   uint32_t loc = 0;
   for (int k = tid * per; k < min(nk, (tid + 1) * per); ++k) {
     const uint32_t mx = s_prefix[k + 1];
-    const uint32_t tl = ((mx + BLOCK - 1) / BLOCK) * (uint32_t)C.ip[k >> 1].parts;
+    const uint32_t tl = ((mx + BLOCK - 1) / BLOCK) * (uint32_t)param(C.ip, k >> 1).parts;
     s_prefix[k + 1] = tl;
     loc += tl;
   }
@@ -759,13 +775,28 @@ struct TileCursor {
 // ---------------------------------------------------------------- main kernel
 template <typename R>
 struct LaneOut {
-  Mk<R> e[2];   // electrons produced by this lane (before population control)
-  Mk<R> i1;     // ion produced by this lane
-  int ne, ni;   // how many of e[] / i1 are set
+  Mk<R> e[2];        // electrons produced by this lane (before population control)
+  Mk<R> i[2];        // ions produced by this lane
+  uint32_t me, mi;   // which slots of e[] / i[] are set (bit j: slot j)
 };
 
 constexpr int NWAVE = BLOCK / WAVE;
-constexpr int QW = 2 * WAVE;  // collision-queue slots per wave
+// collision-queue slots per wave: fewer than WAVE wait between tiles, and a
+// tile pair adds at most 2 WAVE
+constexpr int QW = 3 * WAVE;
+
+// a wave-uniform or lane ring position a + b for a, b < QW
+__device__ __forceinline__ uint32_t ring(uint32_t a, uint32_t b) {
+  const uint32_t s = a + b;
+  return s >= (uint32_t)QW ? s - (uint32_t)QW : s;
+}
+
+// count event bits b in ev, or in ev2 for those ev already holds (the same
+// event for the lane's other marker)
+__device__ __forceinline__ void note(uint32_t& ev, uint32_t& ev2, uint32_t b) {
+  ev2 |= ev & b;
+  ev |= b;
+}
 
 // What a wave is working on: one (instance, species), and the output
 // partition of its next emit.
@@ -782,7 +813,7 @@ struct Work {
 // output in expectation whatever partition the markers came from, and no
 // fixed stride between tiles can map one input partition to one output
 // partition step after step.
-__device__ __forceinline__ void next_output(Work& W, const InstParams& P) {
+__device__ __forceinline__ void next_output(Work& W, IP& P) {
   const uint32_t wid = blockIdx.x * (uint32_t)NWAVE + threadIdx.x / WAVE;
   uint32_t h = wid * 0x9E3779B1u ^ (W.emits * 0x85EBCA77u + W.step * 0xC2B2AE3Du);
   h ^= h >> 16;
@@ -798,15 +829,17 @@ __device__ __forceinline__ void next_output(Work& W, const InstParams& P) {
 // Population control, charge deposit, event counts and stream compaction of
 // the markers each lane of one wave produced.  Called by all lanes of the
 // wave, independently of the other waves.  QUEUE: outputs of collided
-// candidates (collision events) rather than of a tile (wall and emission
-// events).  Event counts go to the wave's row evw of LDS counters.
+// candidates (collision events) rather than of a tile pair (wall and
+// emission events; a lane counts an event that both of its markers had once
+// in ev and once in ev2).  Event counts go to the wave's row evw of LDS
+// counters.
 template <typename R, int MODE, bool QUEUE>
 __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWin& win,
                                      unsigned long long (*hist)[HWIN], const LaneOut<R>& o,
-                                     uint32_t ev, uint32_t err, uint32_t g, uint32_t bsel,
-                                     uint32_t* evw) {
+                                     uint32_t ev, uint32_t ev2, uint32_t err, uint32_t g,
+                                     uint32_t bsel, uint32_t* evw) {
   const int lane = threadIdx.x & (WAVE - 1);
-  const InstParams& P = C.ip[W.inst];
+  IP& P = param(C.ip, W.inst);
   const int inst = W.inst, pop = W.pop;
   const uint32_t step = W.step;
   const R v0 = (R)P.v0;
@@ -814,11 +847,11 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
 
   // population control: each output is kept (roulette) or doubled (split)
   uint32_t keep_e = 0, keep_i = 0;
-  uint64_t clone_e[2] = {0, 0}, clone_i = 0;
+  uint64_t clone_e[2] = {0, 0}, clone_i[2] = {0, 0};
   int cnt_e = 0, cnt_i = 0;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    if (j >= o.ne) continue;
+    if (!(o.me >> j & 1u)) continue;
     if (pop == POP_ROULETTE) {
       const U4 r = draw_cold(o.e[j].id, step, CH_ROULETTE, C.seed, inst);
       if ((r.x >> 9) < (1u << 22)) { keep_e |= 1u << j; ++cnt_e; }
@@ -832,22 +865,27 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
       }
     }
   }
-  if (o.ni) {
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    if (!(o.mi >> j & 1u)) continue;
     if (pop == POP_ROULETTE) {
-      const U4 r = draw_cold(o.i1.id, step, CH_ROULETTE, C.seed, inst);
-      if ((r.x >> 9) < (1u << 22)) { keep_i = 1; ++cnt_i; }
+      const U4 r = draw_cold(o.i[j].id, step, CH_ROULETTE, C.seed, inst);
+      if ((r.x >> 9) < (1u << 22)) { keep_i |= 1u << j; ++cnt_i; }
     } else {
-      keep_i = 1;
+      keep_i |= 1u << j;
       ++cnt_i;
       if (pop == POP_SPLIT) {
-        const U4 r = draw_cold(o.i1.id, step, CH_CHILD | (1u << 8), C.seed, inst);
-        clone_i = child(r.x, r.y);
+        const U4 r = draw_cold(o.i[j].id, step, CH_CHILD | (1u << 8), C.seed, inst);
+        clone_i[j] = child(r.x, r.y);
         ++cnt_i;
       }
     }
   }
-  const int removed = pop == POP_ROULETTE ? (o.ne + o.ni) - (cnt_e + cnt_i) : 0;
-  const int split_added = pop == POP_SPLIT ? (o.ne + o.ni) : 0;
+  // at most three outputs per lane (two from a tile pair, three from an
+  // ionization)
+  const int n_out = __popc(o.me) + __popc(o.mi);
+  const int removed = pop == POP_ROULETTE ? n_out - (cnt_e + cnt_i) : 0;
+  const int split_added = pop == POP_SPLIT ? n_out : 0;
 
   // deposit (fixed point, units of q w_j): every kept marker adds its two
   // linear weights to the LDS window (clones count twice)
@@ -855,17 +893,19 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
     const int shift = C.dep_shift;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      if (q >= o.ne || !(keep_e >> q & 1u)) continue;
+      if (!(keep_e >> q & 1u)) continue;
       const Mk<R>& e = o.e[q];
       const R b = beta_fast(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
       const unsigned long long mul = clone_e[q] ? 2ull : 1ull;
       dep_add(C.acc, C.acc, hist, win, 0, P.node, C.total_nodes, e.cell,
               fixed_pt<R>(b * (R(1) - e.off), shift) * mul, fixed_pt<R>(b * e.off, shift) * mul);
     }
-    if (o.ni && keep_i) {
-      const Mk<R>& e = o.i1;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (!(keep_i >> q & 1u)) continue;
+      const Mk<R>& e = o.i[q];
       const R b = beta_fast(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
-      const unsigned long long mul = clone_i ? 2ull : 1ull;
+      const unsigned long long mul = clone_i[q] ? 2ull : 1ull;
       dep_add(C.acc, C.acc, hist, win, 1, P.node, C.total_nodes, e.cell,
               fixed_pt<R>(b * (R(1) - e.off), shift) * mul, fixed_pt<R>(b * e.off, shift) * mul);
     }
@@ -875,9 +915,11 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
   if (__ballot(ev != 0u)) {
     constexpr int q0 = QUEUE ? EV_ELASTIC : EV_ABS_E_CATH;
     constexpr int q1 = QUEUE ? EV_ABS_E_CATH : EV_ROULETTE;
+    const bool twice = !QUEUE && __ballot(ev2 != 0u);
 #pragma unroll
     for (int q = q0; q < q1; ++q) {
-      const uint32_t n = (uint32_t)__popcll(__ballot((ev >> q) & 1u));
+      uint32_t n = (uint32_t)__popcll(__ballot((ev >> q) & 1u));
+      if (twice) n += (uint32_t)__popcll(__ballot((ev2 >> q) & 1u));
       if (lane == 0 && n) atomicAdd(&evw[q], n);
     }
   }
@@ -889,16 +931,18 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
   if (err) atomicOr(C.inst_err + inst, err);
 
   if (MODE != MODE_STEP) return;
-  // compaction: prefix within the wave by bit-sliced ballots, one
-  // reservation per wave and species on the partition's counter
+  // compaction: prefix within the wave by bit-sliced ballots (cnt_e, cnt_i
+  // in 0..4), one reservation per wave and species on the partition's
+  // counter
   const unsigned long long lt = (1ull << lane) - 1ull;
   const unsigned long long be0 = __ballot(cnt_e & 1), be1 = __ballot(cnt_e & 2),
                            be2 = __ballot(cnt_e & 4);
-  const unsigned long long bi0 = __ballot(cnt_i & 1), bi1 = __ballot(cnt_i & 2);
+  const unsigned long long bi0 = __ballot(cnt_i & 1), bi1 = __ballot(cnt_i & 2),
+                           bi2 = QUEUE ? 0ull : __ballot(cnt_i & 4);
   const uint32_t pre_e = __popcll(be0 & lt) + 2 * __popcll(be1 & lt) + 4 * __popcll(be2 & lt);
-  const uint32_t pre_i = __popcll(bi0 & lt) + 2 * __popcll(bi1 & lt);
+  const uint32_t pre_i = __popcll(bi0 & lt) + 2 * __popcll(bi1 & lt) + 4 * __popcll(bi2 & lt);
   const uint32_t te = __popcll(be0) + 2 * __popcll(be1) + 4 * __popcll(be2);
-  const uint32_t ti = __popcll(bi0) + 2 * __popcll(bi1);
+  const uint32_t ti = __popcll(bi0) + 2 * __popcll(bi1) + 4 * __popcll(bi2);
   uint32_t base_e = 0u, base_i = 0u;
   if (lane == 0) {
     if (te) base_e = atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 0, W.part), te);
@@ -910,7 +954,7 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
   uint32_t werr = 0;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    if (j >= o.ne || !(keep_e >> j & 1u)) continue;
+    if (!(keep_e >> j & 1u)) continue;
 #pragma unroll
     for (int rep = 0; rep < 2; ++rep) {
       if (rep == 1 && !clone_e[j]) continue;
@@ -928,18 +972,20 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
       ++pe;
     }
   }
-  if (o.ni && keep_i) {
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    if (!(keep_i >> j & 1u)) continue;
 #pragma unroll
     for (int rep = 0; rep < 2; ++rep) {
-      if (rep == 1 && !clone_i) continue;
+      if (rep == 1 && !clone_i[j]) continue;
       if (pi < (uint32_t)P.cap_p) {
         const int64_t s = W.pbase + pi;
-        oi.cell[s] = o.i1.cell;
-        oi.off[s] = o.i1.off;
-        oi.vx[s] = o.i1.vx;
-        oi.vy[s] = o.i1.vy;
-        oi.vz[s] = o.i1.vz;
-        oi.id[s] = rep ? clone_i : o.i1.id;
+        oi.cell[s] = o.i[j].cell;
+        oi.off[s] = o.i[j].off;
+        oi.vx[s] = o.i[j].vx;
+        oi.vy[s] = o.i[j].vy;
+        oi.vz[s] = o.i[j].vz;
+        oi.id[s] = rep ? clone_i[j] : o.i[j].id;
       } else {
         werr |= ERR_CAPACITY;
       }
@@ -953,7 +999,7 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
 // the SLPIC rate of Eq. (16) or the fixed-event thresholds, then the scatter
 // law of the channel; ionization spawns an electron and an ion.
 template <typename R>
-__device__ void collide_electron(const Ctx<R>& C, const InstParams& P, int inst, uint32_t step,
+__device__ void collide_electron(const Ctx<R>& C, IP& P, int inst, uint32_t step,
                                  Mk<R>& m, LaneOut<R>& o, uint32_t& ev, uint32_t& err) {
   const U4 r = draw(m.id, step, CH_COLL, C.seed, inst);
   const R v2 = m.vx * m.vx + m.vy * m.vy + m.vz * m.vz;
@@ -1017,18 +1063,18 @@ __device__ void collide_electron(const Ctx<R>& C, const InstParams& P, int inst,
       normals3<R>(b, (R)P.vth_i, i2.vx, i2.vy, i2.vz);
       i2.id = child(cid.z, cid.w);
       o.e[1] = e2;
-      o.i1 = i2;
-      o.ni = 1;
+      o.i[0] = i2;
+      o.mi = 1u;
     }
   }
   o.e[0] = m;
-  o.ne = o.ni ? 2 : 1;
+  o.me = o.mi ? 3u : 1u;
 }
 
 // Ar+ charge exchange of a candidate: the ion takes a neutral's thermal
 // velocity.
 template <typename R>
-__device__ void collide_ion(const Ctx<R>& C, const InstParams& P, int inst, uint32_t step,
+__device__ void collide_ion(const Ctx<R>& C, IP& P, int inst, uint32_t step,
                             Mk<R>& m, LaneOut<R>& o, uint32_t& ev, uint32_t& err) {
   bool hit = true;  // fixed-event candidates always exchange
   if (!C.fixed) {
@@ -1047,12 +1093,94 @@ __device__ void collide_ion(const Ctx<R>& C, const InstParams& P, int inst, uint
     normals3<R>(b, (R)P.vth_i, m.vx, m.vy, m.vz);
     ev |= 1u << EV_CX;
   }
-  o.i1 = m;
-  o.ni = 1;
+  o.i[0] = m;
+  o.mi = 1u;
+}
+
+// One marker of a tile, taken by slot H of its lane's outputs: gather at
+// x^n, null-collision draw, flight, walls and emission.  A collision
+// candidate sets cand and produces nothing yet; otherwise the marker, or the
+// electron its cathode impact emits, becomes output H.
+template <typename R, int MODE, int H>
+__device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp,
+                                        uint32_t g, uint32_t step, bool valid, Mk<R>& m,
+                                        LaneOut<R>& o, uint32_t& ev, uint32_t& ev2,
+                                        uint32_t& err, bool& cand) {
+  if (!valid) return;
+  if (MODE == MODE_REFRESH) {
+    if (sp == 0) { o.e[H] = m; o.me |= 1u << H; }
+    else { o.i[H] = m; o.mi |= 1u << H; }
+    return;
+  }
+  // the null-collision draw does not depend on the field and overlaps the
+  // gather
+  const R* E = C.E + (size_t)(g % 2u) * C.total_nodes + P.node;
+  const R e0 = E[m.cell], e1 = E[m.cell + 1];
+  const U4 rn = draw(m.id, step, sp == 0 ? (uint32_t)CH_COLL : (uint32_t)CH_CX, C.seed, inst);
+  const R Ep = e0 + m.off * (e1 - e0);
+  const R a = (R)(sp == 0 ? P.qm_e : P.qm_i) * Ep;
+  const R c = Fm<R>::sqrt(m.vy * m.vy + m.vz * m.vz);
+  R disp, vx1, tdisp;
+  bool turns;
+  flight<R>(m.vx, c, a, (R)P.dt, (R)P.v0, P.limited, disp, vx1, turns, tdisp);
+  const R inv_dx = (R)P.inv_dx;
+  R f = m.off + disp * inv_dx;
+  const R fl = m_floor(f);
+  int cell = m.cell + (int)fl;
+  f -= fl;
+  if (f >= R(1)) f = one_below<R>();
+  bool out_lo = cell < 0, out_hi = cell >= P.cells;
+  if (turns) {
+    const R ft = m.off + tdisp * inv_dx;
+    const int ct = m.cell + (int)m_floor(ft);
+    out_lo = out_lo || ct < 0;
+    out_hi = out_hi || ct >= P.cells;
+  }
+  if (!m_finite(f) || !m_finite(vx1)) {
+    err |= ERR_NONFINITE;
+  } else if (out_lo) {
+    note(ev, ev2, 1u << (sp == 0 ? EV_ABS_E_CATH : EV_ABS_I_CATH));
+    if (sp == 1) {
+      // ion-induced secondary emission (Sec. IV): an electron at rest at
+      // the cathode with probability gamma_se, or with the yield of
+      // Eq. (17) at the impact energy; v_x^2 - 2 a x is constant along
+      // the flight, so the ion reaches x = 0 with v_x^2 = vx^2 - 2 a x
+      const U4 r = draw_cold(m.id, step, CH_SEE, C.seed, inst);
+      const bool see = (C.flags & 2u)
+                           ? unif<R>(r.x) < impact_yield<R>(E, (R)P.qm_i, (R)P.dx, m)
+                           : (r.x >> 9) < P.t_see;
+      if (see) {
+        note(ev, ev2, 1u << EV_SEE);
+        Mk<R> e;
+        e.cell = 0;
+        e.off = R(0);
+        e.vx = e.vy = e.vz = R(0);
+        e.id = child(r.z, r.w);
+        o.e[H] = e;
+        o.me |= 1u << H;
+      }
+    }
+  } else if (out_hi) {
+    note(ev, ev2, 1u << (sp == 0 ? EV_ABS_E_ANODE : EV_ABS_I_ANODE));
+  } else {
+    m.cell = cell;
+    m.off = f;
+    m.vx = vx1;
+    // null-collision test: candidates go to the queue
+    const uint32_t u = rn.x >> 9;
+    uint32_t tcand;
+    if (C.fixed) tcand = sp == 0 ? (C.n_chan > 0 ? P.t_fixed[C.n_chan - 1] : 0u) : P.t_fixed_cx;
+    else tcand = sp == 0 ? P.t_null_e : (P.sigma_cx > 0.0 ? P.t_null_cx : 0u);
+    cand = u < tcand;
+    if (!cand) {
+      if (sp == 0) { o.e[H] = m; o.me |= 1u << H; }
+      else { o.i[H] = m; o.mi |= 1u << H; }
+    }
+  }
 }
 
 template <typename R, int MODE>
-__global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
+__global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 4 : 1) k_gen(Ctx<R> C) {
   extern __shared__ uint32_t s_prefix[];  // 2 n_inst + 1 tile offsets (dynamic)
   __shared__ unsigned long long s_hist[2][HWIN];
   __shared__ uint32_t s_gen;
@@ -1096,13 +1224,13 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
   // collide up to WAVE queued candidates and emit the results
   auto run_queue = [&](uint32_t n) {
     LaneOut<R> o;
-    o.ne = o.ni = 0;
+    o.me = o.mi = 0u;
     uint32_t ev = 0, err = 0;
     // the appends of other lanes land before these reads (one wave: LDS
     // operations complete in order; the fence keeps the compiler's order)
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if ((uint32_t)lane < n) {
-      const uint32_t s = (q_head + (uint32_t)lane) % QW;
+      const uint32_t s = ring(q_head, (uint32_t)lane);
       Mk<R> m;
       m.cell = q_cell[wv][s];
       m.off = q_off[wv][s];
@@ -1110,29 +1238,46 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
       m.vy = q_vy[wv][s];
       m.vz = q_vz[wv][s];
       m.id = q_id[wv][s];
-      const InstParams& P = C.ip[W.inst];
+      IP& P = param(C.ip, W.inst);
       if (W.sp == 0) collide_electron(C, P, W.inst, W.step, m, o, ev, err);
       else collide_ion(C, P, W.inst, W.step, m, o, ev, err);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // reads before reuse
-    q_head = (q_head + n) % QW;
+    q_head = ring(q_head, n);
     q_count -= n;
-    next_output(W, C.ip[W.inst]);
-    emit<R, MODE, true>(C, W, win, s_hist, o, ev, err, g, bsel, evw);
+    next_output(W, param(C.ip, W.inst));
+    emit<R, MODE, true>(C, W, win, s_hist, o, ev, 0u, err, g, bsel, evw);
+  };
+  // append marker m to the queue at offset off (< QW) past its head
+  auto q_put = [&](const Mk<R>& m, uint32_t off) {
+    const uint32_t s = ring(q_head, off);
+    q_cell[wv][s] = m.cell;
+    q_off[wv][s] = m.off;
+    q_vx[wv][s] = m.vx;
+    q_vy[wv][s] = m.vy;
+    q_vz[wv][s] = m.vz;
+    q_id[wv][s] = m.id;
   };
 
+  // A wave takes two tiles of its run at once, one marker of each per lane,
+  // when both belong to the same (instance, species): two independent
+  // loads, gathers and flights per lane, and one reservation per species
+  // for both.
   TileCursor cur;
-  for (uint32_t t = t_begin; t < t_end; ++t) {
+  for (uint32_t t = t_begin; t < t_end;) {
     cur.locate(s_prefix, nk, t);
     const int k = cur.kc, inst = k >> 1, sp = k & 1;
-    const InstParams& P = C.ip[inst];
-    int part;
-    uint32_t first;
-    cur.place(t, P.parts, part, first);
-    const uint32_t n_in = C.counts[cidx(C.n_inst, g % 3u, inst, sp, part)];
-    const uint32_t idx = first + (uint32_t)tid;
-    const bool valid = idx < n_in;
-    const int64_t pbase = P.seg + (int64_t)part * P.cap_p;
+    IP& P = param(C.ip, inst);
+    const bool two = t + 1u < t_end && t + 1u < cur.kend;
+    int part0, part1 = 0;
+    uint32_t first0, first1 = 0u;
+    cur.place(t, P.parts, part0, first0);
+    if (two) cur.place(t + 1u, P.parts, part1, first1);
+    const uint32_t n0 = count_in(C.counts, C.n_inst, g, inst, sp, part0);
+    const uint32_t n1 = two ? count_in(C.counts, C.n_inst, g, inst, sp, part1) : 0u;
+    const uint32_t idx0 = first0 + (uint32_t)tid, idx1 = first1 + (uint32_t)tid;
+    const int64_t pb0 = P.seg + (int64_t)part0 * P.cap_p;
+    const int64_t pb1 = P.seg + (int64_t)part1 * P.cap_p;
     if (inst != W.inst || sp != W.sp) {
       // new (instance, species): collide what is queued for the old one
       while (q_count > 0) run_queue(q_count < (uint32_t)WAVE ? q_count : (uint32_t)WAVE);
@@ -1140,7 +1285,7 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
         // flush the old deposit window, anchor the new one a quarter window
         // below the tile's first marker
         if (win.inst >= 0) dep_flush(C, s_hist, win, s_evw);
-        int c0 = first < n_in ? C.buf[bsel][sp].cell[pbase + first] : 0;
+        int c0 = first0 < n0 ? C.buf[bsel][sp].cell[pb0 + first0] : 0;
         int anchor = c0 - HWIN / 4;
         const int top = P.cells + 1 - HWIN;
         anchor = anchor > top ? top : anchor;
@@ -1154,113 +1299,48 @@ __global__ void __launch_bounds__(BLOCK) k_gen(Ctx<R> C) {
       W.pop = MODE == MODE_STEP ? S0.popmode : POP_NONE;
     }
     const Soa<R> in = C.buf[bsel][sp];
-    const R v0 = (R)P.v0;
-    const int limited = P.limited;
-    const uint32_t step = W.step;
 
-    Mk<R> m;
-    if (idx < (uint32_t)P.cap_p) {  // inside the partition: no wait for n_in
-      const int64_t s = pbase + idx;
-      m.cell = in.cell[s];
-      m.off = in.off[s];
-      m.vx = in.vx[s];
-      m.vy = in.vy[s];
-      m.vz = in.vz[s];
-      m.id = in.id[s];
+    // loads inside the partitions need not wait for the counts
+    Mk<R> m0, m1;
+    if (idx0 < (uint32_t)P.cap_p) {
+      const int64_t s = pb0 + idx0;
+      m0.cell = in.cell[s];
+      m0.off = in.off[s];
+      m0.vx = in.vx[s];
+      m0.vy = in.vy[s];
+      m0.vz = in.vz[s];
+      m0.id = in.id[s];
+    }
+    if (two && idx1 < (uint32_t)P.cap_p) {
+      const int64_t s = pb1 + idx1;
+      m1.cell = in.cell[s];
+      m1.off = in.off[s];
+      m1.vx = in.vx[s];
+      m1.vy = in.vy[s];
+      m1.vz = in.vz[s];
+      m1.id = in.id[s];
     }
     LaneOut<R> o;
-    o.ne = o.ni = 0;
-    uint32_t ev = 0, err = 0;
-    bool cand = false;
-
-    if (valid && MODE == MODE_REFRESH) {
-      if (sp == 0) { o.e[0] = m; o.ne = 1; }
-      else { o.i1 = m; o.ni = 1; }
-    } else if (valid) {
-      // gather at x^n and fly; the null-collision draw does not depend on the
-      // field and overlaps the gather
-      const R* E = C.E + (size_t)(g % 2u) * C.total_nodes + P.node;
-      const R e0 = E[m.cell], e1 = E[m.cell + 1];
-      const U4 rn = draw(m.id, step, sp == 0 ? (uint32_t)CH_COLL : (uint32_t)CH_CX, C.seed, inst);
-      const R Ep = e0 + m.off * (e1 - e0);
-      const R a = (R)(sp == 0 ? P.qm_e : P.qm_i) * Ep;
-      const R c = Fm<R>::sqrt(m.vy * m.vy + m.vz * m.vz);
-      R disp, vx1, tdisp;
-      bool turns;
-      flight<R>(m.vx, c, a, (R)P.dt, v0, limited, disp, vx1, turns, tdisp);
-      const R inv_dx = (R)P.inv_dx;
-      R f = m.off + disp * inv_dx;
-      const R fl = m_floor(f);
-      int cell = m.cell + (int)fl;
-      f -= fl;
-      if (f >= R(1)) f = one_below<R>();
-      bool out_lo = cell < 0, out_hi = cell >= P.cells;
-      if (turns) {
-        const R ft = m.off + tdisp * inv_dx;
-        const int ct = m.cell + (int)m_floor(ft);
-        out_lo = out_lo || ct < 0;
-        out_hi = out_hi || ct >= P.cells;
-      }
-      if (!m_finite(f) || !m_finite(vx1)) {
-        err |= ERR_NONFINITE;
-      } else if (out_lo) {
-        ev |= 1u << (sp == 0 ? EV_ABS_E_CATH : EV_ABS_I_CATH);
-        if (sp == 1) {
-          // ion-induced secondary emission (Sec. IV): an electron at rest at
-          // the cathode with probability gamma_se, or with the yield of
-          // Eq. (17) at the impact energy; v_x^2 - 2 a x is constant along
-          // the flight, so the ion reaches x = 0 with v_x^2 = vx^2 - 2 a x
-          const U4 r = draw_cold(m.id, step, CH_SEE, C.seed, inst);
-          const bool see = (C.flags & 2u)
-                               ? unif<R>(r.x) < impact_yield<R>(C.E + (size_t)(g % 2u) * C.total_nodes + P.node,
-                                                               (R)P.qm_i, (R)P.dx, m)
-                               : (r.x >> 9) < P.t_see;
-          if (see) {
-            ev |= 1u << EV_SEE;
-            Mk<R> e;
-            e.cell = 0;
-            e.off = R(0);
-            e.vx = e.vy = e.vz = R(0);
-            e.id = child(r.z, r.w);
-            o.e[0] = e;
-            o.ne = 1;
-          }
-        }
-      } else if (out_hi) {
-        ev |= 1u << (sp == 0 ? EV_ABS_E_ANODE : EV_ABS_I_ANODE);
-      } else {
-        m.cell = cell;
-        m.off = f;
-        m.vx = vx1;
-        // null-collision test: candidates go to the queue
-        const uint32_t u = rn.x >> 9;
-        uint32_t tcand;
-        if (C.fixed) tcand = sp == 0 ? (C.n_chan > 0 ? P.t_fixed[C.n_chan - 1] : 0u) : P.t_fixed_cx;
-        else tcand = sp == 0 ? P.t_null_e : (P.sigma_cx > 0.0 ? P.t_null_cx : 0u);
-        cand = u < tcand;
-        if (!cand) {
-          if (sp == 0) { o.e[0] = m; o.ne = 1; }
-          else { o.i1 = m; o.ni = 1; }
-        }
-      }
-    }
+    o.me = o.mi = 0u;
+    uint32_t ev = 0, ev2 = 0, err = 0;
+    bool cand0 = false, cand1 = false;
+    advance<R, MODE, 0>(C, P, inst, sp, g, W.step, idx0 < n0, m0, o, ev, ev2, err, cand0);
+    // the second marker's arithmetic after the first's (its loads are in
+    // flight meanwhile): interleaving the two flights costs registers
+    __builtin_amdgcn_sched_barrier(0);
+    advance<R, MODE, 1>(C, P, inst, sp, g, W.step, two && idx1 < n1, m1, o, ev, ev2, err, cand1);
     if (MODE == MODE_STEP) {
-      // append the wave's candidates to its queue
-      const unsigned long long bc = __ballot(cand);
-      if (cand) {
-        const uint32_t s = (q_head + q_count + (uint32_t)__popcll(bc & lt)) % QW;
-        q_cell[wv][s] = m.cell;
-        q_off[wv][s] = m.off;
-        q_vx[wv][s] = m.vx;
-        q_vy[wv][s] = m.vy;
-        q_vz[wv][s] = m.vz;
-        q_id[wv][s] = m.id;
-      }
-      q_count += (uint32_t)__popcll(bc);
+      // append the wave's candidates to its queue (fewer than WAVE wait)
+      const unsigned long long b0 = __ballot(cand0), b1 = __ballot(cand1);
+      const uint32_t c0 = (uint32_t)__popcll(b0);
+      if (cand0) q_put(m0, q_count + (uint32_t)__popcll(b0 & lt));
+      if (cand1) q_put(m1, q_count + c0 + (uint32_t)__popcll(b1 & lt));
+      q_count += c0 + (uint32_t)__popcll(b1);
     }
     next_output(W, P);
-    emit<R, MODE, false>(C, W, win, s_hist, o, ev, err, g, bsel, evw);
-    if (MODE == MODE_STEP && q_count >= (uint32_t)WAVE) run_queue((uint32_t)WAVE);
+    emit<R, MODE, false>(C, W, win, s_hist, o, ev, ev2, err, g, bsel, evw);
+    while (MODE == MODE_STEP && q_count >= (uint32_t)WAVE) run_queue((uint32_t)WAVE);
+    t += two ? 2u : 1u;
   }
   while (q_count > 0) run_queue(q_count < (uint32_t)WAVE ? q_count : (uint32_t)WAVE);
   if (win.inst >= 0) dep_flush(C, s_hist, win, s_evw);
@@ -1289,7 +1369,7 @@ __device__ __forceinline__ void sort_state(const Ctx<R>& C, uint32_t& g, uint32_
 template <typename R>
 __device__ __forceinline__ uint32_t pair_count(const Ctx<R>& C, uint32_t g, int inst, int sp) {
   uint32_t n = 0;
-  for (int p = 0; p < C.ip[inst].parts; ++p) n += C.counts[cidx(C.n_inst, g % 3u, inst, sp, p)];
+  for (int p = 0; p < param(C.ip, inst).parts; ++p) n += C.counts[cidx(C.n_inst, g % 3u, inst, sp, p)];
   return n;
 }
 
@@ -1312,7 +1392,7 @@ __global__ void __launch_bounds__(BLOCK) k_sort_count(Ctx<R> C) {
   int k_open = -1;
   auto flush = [&]() {
     __syncthreads();
-    const InstParams& P = C.ip[k_open >> 1];
+    IP& P = param(C.ip, k_open >> 1);
     uint32_t* dst = C.sort_hist + (size_t)(k_open & 1) * C.total_nodes + P.node;
     for (int c = tid; c < P.cells; c += BLOCK) {
       const uint32_t v = s_hist[c];
@@ -1330,7 +1410,7 @@ __global__ void __launch_bounds__(BLOCK) k_sort_count(Ctx<R> C) {
       k_open = cur.kc;
     }
     const int inst = cur.kc >> 1, sp = cur.kc & 1;
-    const InstParams& P = C.ip[inst];
+    IP& P = param(C.ip, inst);
     int part;
     uint32_t first;
     cur.place(t, P.parts, part, first);
@@ -1347,7 +1427,7 @@ template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_sort_scan(Ctx<R> C) {
   __shared__ double s_scan[4];
   const int k = blockIdx.x, inst = k >> 1, sp = k & 1, tid = threadIdx.x;
-  const InstParams& P = C.ip[inst];
+  IP& P = param(C.ip, inst);
   uint32_t* hist = C.sort_hist + (size_t)sp * C.total_nodes + P.node;
   uint32_t* cursor = C.sort_cur + (size_t)sp * C.total_nodes + P.node;
   const int chunk = (P.cells + BLOCK - 1) / BLOCK;
@@ -1390,7 +1470,7 @@ __global__ void __launch_bounds__(BLOCK) k_sort_scatter(Ctx<R> C) {
     cur.locate(s_prefix, nk, t);
     const int k = cur.kc, inst = k >> 1, sp = k & 1;
     const uint32_t run_end = min(t_end, cur.kend);
-    const InstParams& P = C.ip[inst];
+    IP& P = param(C.ip, inst);
     const Soa<R> in = C.buf[bsel][sp], out = C.buf[1u - bsel][sp];
     const uint32_t n = pair_count(C, g, inst, sp);
     const uint32_t q = (n + (uint32_t)P.parts - 1) / (uint32_t)P.parts;
@@ -1445,7 +1525,7 @@ __global__ void k_sort_commit(Ctx<R> C) {
   sort_state(C, g, bsel);
   if (k < 2 * C.n_inst) {
     const int inst = k >> 1, sp = k & 1;
-    const InstParams& P = C.ip[inst];
+    IP& P = param(C.ip, inst);
     const uint32_t n = pair_count(C, g, inst, sp);
     const uint32_t q = (n + (uint32_t)P.parts - 1) / (uint32_t)P.parts;
     for (int p = 0; p < P.parts; ++p) {
@@ -1469,7 +1549,7 @@ template <typename R>
 __global__ void k_seed(Ctx<R> C, int inst, int mode, int64_t n, double sigma_v, uint32_t bsel) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  const InstParams& P = C.ip[inst];
+  IP& P = param(C.ip, inst);
   const Soa<R> o = C.buf[bsel][0];
   // seed k goes to partition k mod P, slot k / P
   const int64_t s = P.seg + (k % P.parts) * P.cap_p + k / P.parts;
