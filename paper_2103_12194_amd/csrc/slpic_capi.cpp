@@ -798,9 +798,6 @@ int slpic_step(slpic_t* h, int n_steps) {
 // graph holds the old grid and is dropped.
 static int set_grid(slpic_t* h, int grid) {
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  const unsigned long long wgc = (unsigned long long)h->gen * (unsigned long long)grid;
-  HIPCHK(h, hipMemcpy(h->ws + h->L.glob + offsetof(Global, wgc), &wgc, sizeof(wgc),
-                      hipMemcpyHostToDevice));
   h->grid = grid;
   h->c32.grid = grid;
   h->c64.grid = grid;

@@ -87,13 +87,14 @@ struct InstState {
   int32_t popmode;
 };
 
-// Handle-wide device words.  wgc counts workgroup starts of the particle
-// kernel: every launch has exactly `grid` workgroups, so a workgroup's
-// generation is its ticket / grid, and the tail kernel that follows reads
-// the generation as wgc / grid - 1.  Per-step state is buffered by
-// generation: a launch reads generation g and writes g + 1.
+// Handle-wide device words.  Per-step state is buffered by generation: a
+// launch pair reads generation g and writes g + 1.  The particle kernel
+// reads g from cur_gen (written only by tail kernels) and passes it to the
+// tail kernel in tail_gen; the tail kernel sets cur_gen to g + 1.  Launches
+// therefore take no host arguments, so a captured graph can replay them.
 struct Global {
-  unsigned long long wgc;
+  uint32_t tail_gen;    // generation the last particle kernel advanced from
+  uint32_t pad;
   uint32_t cur_gen;     // generation of the current state (set by tails)
   uint32_t bufsel[2];   // particle buffer holding generation g's markers
   uint32_t err;

@@ -495,7 +495,7 @@ __global__ void __launch_bounds__(BLOCK) k_tail(Ctx<R> C) {
   __shared__ InstState s_cur;
   __shared__ uint32_t s_bs;
   const int inst = blockIdx.x, t = threadIdx.x;
-  const uint32_t g = (uint32_t)(C.g->wgc / (unsigned long long)C.grid) - 1u;
+  const uint32_t g = C.g->tail_gen;
   IP& P = param(C.ip, inst);
   const int N = P.cells, node = P.node;
   const uint32_t sn = (g + 1) % 2u;
@@ -1193,9 +1193,13 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 4 : 1) k_gen(Ctx<R> C)
   __shared__ uint64_t q_id[NWAVE][QW];
 
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+  // the generation to advance from: set by the previous tail kernel, and
+  // handed to the next one through tail_gen (tail workgroups cannot read
+  // cur_gen, which the first of them to finish moves on)
   if (tid == 0) {
-    const unsigned long long ticket = atomicAdd(&C.g->wgc, 1ull);
-    s_gen = (uint32_t)(ticket / (unsigned long long)C.grid);
+    const uint32_t gg = C.g->cur_gen;
+    s_gen = gg;
+    if (blockIdx.x == 0) C.g->tail_gen = gg;
   }
   if (tid < NWAVE * NEV) s_evw[tid / NEV][tid % NEV] = 0u;
   for (int i = tid; i < 2 * HWIN; i += BLOCK) s_hist[i / HWIN][i % HWIN] = 0ull;
