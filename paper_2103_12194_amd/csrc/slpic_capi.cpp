@@ -59,7 +59,7 @@ uint32_t prob_threshold(double P) {
 }
 
 struct Layout {
-  size_t ip, st, counts, ev, acc, E, E64, phi, rho, scratch, ring, inst_err, sort_hist, sort_cur,
+  size_t ip, st, counts, tiles, ev, acc, E, E64, phi, rho, scratch, ring, inst_err, sort_hist, sort_cur,
       glob, xs_e, xs_sig, xs_thr, xs_kind;
   size_t part[2][2][6];  // [buffer][species][array]
   size_t total;
@@ -127,6 +127,7 @@ bool make_layout(const slpic_config* cfg, const slpic_instance* inst, int n_inst
   L.inst_err = take(sizeof(uint32_t) * n_inst);
   L.sort_hist = take(sizeof(uint32_t) * 2 * (size_t)nodes);
   L.sort_cur = take(sizeof(uint32_t) * 2 * (size_t)nodes);
+  L.tiles = take(sizeof(uint32_t) * 3 * 2 * (size_t)n_inst);
   L.glob = take(sizeof(Global));
   const int ng = xs->n_grid, nc = std::max(xs->n_chan, 1);
   L.xs_e = take(rs * ng);
@@ -338,6 +339,7 @@ void fill_ctx(slpic_t* h, Ctx<R>& C) {
   C.inst_err = reinterpret_cast<uint32_t*>(w + L.inst_err);
   C.sort_hist = reinterpret_cast<uint32_t*>(w + L.sort_hist);
   C.sort_cur = reinterpret_cast<uint32_t*>(w + L.sort_cur);
+  C.tiles = reinterpret_cast<uint32_t*>(w + L.tiles);
   C.g = reinterpret_cast<Global*>(w + L.glob);
   C.xs_e = reinterpret_cast<const R*>(w + L.xs_e);
   C.xs_sig = reinterpret_cast<const R*>(w + L.xs_sig);
@@ -565,6 +567,9 @@ int load_impl(slpic_t* h, int inst, int sp, int64_t n, const int32_t* cell, cons
     HIPCHK(h, hipMemcpy(h->ws + count_offset(h, slot3, inst, sp, p), &cnt, sizeof(uint32_t),
                         hipMemcpyHostToDevice));
   }
+  const uint32_t tl = pair_tiles((uint32_t)((n + P.parts - 1) / P.parts), P.parts);
+  HIPCHK(h, hipMemcpy(h->ws + h->L.tiles + sizeof(uint32_t) * (((size_t)slot3 * h->n_inst + inst) * 2 + sp),
+                      &tl, sizeof(uint32_t), hipMemcpyHostToDevice));
   rc = launch_gen_any(h, MODE_REFRESH);
   if (rc) return rc;
   HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -699,6 +704,7 @@ int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst
   // constant and initial state: generation 0, buffer 0, seeds in counts[0]
   std::vector<InstState> st(2 * n_inst);
   std::vector<uint32_t> counts((size_t)CSTRIDE * 3 * 2 * MAX_PART * n_inst, 0u);
+  std::vector<uint32_t> tiles((size_t)3 * 2 * n_inst, 0u);
   for (int i = 0; i < n_inst; ++i) {
     st[i] = InstState{cfg->w_j0, 0u, POP_NONE};
     st[n_inst + i] = st[i];
@@ -706,6 +712,7 @@ int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst
     const int P = L.parts[i];
     for (int p = 0; p < P; ++p)  // seed k sits in partition k mod P
       counts[((size_t)i * 2 * MAX_PART + p) * CSTRIDE] = (uint32_t)(ns / P + (p < ns % P ? 1 : 0));
+    tiles[2 * (size_t)i] = pair_tiles((uint32_t)((ns + P - 1) / P), P);
   }
   Global G;
   std::memset(&G, 0, sizeof(G));
@@ -715,6 +722,7 @@ int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst
   e = up(L.ip, h->ip.data(), sizeof(InstParams) * n_inst);
   if (e == hipSuccess) e = up(L.st, st.data(), sizeof(InstState) * st.size());
   if (e == hipSuccess) e = up(L.counts, counts.data(), sizeof(uint32_t) * counts.size());
+  if (e == hipSuccess) e = up(L.tiles, tiles.data(), sizeof(uint32_t) * tiles.size());
   if (e == hipSuccess) e = up(L.glob, &G, sizeof(G));
   if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.ev, 0, sizeof(unsigned long long) * NEV * NSLOT * n_inst, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.acc, 0, sizeof(unsigned long long) * 2 * NSLOT * L.total_nodes, h->stream);

@@ -21,6 +21,13 @@ constexpr int CSTRIDE = 64;       // uint32 slots between compaction counters:
 constexpr int NSLOT = 4;          // copies of each global deposit node
 constexpr int HWIN = 1024;        // nodes in a workgroup's LDS deposit window
 
+// Tiles an (instance, species) takes in the tile space of a step: every
+// partition gets as many as the fullest one needs, so that tile j of the
+// pair reads chunk j mod T of partition j / T.
+__host__ __device__ inline uint32_t pair_tiles(uint32_t max_count, int parts) {
+  return ((max_count + (uint32_t)BLOCK - 1u) / (uint32_t)BLOCK) * (uint32_t)parts;
+}
+
 // event counter slots (order of the public slpic_stats fields)
 enum Ev {
   EV_ELASTIC = 0, EV_EXCIT, EV_IONIZ, EV_CX, EV_ABS_E_CATH, EV_ABS_E_ANODE,
@@ -132,6 +139,7 @@ struct Ctx {
   int gen_lds;               // dynamic LDS bytes of the particle kernel
   uint32_t* sort_hist;       // [2][total_nodes] cell counts of the cell sort
   uint32_t* sort_cur;        // [2][total_nodes] cursors of the cell sort
+  uint32_t* tiles;           // [3][n_inst][2] tiles of each (instance, species)
   int max_cells;             // largest cell count of the batch
   int sort_lds1, sort_lds2;  // dynamic LDS bytes of the sort's count and scatter
 };

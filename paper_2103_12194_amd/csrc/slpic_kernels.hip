@@ -492,6 +492,7 @@ __global__ void __launch_bounds__(BLOCK) k_tail(Ctx<R> C) {
   __shared__ double sh[4 * 3];
   __shared__ unsigned long long s_ev[NEV];
   __shared__ uint32_t s_cnt[2][2];         // [in, out][species]
+  __shared__ uint32_t s_mx[2];             // fullest output partition per species
   __shared__ InstState s_cur;
   __shared__ uint32_t s_bs;
   const int inst = blockIdx.x, t = threadIdx.x;
@@ -501,6 +502,7 @@ __global__ void __launch_bounds__(BLOCK) k_tail(Ctx<R> C) {
   const uint32_t sn = (g + 1) % 2u;
   if (t < NEV) s_ev[t] = 0ull;
   if (t < 4) s_cnt[t / 2][t % 2] = 0u;
+  if (t < 2) s_mx[t] = 0u;
   if (t == 0) {
     s_cur = C.st[(g % 2u) * C.n_inst + inst];
     s_bs = C.g->bufsel[g % 2u];
@@ -523,24 +525,39 @@ __global__ void __launch_bounds__(BLOCK) k_tail(Ctx<R> C) {
     unsigned long long* acc_e = C.acc + node;
     unsigned long long* acc_i = C.acc + (size_t)NSLOT * tn + node;
     double* rho = C.rho + (size_t)sn * C.total_nodes + node;
-    for (int i = t; i <= N; i += BLOCK) {
-      unsigned long long ae = 0ull, ai = 0ull;
+    // the loads of UN nodes per thread are issued before any of their
+    // clearing stores, so that they are in flight together
+    constexpr int UN = 4;
+    for (int i0 = t; i0 <= N; i0 += UN * BLOCK) {
+      unsigned long long ae[UN], ai[UN];
 #pragma unroll
-      for (int q = 0; q < NSLOT; ++q) {
-        ae += acc_e[q * tn + i];
-        ai += acc_i[q * tn + i];
+      for (int u = 0; u < UN; ++u) {
+        // past the last node, read the last node again (no branch around
+        // the loads) and drop the sum
+        const int i = min(i0 + u * BLOCK, N);
+        ae[u] = ai[u] = 0ull;
+#pragma unroll
+        for (int q = 0; q < NSLOT; ++q) {
+          ae[u] += acc_e[q * tn + i];
+          ai[u] += acc_i[q * tn + i];
+        }
       }
 #pragma unroll
-      for (int q = 0; q < NSLOT; ++q) {
-        acc_e[q * tn + i] = 0ull;
-        acc_i[q * tn + i] = 0ull;
+      for (int u = 0; u < UN; ++u) {
+        const int i = i0 + u * BLOCK;
+        if (i > N) break;
+#pragma unroll
+        for (int q = 0; q < NSLOT; ++q) {
+          acc_e[q * tn + i] = 0ull;
+          acc_i[q * tn + i] = 0ull;
+        }
+        se += (double)ae[u];
+        si += (double)ai[u];
+        double r = ((double)ai[u] - (double)ae[u]) * qvol;
+        if (i == 0 || i == N) r *= 2.0;  // half cells at the electrodes
+        rho[i] = r;
+        s_S[i] = r;
       }
-      se += (double)ae;
-      si += (double)ai;
-      double r = ((double)ai - (double)ae) * qvol;
-      if (i == 0 || i == N) r *= 2.0;  // half cells at the electrodes
-      rho[i] = r;
-      s_S[i] = r;
     }
     if (t < NEV * NSLOT) {
       unsigned long long* e = C.ev + (size_t)inst * NEV * NSLOT + t;
@@ -564,6 +581,7 @@ __global__ void __launch_bounds__(BLOCK) k_tail(Ctx<R> C) {
         *cf = 0u;
         atomicAdd(&s_cnt[0][sp], cin);
         atomicAdd(&s_cnt[1][sp], c);
+        atomicMax(&s_mx[sp], c);
       }
     }
   }
@@ -633,6 +651,8 @@ __global__ void __launch_bounds__(BLOCK) k_tail(Ctx<R> C) {
       row.err = C.inst_err[inst];
       C.ring[(size_t)inst * RING + (nx.step - 1) % RING] = row;
     }
+    for (int sp = 0; sp < 2; ++sp)
+      C.tiles[(size_t)((g + 1) % 3u) * 2 * C.n_inst + 2 * inst + sp] = pair_tiles(s_mx[sp], P.parts);
     C.g->bufsel[(g + 1) % 2u] = MODE == MODE_STEP ? 1u - s_bs : s_bs;
     C.g->cur_gen = g + 1;
   }
@@ -707,23 +727,12 @@ __device__ __forceinline__ void dep_flush(const Ctx<R>& C, unsigned long long (*
 template <typename R>
 __device__ void tile_prefix(const Ctx<R>& C, uint32_t g, uint32_t* s_prefix, double* s_scan) {
   const int tid = threadIdx.x, nk = 2 * C.n_inst;
-  // per (instance, species): the largest partition count, read with one
-  // thread per (instance, species, partition) so the loads overlap
-  for (int k = tid; k <= nk; k += BLOCK) s_prefix[k] = 0u;
-  __syncthreads();
-  for (int q = tid; q < nk * MAX_PART; q += BLOCK) {
-    const int k = q / MAX_PART, p = q % MAX_PART;
-    if (p < param(C.ip, k >> 1).parts) {
-      const uint32_t n = C.counts[cidx(C.n_inst, g % 3u, k >> 1, k & 1, p)];
-      if (n) atomicMax(&s_prefix[k + 1], n);
-    }
-  }
-  __syncthreads();
+  // per (instance, species): its tile count, set with the partition counts
+  // (by the tail kernel, the cell sort or the host)
   const int per = (nk + BLOCK - 1) / BLOCK;
   uint32_t loc = 0;
   for (int k = tid * per; k < min(nk, (tid + 1) * per); ++k) {
-    const uint32_t mx = s_prefix[k + 1];
-    const uint32_t tl = ((mx + BLOCK - 1) / BLOCK) * (uint32_t)param(C.ip, k >> 1).parts;
+    const uint32_t tl = C.tiles[(size_t)(g % 3u) * nk + k];
     s_prefix[k + 1] = tl;
     loc += tl;
   }
@@ -1536,6 +1545,7 @@ __global__ void k_sort_commit(Ctx<R> C) {
       const uint32_t lo = (uint32_t)p * q;
       C.counts[cidx(C.n_inst, g % 3u, inst, sp, p)] = lo < n ? min(q, n - lo) : 0u;
     }
+    C.tiles[(size_t)(g % 3u) * 2 * C.n_inst + k] = pair_tiles(min(q, n), P.parts);
   }
   // every thread has read the counts above before one of them switches the
   // buffer: the switch is made by a second launch (see launch_sort)
