@@ -8,6 +8,7 @@
 namespace slpic {
 
 constexpr int BLOCK = 256;        // threads per workgroup = markers per tile
+constexpr int TBLOCK = 1024;      // threads of a tail-kernel workgroup (one per instance)
 constexpr int WAVE = 64;
 constexpr int MAX_INST = 1024;
 constexpr int MAX_CHAN = 8;
@@ -18,7 +19,7 @@ constexpr int CSTRIDE = 64;       // uint32 slots between compaction counters:
                                   // one 256-byte line each, so that the
                                   // reservations of one (instance, species)
                                   // spread over memory channels
-constexpr int NSLOT = 4;          // copies of each global deposit node
+constexpr int NSLOT = 1;          // copies of each global deposit node
 constexpr int HWIN = 1024;        // nodes in a workgroup's LDS deposit window
 
 // Tiles an (instance, species) takes in the tile space of a step: every

@@ -444,12 +444,14 @@ __device__ __forceinline__ uint32_t count_in(const uint32_t* counts, int n_inst,
   return ((CU*)counts)[cidx(n_inst, g % 3u, inst, sp, p)];
 }
 
-// Exclusive prefix sums of NV values over the 256 threads of a workgroup:
-// wave-level shuffles, then one exchange of the four wave totals through
-// LDS (sh holds 4 NV doubles).  ex[] receives the prefixes, tot[] the sums.
-template <int NV>
+// Exclusive prefix sums of NV values over the NW waves of a workgroup:
+// wave-level shuffles, then the first wave scans the wave totals (sh holds
+// (NW + 1) NV doubles: each wave's prefix, then the sums).  ex[] receives
+// the prefixes, tot[] the sums.
+template <int NV, int NW = BLOCK / WAVE>
 __device__ __forceinline__ void block_scan(const double (&v)[NV], double (&ex)[NV],
                                            double (&tot)[NV], double* sh) {
+  static_assert(NW <= WAVE, "one wave scans the wave totals");
   const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
   double inc[NV];
 #pragma unroll
@@ -466,75 +468,72 @@ __device__ __forceinline__ void block_scan(const double (&v)[NV], double (&ex)[N
 #pragma unroll
     for (int k = 0; k < NV; ++k) sh[wave * NV + k] = inc[k];
   __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const double x = lane < NW ? sh[lane * NV + k] : 0.0;
+      double w = x;
+#pragma unroll
+      for (int d = 1; d < NW; d <<= 1) {
+        const double u = __shfl_up(w, d);
+        if (lane >= d) w += u;
+      }
+      if (lane < NW) sh[lane * NV + k] = w - x;
+      if (lane == NW - 1) sh[NW * NV + k] = w;
+    }
+  }
+  __syncthreads();
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    double base = 0.0, t = 0.0;
-    for (int w = 0; w < BLOCK / WAVE; ++w) {
-      const double sw = sh[w * NV + k];
-      if (w < wave) base += sw;
-      t += sw;
-    }
     const double prev = __shfl_up(inc[k], 1);
-    ex[k] = base + (lane == 0 ? 0.0 : prev);
-    tot[k] = t;
+    ex[k] = sh[wave * NV + k] + (lane == 0 ? 0.0 : prev);
+    tot[k] = sh[NW * NV + k];
   }
   __syncthreads();
 }
 
-// One workgroup per instance, launched after the particle kernel: charge
-// density from the fixed-point deposit, Poisson solve, statistics row,
-// population-control decision for the next step and the generation switch.
-// Every global load is issued up front; the prefix sums run in LDS
-// (dynamic shared memory of cells + 1 doubles).
+// One workgroup of TBLOCK threads per instance, launched after the particle
+// kernel: charge density from the fixed-point deposit, Poisson solve,
+// statistics row, population-control decision for the next step and the
+// generation switch.  Every global load is issued up front; the prefix sums
+// run in LDS (dynamic shared memory of cells + 1 doubles).
 template <typename R, int MODE>
-__global__ void __launch_bounds__(BLOCK) k_tail(Ctx<R> C) {
+__global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
   extern __shared__ double s_S[];          // rho, then S
-  __shared__ double sh[4 * 3];
+  __shared__ double sh[(TBLOCK / WAVE + 1) * 3];
   __shared__ unsigned long long s_ev[NEV];
   __shared__ uint32_t s_cnt[2][2];         // [in, out][species]
   __shared__ uint32_t s_mx[2];             // fullest output partition per species
+  __shared__ uint32_t s_err;               // capacity errors found here
   __shared__ InstState s_cur;
   __shared__ uint32_t s_bs;
   const int inst = blockIdx.x, t = threadIdx.x;
-  const uint32_t g = C.g->tail_gen;
   IP& P = param(C.ip, inst);
   const int N = P.cells, node = P.node;
-  const uint32_t sn = (g + 1) % 2u;
   if (t < NEV) s_ev[t] = 0ull;
   if (t < 4) s_cnt[t / 2][t % 2] = 0u;
   if (t < 2) s_mx[t] = 0u;
-  if (t == 0) {
-    s_cur = C.st[(g % 2u) * C.n_inst + inst];
-    s_bs = C.g->bufsel[g % 2u];
-  }
+  if (t == 0) s_err = 0u;
   __syncthreads();
-  const InstState cur = s_cur;
-  const double factor = MODE == MODE_STEP
-                            ? (cur.popmode == POP_ROULETTE ? 2.0 : (cur.popmode == POP_SPLIT ? 0.5 : 1.0))
-                            : 1.0;
-  const double wj = cur.w_j * factor;
-  const double unit = 1.0 / (double)(1ull << C.dep_shift);
-  const double qvol = QE * wj * unit / (P.area * P.dx);
 
-  // charge density at the nodes (each of the NSLOT copies read with
-  // consecutive threads on consecutive nodes), species totals; events and
-  // marker counts alongside
+  // The loads that do not need the generation go first, so that they
+  // overlap the loads that do: the deposit slots (each of the NSLOT copies
+  // read with consecutive threads on consecutive nodes, UN nodes per thread
+  // in flight together, then cleared) as raw fixed-point differences in
+  // LDS with the species totals, and the step's event slots.
   double se = 0.0, si = 0.0;
+  const size_t tn = (size_t)C.total_nodes;
   {
-    const size_t tn = (size_t)C.total_nodes;
     unsigned long long* acc_e = C.acc + node;
     unsigned long long* acc_i = C.acc + (size_t)NSLOT * tn + node;
-    double* rho = C.rho + (size_t)sn * C.total_nodes + node;
-    // the loads of UN nodes per thread are issued before any of their
-    // clearing stores, so that they are in flight together
-    constexpr int UN = 4;
-    for (int i0 = t; i0 <= N; i0 += UN * BLOCK) {
+    constexpr int UN = 5;  // a 4096-cell gap in one round
+    for (int i0 = t; i0 <= N; i0 += UN * TBLOCK) {
       unsigned long long ae[UN], ai[UN];
 #pragma unroll
       for (int u = 0; u < UN; ++u) {
         // past the last node, read the last node again (no branch around
         // the loads) and drop the sum
-        const int i = min(i0 + u * BLOCK, N);
+        const int i = min(i0 + u * TBLOCK, N);
         ae[u] = ai[u] = 0ull;
 #pragma unroll
         for (int q = 0; q < NSLOT; ++q) {
@@ -544,7 +543,7 @@ __global__ void __launch_bounds__(BLOCK) k_tail(Ctx<R> C) {
       }
 #pragma unroll
       for (int u = 0; u < UN; ++u) {
-        const int i = i0 + u * BLOCK;
+        const int i = i0 + u * TBLOCK;
         if (i > N) break;
 #pragma unroll
         for (int q = 0; q < NSLOT; ++q) {
@@ -553,10 +552,7 @@ __global__ void __launch_bounds__(BLOCK) k_tail(Ctx<R> C) {
         }
         se += (double)ae[u];
         si += (double)ai[u];
-        double r = ((double)ai[u] - (double)ae[u]) * qvol;
-        if (i == 0 || i == N) r *= 2.0;  // half cells at the electrodes
-        rho[i] = r;
-        s_S[i] = r;
+        s_S[i] = (double)ai[u] - (double)ae[u];
       }
     }
     if (t < NEV * NSLOT) {
@@ -565,38 +561,67 @@ __global__ void __launch_bounds__(BLOCK) k_tail(Ctx<R> C) {
       *e = 0ull;
       if (v) atomicAdd(&s_ev[t / NSLOT], v);
     }
-    if (t < 2 * MAX_PART) {
-      const int sp = t / MAX_PART, p = t % MAX_PART;
-      if (p < P.parts) {
-        uint32_t* ci = C.counts + cidx(C.n_inst, g % 3u, inst, sp, p);
-        uint32_t* co = C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, sp, p);
-        uint32_t* cf = C.counts + cidx(C.n_inst, (g + 2) % 3u, inst, sp, p);
-        const uint32_t cin = *ci;
-        uint32_t c = MODE == MODE_STEP ? *co : cin;
-        if (c > (uint32_t)P.cap_p) {
-          atomicOr(C.inst_err + inst, (uint32_t)ERR_CAPACITY);
-          c = (uint32_t)P.cap_p;
-        }
-        *co = c;
-        *cf = 0u;
-        atomicAdd(&s_cnt[0][sp], cin);
-        atomicAdd(&s_cnt[1][sp], c);
-        atomicMax(&s_mx[sp], c);
+  }
+  // the generation, then the state, buffer choice and partition counts
+  const uint32_t g = C.g->tail_gen;
+  const uint32_t sn = (g + 1) % 2u;
+  uint32_t err0 = 0u;
+  if (t == 0) {
+    s_cur = C.st[(g % 2u) * C.n_inst + inst];
+    s_bs = C.g->bufsel[g % 2u];
+    err0 = C.inst_err[inst];
+  }
+  if (t < 2 * MAX_PART) {
+    const int sp = t / MAX_PART, p = t % MAX_PART;
+    if (p < P.parts) {
+      uint32_t* ci = C.counts + cidx(C.n_inst, g % 3u, inst, sp, p);
+      uint32_t* co = C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, sp, p);
+      uint32_t* cf = C.counts + cidx(C.n_inst, (g + 2) % 3u, inst, sp, p);
+      const uint32_t cin = *ci;
+      uint32_t c = MODE == MODE_STEP ? *co : cin;
+      if (c > (uint32_t)P.cap_p) {
+        atomicOr(C.inst_err + inst, (uint32_t)ERR_CAPACITY);
+        atomicOr(&s_err, (uint32_t)ERR_CAPACITY);
+        c = (uint32_t)P.cap_p;
       }
+      *co = c;
+      *cf = 0u;
+      atomicAdd(&s_cnt[0][sp], cin);
+      atomicAdd(&s_cnt[1][sp], c);
+      atomicMax(&s_mx[sp], c);
+    }
+  }
+  __syncthreads();
+  const InstState cur = s_cur;
+  const double factor = MODE == MODE_STEP
+                            ? (cur.popmode == POP_ROULETTE ? 2.0 : (cur.popmode == POP_SPLIT ? 0.5 : 1.0))
+                            : 1.0;
+  const double wj = cur.w_j * factor;
+  const double unit = 1.0 / (double)(1ull << C.dep_shift);
+  const double qvol = QE * wj * unit / (P.area * P.dx);
+  // charge density at the nodes this thread read (half cells at the
+  // electrodes)
+  {
+    double* rho = C.rho + (size_t)sn * C.total_nodes + node;
+    for (int i = t; i <= N; i += TBLOCK) {
+      double r = s_S[i] * qvol;
+      if (i == 0 || i == N) r *= 2.0;
+      rho[i] = r;
+      s_S[i] = r;
     }
   }
   __syncthreads();
 
   // S_i = sum_{j=1..i} rho_j for i < N (S_0 = 0), then U_i = sum_{k<i} S_k,
   // both over contiguous chunks per thread
-  const int chunk = (N + 1 + BLOCK - 1) / BLOCK;
+  const int chunk = (N + 1 + TBLOCK - 1) / TBLOCK;
   const int i0 = t * chunk, i1 = min(i0 + chunk, N + 1);
   const double rho0 = s_S[0], rhoN = s_S[N];
   double loc = 0.0;
   for (int i = i0; i < i1; ++i)
     if (i >= 1 && i <= N - 1) loc += s_S[i];
   double v3[3] = {loc, se, si}, ex3[3], tot3[3];
-  block_scan<3>(v3, ex3, tot3, sh);
+  block_scan<3, TBLOCK / WAVE>(v3, ex3, tot3, sh);
   double run = ex3[0], usum = 0.0;
   for (int i = i0; i < i1; ++i) {
     if (i >= 1 && i <= N - 1) run += s_S[i];
@@ -605,7 +630,7 @@ __global__ void __launch_bounds__(BLOCK) k_tail(Ctx<R> C) {
     if (i <= N - 1) usum += sv;
   }
   double v1[1] = {usum}, ex1[1], tot1[1];
-  block_scan<1>(v1, ex1, tot1, sh);  // its barriers also publish s_S
+  block_scan<1, TBLOCK / WAVE>(v1, ex1, tot1, sh);  // its barriers also publish s_S
   const double T = tot1[0];
   const double dx = P.dx, k = dx / EPS0;
   const double Ehalf = (-P.V / dx - k * T) / (double)N;
@@ -639,7 +664,8 @@ __global__ void __launch_bounds__(BLOCK) k_tail(Ctx<R> C) {
     nx.popmode = pm;
     C.st[sn * C.n_inst + inst] = nx;
     if (MODE == MODE_STEP) {
-      StatsRow row;
+      // field by field, so that the row is never held in registers
+      StatsRow& row = C.ring[(size_t)inst * RING + (nx.step - 1) % RING];
       row.step = nx.step;
       row.n_e = n[0];
       row.n_i = n[1];
@@ -648,8 +674,7 @@ __global__ void __launch_bounds__(BLOCK) k_tail(Ctx<R> C) {
       row.w_i = tot3[2] * unit * wj;
       row.w_j = wj;
       for (int q = 0; q < NEV; ++q) row.ev[q] = (int64_t)s_ev[q];
-      row.err = C.inst_err[inst];
-      C.ring[(size_t)inst * RING + (nx.step - 1) % RING] = row;
+      row.err = err0 | s_err;
     }
     for (int sp = 0; sp < 2; ++sp)
       C.tiles[(size_t)((g + 1) % 3u) * 2 * C.n_inst + 2 * inst + sp] = pair_tiles(s_mx[sp], P.parts);
@@ -1194,7 +1219,7 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 4 : 1) k_gen(Ctx<R> C)
   __shared__ unsigned long long s_hist[2][HWIN];
   __shared__ uint32_t s_gen;
   __shared__ uint32_t s_evw[NWAVE][NEV];
-  __shared__ double s_scan[4];
+  __shared__ double s_scan[NWAVE + 1];
   // collision queues (rings), one per wave: candidates of the wave's
   // current (instance, species)
   __shared__ int32_t q_cell[NWAVE][QW];
@@ -1390,7 +1415,7 @@ __device__ __forceinline__ uint32_t pair_count(const Ctx<R>& C, uint32_t g, int 
 template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_sort_count(Ctx<R> C) {
   extern __shared__ uint32_t s_dyn[];
-  __shared__ double s_scan[4];
+  __shared__ double s_scan[NWAVE + 1];
   const int nk = 2 * C.n_inst, tid = threadIdx.x;
   uint32_t* s_prefix = s_dyn;
   uint32_t* s_hist = s_dyn + ((nk + 1 + 3) & ~3);
@@ -1438,7 +1463,7 @@ __global__ void __launch_bounds__(BLOCK) k_sort_count(Ctx<R> C) {
 // cursors of the scatter; the counts are cleared for the next sort
 template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_sort_scan(Ctx<R> C) {
-  __shared__ double s_scan[4];
+  __shared__ double s_scan[NWAVE + 1];
   const int k = blockIdx.x, inst = k >> 1, sp = k & 1, tid = threadIdx.x;
   IP& P = param(C.ip, inst);
   uint32_t* hist = C.sort_hist + (size_t)sp * C.total_nodes + P.node;
@@ -1464,7 +1489,7 @@ __global__ void __launch_bounds__(BLOCK) k_sort_scan(Ctx<R> C) {
 template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_sort_scatter(Ctx<R> C) {
   extern __shared__ uint32_t s_dyn[];
-  __shared__ double s_scan[4];
+  __shared__ double s_scan[NWAVE + 1];
   const int nk = 2 * C.n_inst, tid = threadIdx.x;
   uint32_t* s_prefix = s_dyn;
   uint32_t* s_cnt = s_dyn + ((nk + 1 + 3) & ~3);
@@ -1610,9 +1635,9 @@ hipError_t launch_particles(const Ctx<R>& C, int mode, hipStream_t s) {
 template <typename R>
 hipError_t launch_tail(const Ctx<R>& C, int mode, hipStream_t s) {
   if (mode == MODE_STEP)
-    hipLaunchKernelGGL((k_tail<R, MODE_STEP>), dim3(C.n_inst), dim3(BLOCK), C.tail_lds, s, C);
+    hipLaunchKernelGGL((k_tail<R, MODE_STEP>), dim3(C.n_inst), dim3(TBLOCK), C.tail_lds, s, C);
   else
-    hipLaunchKernelGGL((k_tail<R, MODE_REFRESH>), dim3(C.n_inst), dim3(BLOCK), C.tail_lds, s, C);
+    hipLaunchKernelGGL((k_tail<R, MODE_REFRESH>), dim3(C.n_inst), dim3(TBLOCK), C.tail_lds, s, C);
   return hipGetLastError();
 }
 
