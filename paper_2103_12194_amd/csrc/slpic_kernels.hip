@@ -193,16 +193,17 @@ __device__ __forceinline__ R half_span(R p, R len, R c, R inv_v0, R ss) {
 }
 
 // Wall-clock time (times |a|) for s to move from s0 to s0 + len: the
-// integral of max(1, |v|/v0) ds, split at s = 0 by symmetry.  Always two
-// half spans (one empty unless s crosses 0), chosen without branching.
+// integral of max(1, |v|/v0) ds, split at s = 0 by symmetry.  The second
+// half span is taken only when s crosses 0 (rare; it would add +0).
 template <typename R>
 __device__ __forceinline__ R time_span(R s0, R len, R c, R inv_v0, R ss) {
   const R s1 = s0 + len;
   const bool pos = s0 >= R(0), neg = !(s1 > R(0));
   const R p1 = pos ? s0 : (neg ? -s1 : R(0));
   const R l1 = (pos || neg) ? len : -s0;
-  const R l2 = (pos || neg) ? R(0) : s1;
-  return half_span(p1, l1, c, inv_v0, ss) + half_span(R(0), l2, c, inv_v0, ss);
+  R t = half_span(p1, l1, c, inv_v0, ss);
+  if (!(pos || neg)) t += half_span(R(0), s1, c, inv_v0, ss);
+  return t;
 }
 
 // Exact speed-limited flight over dt in the uniform acceleration a along x.
