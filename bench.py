@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--pic", action="store_true",
+                    help="also compare SLPIC with plain PIC on one gap")
     return ap.parse_args()
 
 
@@ -173,6 +175,37 @@ def cpu_leg(w, xs, budget_s):
     return ps / secs, desc
 
 
+def pic_leg(xs):
+    """SLPIC against plain PIC (v_limit = +inf, beta == 1, the PIC step of
+    Sec. IV) on the C1 gap in FP32, each from the same seeded state over the
+    same simulated time, one ion crossing time (Sec. IV), with graph replay:
+    the Table I comparison of steps and wall time on this GPU."""
+    import math
+    import paper_2103_12194_amd as slpic
+    from paper_2103_12194_amd import breakdown as bd
+    from synth import configs
+    w = configs.c1(precision=32)
+    base = w.instances[0]
+    t_c = bd.crossing_time(base.d, base.V)
+    out = {"gap": "C1: d=1 cm, p=1 Torr, V=300 V, 64 cells, 1e4 seeded electrons, FP32",
+           "simulated_s": t_c}
+    for name, v_limit in (("slpic", 0.0), ("pic", math.inf)):
+        inst = configs.replace(base, v_limit=v_limit)
+        sim = slpic.Sim([inst], w.run, xs)
+        steps = int(math.ceil(t_c / sim.scalars()["dt"]))
+        sim.use_graph(True)
+        s0, secs, _ = time_steps(sim, steps, profile=False)
+        out[name] = {"dt_s": sim.scalars()["dt"], "steps": steps, "wall_s": secs,
+                     "electrons_at_end": sim.count(0), "ions_at_end": sim.count(1)}
+        sim.close()
+    out["step_ratio"] = out["pic"]["steps"] / out["slpic"]["steps"]
+    out["speedup"] = out["pic"]["wall_s"] / out["slpic"]["wall_s"]
+    print(f"# pic leg: {out['pic']['steps']} PIC steps in {out['pic']['wall_s']:.2f} s, "
+          f"{out['slpic']['steps']} SLPIC steps in {out['slpic']['wall_s']:.3f} s",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -234,6 +267,8 @@ def main():
                  "batched_over_plain": value / (pps / psecs)}
         print(f"# plain leg: {plain['value']:.3e} particle-steps/s", file=sys.stderr, flush=True)
 
+    pic = pic_leg(xs) if args.pic else None
+
     cpu = None
     if not args.no_cpu:
         rate, desc = cpu_leg(w, xs, args.cpu_seconds)
@@ -256,6 +291,8 @@ def main():
         "roofline": roofline, "plain": plain, "graph": graph,
         "cpu_baseline": cpu,
     }
+    if pic is not None:
+        line["pic"] = pic
     print(json.dumps(line), flush=True)
     return 0
 

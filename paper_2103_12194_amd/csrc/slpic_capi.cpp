@@ -800,10 +800,9 @@ int slpic_step(slpic_t* h, int n_steps) {
   return SLPIC_OK;
 }
 
-// Changes the particle-kernel grid between steps.  The kernels derive the
-// generation from the workgroup counter (generation x grid before every
-// launch pair), so the counter is rewritten for the new grid; a captured
-// graph holds the old grid and is dropped.
+// Changes the particle-kernel grid between steps.  Kernels read the
+// generation from device words, so only the launch shape changes; a
+// captured graph holds the old grid and is dropped.
 static int set_grid(slpic_t* h, int grid) {
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->grid = grid;
