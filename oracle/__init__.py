@@ -21,6 +21,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 ELECTRON, ION = 0, 1
 FLAG_PRODUCTS_AT_REST = 1
 FLAG_SEE_ENERGY = 2
+FLAG_FLUX = 4
 STAT_NAMES = ["step", "n_e", "n_i", "w_e", "w_i", "w_j", "elastic",
               "excitation", "ionization", "cx", "abs_e_cathode",
               "abs_e_anode", "abs_i_cathode", "abs_i_anode", "see",
@@ -79,6 +80,8 @@ def lib():
         L.or_read.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp]
         L.or_fields.argtypes = [vp, vp, vp, vp]
         L.or_last_stats.argtypes = [vp, vp]
+        L.or_flux.argtypes = [vp, C.c_int, vp]
+        L.or_flux_reset.argtypes = [vp]
         L.or_scalars.argtypes = [vp, vp]
         L.or_min_margin.restype = C.c_double
         L.or_min_margin.argtypes = [vp]
@@ -245,6 +248,15 @@ class Sim:
         rho, phi, E = np.zeros(n), np.zeros(n), np.zeros(n)
         lib().or_fields(self.h, _ptr(rho), _ptr(phi), _ptr(E))
         return rho, phi, E
+
+    def flux(self, species, reset=False):
+        """Time-integrated flux through each node (sum over steps of w_j
+        times the net upward crossings), needs FLAG_FLUX."""
+        out = np.zeros(self.cells + 1)
+        lib().or_flux(self.h, species, _ptr(out))
+        if reset:
+            lib().or_flux_reset(self.h)
+        return out
 
     def stats(self):
         row = np.zeros(NSTAT)

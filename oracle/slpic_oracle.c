@@ -74,6 +74,8 @@ struct or_sim {
   uint32_t step;
   mlist e, i;
   double *Q, *rho, *phi, *E;
+  int64_t* cross[2];  /* net upward crossings of each node in this step */
+  double* flux[2];    /* time-integrated flux through each node */
   double stats[OR_NSTAT];
   double min_margin;
   int err;
@@ -535,6 +537,10 @@ or_sim* or_create(const or_params* p) {
   s->rho = (double*)calloc(N + 1, sizeof(double));
   s->phi = (double*)calloc(N + 1, sizeof(double));
   s->E = (double*)calloc(N + 1, sizeof(double));
+  for (int sp = 0; sp < 2; ++sp) {
+    s->cross[sp] = (int64_t*)calloc(N + 1, sizeof(int64_t));
+    s->flux[sp] = (double*)calloc(N + 1, sizeof(double));
+  }
 
   /* seeding (Sec. IV injects electrons at rest on the cathode) */
   for (int64_t k = 0; k < p->n_seed && p->seed_mode != OR_SEED_NONE; ++k) {
@@ -561,6 +567,7 @@ void or_destroy(or_sim* s) {
   free(s->energies); free(s->sigma); free(s->thr); free(s->kind); free(s->fixed);
   free(s->e.a); free(s->i.a);
   free(s->Q); free(s->rho); free(s->phi); free(s->E);
+  for (int sp = 0; sp < 2; ++sp) { free(s->cross[sp]); free(s->flux[sp]); }
   free(s);
 }
 
@@ -711,9 +718,32 @@ static int push(or_sim* s, marker* m, double qm) {
   return 0;
 }
 
+/* Flux through surfaces (Eq. (12) and the passage after it): a marker that
+ * crosses a surface carries w_j physical particles through it, whatever its
+ * speed.  Net crossings of the nodes between the cells before and after the
+ * flight; absorbed markers end in cell -1 (cathode, w == 1) or cells (anode,
+ * w == 2). */
+static void note_crossings(or_sim* s, int sp, double x0, double x1, int w) {
+  if (!(s->p.flags & OR_FLAG_FLUX)) return;
+  if (w == 0 && !isfinite(x1)) return;  /* a non-finite state is an error, not a crossing */
+  const int64_t N = s->p.cells;
+  int64_t c0 = (int64_t)floor(x0 / s->dx);
+  c0 = c0 < 0 ? 0 : (c0 > N - 1 ? N - 1 : c0);
+  int64_t c1;
+  if (w == 1) c1 = -1;
+  else if (w == 2) c1 = N;
+  else {
+    c1 = (int64_t)floor(x1 / s->dx);
+    c1 = c1 < 0 ? 0 : (c1 > N - 1 ? N - 1 : c1);
+  }
+  for (int64_t k = c0 + 1; k <= c1; ++k) s->cross[sp][k] += 1;
+  for (int64_t k = c1 + 1; k <= c0; ++k) s->cross[sp][k] -= 1;
+}
+
 static int one_step(or_sim* s) {
   memset(s->stats, 0, sizeof(s->stats));
   uint32_t step = s->step;
+  const double w_step = s->w_j;  /* the flux weight of the markers this step */
   int64_t nin = s->e.n + s->i.n;
   /* population control decided from the integer counts entering the step */
   int mode = 0;
@@ -725,7 +755,9 @@ static int one_step(or_sim* s) {
   int rc = 0;
   for (int64_t k = 0; k < s->e.n && !rc; ++k) {
     marker m = s->e.a[k];
+    const double xe0 = m.x;
     int w = push(s, &m, -QE / ME);
+    note_crossings(s, OR_ELECTRON, xe0, m.x, w);
     if (w == 1) { s->stats[OR_ST_ABS_E_CATH] += 1; continue; }
     if (w == 2) { s->stats[OR_ST_ABS_E_ANODE] += 1; continue; }
     rc = collide_electron(s, &m, &born_e, &born_i);
@@ -735,6 +767,7 @@ static int one_step(or_sim* s) {
     marker m = s->i.a[k];
     const double x0 = m.x, vx0 = m.vx, a0 = QE / MAR * gather(s, m.x);
     int w = push(s, &m, QE / MAR);
+    note_crossings(s, OR_ION, x0, m.x, w);
     if (w == 1) {
       /* ion-induced secondary emission at the cathode (Sec. IV): an electron
        * at rest at x = 0 with probability gamma_se, or with the yield of
@@ -796,6 +829,12 @@ static int one_step(or_sim* s) {
   s->e = out_e;
   s->i = out_i;
   if (rc) { s->err |= OR_ERR_ALLOC; return -1; }
+  if (s->p.flags & OR_FLAG_FLUX)
+    for (int sp = 0; sp < 2; ++sp)
+      for (int k = 0; k <= s->p.cells; ++k) {
+        s->flux[sp][k] += w_step * (double)s->cross[sp][k];
+        s->cross[sp][k] = 0;
+      }
   deposit_and_solve(s);
   s->step = step + 1;
   s->stats[OR_ST_STEP] = s->step;
@@ -840,6 +879,15 @@ void or_fields(const or_sim* s, double* rho, double* phi, double* E) {
   if (rho) memcpy(rho, s->rho, n * sizeof(double));
   if (phi) memcpy(phi, s->phi, n * sizeof(double));
   if (E) memcpy(E, s->E, n * sizeof(double));
+}
+
+void or_flux(const or_sim* s, int species, double* out) {
+  memcpy(out, s->flux[species == OR_ELECTRON ? 0 : 1], ((size_t)s->p.cells + 1) * sizeof(double));
+}
+
+void or_flux_reset(or_sim* s) {
+  for (int sp = 0; sp < 2; ++sp)
+    memset(s->flux[sp], 0, ((size_t)s->p.cells + 1) * sizeof(double));
 }
 
 void or_last_stats(const or_sim* s, double* row) {

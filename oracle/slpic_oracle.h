@@ -42,8 +42,9 @@ enum {
 /* flags: OR_FLAG_PRODUCTS_AT_REST leaves both electrons of an ionization at
  * rest (the closed-form Townsend test gas); OR_FLAG_SEE_ENERGY takes the
  * ion-induced emission probability from the ion's impact energy by Eq. (17)
- * (Sec. IV) instead of the constant gamma_se */
-enum { OR_FLAG_PRODUCTS_AT_REST = 1, OR_FLAG_SEE_ENERGY = 2 };
+ * (Sec. IV) instead of the constant gamma_se; OR_FLAG_FLUX keeps the flux
+ * through every node (Eq. (12) and the passage after it, see or_flux) */
+enum { OR_FLAG_PRODUCTS_AT_REST = 1, OR_FLAG_SEE_ENERGY = 2, OR_FLAG_FLUX = 4 };
 
 /* error bits */
 enum { OR_ERR_NU_BOUND = 1, OR_ERR_NONFINITE = 2, OR_ERR_ALLOC = 4 };
@@ -98,6 +99,15 @@ int or_read(const or_sim* s, int species, int32_t* cell, double* off,
             double* vx, double* vy, double* vz, uint64_t* id, double* tie);
 /* node arrays of length cells+1 (NULL to skip) */
 void or_fields(const or_sim* s, double* rho, double* phi, double* E);
+/* Time-integrated flux through each node (cells + 1 doubles, node 0 the
+ * cathode) of one species since creation or the last or_flux_reset, with
+ * OR_FLAG_FLUX: every step adds w_j times the net number of markers that
+ * crossed the node in +x.  A marker crosses node k upward when
+ * floor(x0/dx) < k <= floor(x1/dx) for its positions x0, x1 before and after
+ * the flight, downward in the opposite case; a marker absorbed at the
+ * cathode (anode) ends in cell -1 (cells). */
+void or_flux(const or_sim* s, int species, double* out);
+void or_flux_reset(or_sim* s);
 /* statistics of the last step, OR_NSTAT doubles */
 void or_last_stats(const or_sim* s, double* row);
 /* derived scalars: dx, dt, v0, n_g, nu_max_e, nu_max_cx, w_j, step */
