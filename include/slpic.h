@@ -61,8 +61,11 @@ enum { SLPIC_ELECTRON = 0, SLPIC_ION = 1 };
  * the probability of Eq. (17) (Sec. IV) at its impact energy,
  * 0.09 (eps/700 eV)^0.05 below 700 eV and 0.09 (eps/700 eV)^0.72 above,
  * instead of the constant gamma_se; at most one electron per ion (the yield
- * stays below 1 up to about 20 keV). */
-enum { SLPIC_FLAG_PRODUCTS_AT_REST = 1, SLPIC_FLAG_SEE_ENERGY = 2 };
+ * stays below 1 up to about 20 keV).
+ * SLPIC_FLAG_FLUX: keep the time-integrated flux through every node for
+ * slpic_read_flux (Eq. (12) and the passage after it); costs one atomic per
+ * marker that changes cell. */
+enum { SLPIC_FLAG_PRODUCTS_AT_REST = 1, SLPIC_FLAG_SEE_ENERGY = 2, SLPIC_FLAG_FLUX = 4 };
 
 /* Settings shared by all instances of a handle. */
 typedef struct slpic_config {
@@ -227,6 +230,18 @@ int slpic_read_markers(slpic_t* h, int inst, int species, int64_t max_n,
 /* Node arrays (cells + 1 each, host, NULL to skip) of one instance: charge
  * density [C/m^3], potential [V] and field [V/m].  Synchronizes. */
 int slpic_read_fields(slpic_t* h, int inst, double* rho, double* phi, double* E);
+
+/* Time-integrated flux through each node of one instance and species (Eq. (12)
+ * and the passage after it: a marker crossing a surface carries its flux
+ * weight w_j through it, whatever its speed), summed over the steps since
+ * create or the last read with reset != 0: each step adds w_j times the
+ * net number of markers that crossed the node in +x.  A marker crosses node
+ * k upward when its cell goes from below k to k or above during the step
+ * (downward likewise); a marker absorbed at the cathode (anode) ends below
+ * node 0 (above node cells), so nodes 0 and cells give the electrode fluxes.
+ * flux: host array of cells + 1 doubles, node 0 at the cathode.  Needs
+ * SLPIC_FLAG_FLUX at create, else SLPIC_INVALID_ARG.  Synchronizes. */
+int slpic_read_flux(slpic_t* h, int inst, int species, double* flux, int reset);
 
 /* Statistics rows of one instance for steps first_step+1 .. first_step+n
  * (row k describes step first_step+k+1), from a ring of the last 4096 steps.

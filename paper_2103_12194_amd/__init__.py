@@ -19,6 +19,7 @@ ELASTIC, EXCITATION, IONIZATION = 0, 1, 2
 SEED_NONE, SEED_CATHODE, SEED_MAXWELL_CELL0 = 0, 1, 2
 FLAG_PRODUCTS_AT_REST = 1
 FLAG_SEE_ENERGY = 2
+FLAG_FLUX = 4
 MAX_PARTITIONS = 16   # SLPIC_MAX_PARTITIONS
 
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "WORKSPACE_TOO_SMALL",
@@ -72,7 +73,7 @@ class slpic_stats(C.Structure):
 _lib = None
 EXPORTS = ["slpic_workspace_bytes", "slpic_create", "slpic_step", "slpic_sync",
            "slpic_use_graph", "slpic_load_markers", "slpic_count",
-           "slpic_read_markers", "slpic_read_fields", "slpic_read_stats",
+           "slpic_read_markers", "slpic_read_fields", "slpic_read_flux", "slpic_read_stats",
            "slpic_scalars", "slpic_steps_done", "slpic_last_error",
            "slpic_destroy", "slpic_philox_device", "slpic_profile",
            "slpic_kernel_times", "slpic_partitions", "slpic_autotune",
@@ -99,6 +100,7 @@ def lib():
         L.slpic_count.argtypes = [vp, i32, i32, P(i64)]
         L.slpic_read_markers.argtypes = [vp, i32, i32, i64, P(i64), vp, vp, vp, vp, vp, vp]
         L.slpic_read_fields.argtypes = [vp, i32, vp, vp, vp]
+        L.slpic_read_flux.argtypes = [vp, i32, i32, vp, i32]
         L.slpic_read_stats.argtypes = [vp, i32, i64, i32, vp]
         L.slpic_scalars.argtypes = [vp, i32, vp]
         L.slpic_steps_done.restype = i64
@@ -300,6 +302,14 @@ class Sim:
         _check(lib().slpic_read_fields(self.h, inst, _p(rho), _p(phi), _p(E)),
                self.h)
         return rho, phi, E
+
+    def flux(self, species, inst=0, reset=False):
+        """Time-integrated flux through each node since create or the last
+        reset (w_j times net upward crossings per step; needs FLAG_FLUX)."""
+        out = np.zeros(self.cells[inst] + 1)
+        _check(lib().slpic_read_flux(self.h, inst, species, _p(out), 1 if reset else 0),
+               self.h)
+        return out
 
     def stats(self, first_step=None, n=1, inst=0):
         """Statistics rows (dicts) for steps first_step+1 .. first_step+n;

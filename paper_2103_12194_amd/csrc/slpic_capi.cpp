@@ -59,7 +59,7 @@ uint32_t prob_threshold(double P) {
 }
 
 struct Layout {
-  size_t ip, st, counts, tiles, ev, acc, E, E64, phi, rho, scratch, ring, inst_err, sort_hist, sort_cur,
+  size_t ip, st, counts, tiles, cross, flux, ev, acc, E, E64, phi, rho, scratch, ring, inst_err, sort_hist, sort_cur,
       glob, xs_e, xs_sig, xs_thr, xs_kind;
   size_t part[2][2][6];  // [buffer][species][array]
   size_t total;
@@ -128,6 +128,8 @@ bool make_layout(const slpic_config* cfg, const slpic_instance* inst, int n_inst
   L.sort_hist = take(sizeof(uint32_t) * 2 * (size_t)nodes);
   L.sort_cur = take(sizeof(uint32_t) * 2 * (size_t)nodes);
   L.tiles = take(sizeof(uint32_t) * 3 * 2 * (size_t)n_inst);
+  L.cross = take(sizeof(int32_t) * 2 * (size_t)nodes);
+  L.flux = take(sizeof(double) * 2 * (size_t)nodes);
   L.glob = take(sizeof(Global));
   const int ng = xs->n_grid, nc = std::max(xs->n_chan, 1);
   L.xs_e = take(rs * ng);
@@ -151,7 +153,7 @@ std::string validate(const slpic_config* cfg, const slpic_instance* inst, int n_
   if (!(cfg->cfl > 0 && cfg->cfl <= 1)) return "cfl must be in (0, 1]";
   if (!(cfg->ion_B_eV > 0)) return "ion_B_eV must be > 0";
   if (cfg->resort_period < 0) return "resort_period must be >= 0";
-  if (cfg->flags & ~(uint32_t)(SLPIC_FLAG_PRODUCTS_AT_REST | SLPIC_FLAG_SEE_ENERGY))
+  if (cfg->flags & ~(uint32_t)(SLPIC_FLAG_PRODUCTS_AT_REST | SLPIC_FLAG_SEE_ENERGY | SLPIC_FLAG_FLUX))
     return "unknown flags";
   if (xs->n_chan < 0 || xs->n_chan > MAX_CHAN) return "n_chan must be in 0..8";
   if (xs->n_grid < 2 || !xs->energies) return "n_grid must be >= 2";
@@ -340,6 +342,8 @@ void fill_ctx(slpic_t* h, Ctx<R>& C) {
   C.sort_hist = reinterpret_cast<uint32_t*>(w + L.sort_hist);
   C.sort_cur = reinterpret_cast<uint32_t*>(w + L.sort_cur);
   C.tiles = reinterpret_cast<uint32_t*>(w + L.tiles);
+  C.cross = reinterpret_cast<int32_t*>(w + L.cross);
+  C.flux = reinterpret_cast<double*>(w + L.flux);
   C.g = reinterpret_cast<Global*>(w + L.glob);
   C.xs_e = reinterpret_cast<const R*>(w + L.xs_e);
   C.xs_sig = reinterpret_cast<const R*>(w + L.xs_sig);
@@ -727,6 +731,8 @@ int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst
   if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.ev, 0, sizeof(unsigned long long) * NEV * NSLOT * n_inst, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.acc, 0, sizeof(unsigned long long) * 2 * NSLOT * L.total_nodes, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.sort_hist, 0, sizeof(uint32_t) * 2 * L.total_nodes, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.cross, 0, sizeof(int32_t) * 2 * L.total_nodes, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.flux, 0, sizeof(double) * 2 * L.total_nodes, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.inst_err, 0, sizeof(uint32_t) * n_inst, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.ring, 0, sizeof(StatsRow) * RING * n_inst, h->stream);
   for (int i = 0; i < n_inst && e == hipSuccess; ++i) {
@@ -992,6 +998,18 @@ int slpic_read_fields(slpic_t* h, int inst, double* rho, double* phi, double* E)
   if (rho) HIPCHK(h, hipMemcpy(rho, h->ws + h->L.rho + 8 * base, 8 * n, hipMemcpyDeviceToHost));
   if (phi) HIPCHK(h, hipMemcpy(phi, h->ws + h->L.phi + 8 * base, 8 * n, hipMemcpyDeviceToHost));
   if (E) HIPCHK(h, hipMemcpy(E, h->ws + h->L.E64 + 8 * base, 8 * n, hipMemcpyDeviceToHost));
+  return SLPIC_OK;
+}
+
+int slpic_read_flux(slpic_t* h, int inst, int species, double* flux, int reset) {
+  if (!h || inst < 0 || inst >= h->n_inst || (species != 0 && species != 1) || !flux)
+    return fail(h, SLPIC_INVALID_ARG, "bad flux arguments");
+  if (!(h->cfg.flags & SLPIC_FLAG_FLUX)) return fail(h, SLPIC_INVALID_ARG, "created without SLPIC_FLAG_FLUX");
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  const size_t at = h->L.flux + sizeof(double) * ((size_t)species * h->L.total_nodes + h->ip[inst].node);
+  const size_t n = (size_t)h->ip[inst].cells + 1;
+  HIPCHK(h, hipMemcpy(flux, h->ws + at, sizeof(double) * n, hipMemcpyDeviceToHost));
+  if (reset) HIPCHK(h, hipMemset(h->ws + at, 0, sizeof(double) * n));
   return SLPIC_OK;
 }
 

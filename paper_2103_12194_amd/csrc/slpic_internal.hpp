@@ -141,6 +141,8 @@ struct Ctx {
   uint32_t* sort_hist;       // [2][total_nodes] cell counts of the cell sort
   uint32_t* sort_cur;        // [2][total_nodes] cursors of the cell sort
   uint32_t* tiles;           // [3][n_inst][2] tiles of each (instance, species)
+  int32_t* cross;            // [2][total_nodes] net upward node crossings of a step
+  double* flux;              // [2][total_nodes] time-integrated flux (w_j units)
   int max_cells;             // largest cell count of the batch
   int sort_lds1, sort_lds2;  // dynamic LDS bytes of the sort's count and scatter
 };

@@ -601,14 +601,26 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
   const double unit = 1.0 / (double)(1ull << C.dep_shift);
   const double qvol = QE * wj * unit / (P.area * P.dx);
   // charge density at the nodes this thread read (half cells at the
-  // electrodes)
+  // electrodes); with the flux diagnostic, the step's node crossings times
+  // the flux weight the markers had in it
   {
     double* rho = C.rho + (size_t)sn * C.total_nodes + node;
+    const bool flux = MODE == MODE_STEP && (C.flags & 4u);
     for (int i = t; i <= N; i += TBLOCK) {
       double r = s_S[i] * qvol;
       if (i == 0 || i == N) r *= 2.0;
       rho[i] = r;
       s_S[i] = r;
+      if (flux) {
+        for (int sp = 0; sp < 2; ++sp) {
+          const size_t at = (size_t)sp * tn + node + i;
+          const int32_t c = C.cross[at];
+          if (c) {
+            C.flux[at] += cur.w_j * (double)c;
+            C.cross[at] = 0;
+          }
+        }
+      }
     }
   }
   __syncthreads();
@@ -1171,7 +1183,17 @@ __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp
     out_lo = out_lo || ct < 0;
     out_hi = out_hi || ct >= P.cells;
   }
-  if (!m_finite(f) || !m_finite(vx1)) {
+  const bool finite = m_finite(f) && m_finite(vx1);
+  if ((C.flags & 4u) && finite) {
+    // flux diagnostic (Eq. (12) and the passage after it): the net
+    // crossings of the nodes between the cells before and after the flight,
+    // an absorbed marker ending below node 0 or above node cells
+    const int c0 = m.cell, c1 = out_lo ? -1 : (out_hi ? P.cells : cell);
+    int32_t* cr = C.cross + (size_t)sp * C.total_nodes + P.node;
+    for (int k = c0 + 1; k <= c1; ++k) atomicAdd(cr + k, 1);
+    for (int k = c1 + 1; k <= c0; ++k) atomicAdd(cr + k, -1);
+  }
+  if (!finite) {
     err |= ERR_NONFINITE;
   } else if (out_lo) {
     note(ev, ev2, 1u << (sp == 0 ? EV_ABS_E_CATH : EV_ABS_I_CATH));

@@ -316,3 +316,33 @@ def test_cell_sort_orders_markers_and_keeps_results(xs_argon):
         for sp in (0, 1):
             compare_populations(a.read(sp, k), b.read(sp, k), 0.0, 0.0,
                                 a.scalars(k)["v0"], label=f"after inst {k} sp {sp}")
+
+
+def test_fp64_flux_through_nodes_matches_oracle(xs_argon):
+    """Flux diagnostic (Eq. (12) and the passage after it): the net node
+    crossings times w_j, summed over steps, bit-identical to the oracle's in
+    FP64 for both species, and reset on request."""
+    inst = _c1_small()
+    run = configs.Run(precision=64)
+    flags = slpic.FLAG_FLUX
+    gpu = slpic.Sim([inst], run, xs_argon, flags=flags)
+    ref = oracle.Sim(inst, run, xs_argon, flags=oracle.FLAG_FLUX)
+    ions = synth.markers.ions(13, 3000, inst.cells, cell_hi=8, e_beam_hi=1500.0)
+    gpu.load(1, ions)
+    ref.load(1, ions)
+    gpu.step(40)
+    ref.step(40)
+    assert gpu.sync() == 0
+    for sp in (0, 1):
+        fg, fo = gpu.flux(sp), ref.flux(sp)
+        assert np.any(fo != 0), sp
+        assert np.array_equal(fg, fo), (sp, np.abs(fg - fo).max())
+    # the cathode node sees the cathode absorptions of the run
+    assert gpu.flux(1, reset=True)[0] < 0
+    assert not np.any(gpu.flux(1))
+    gpu.step(5)
+    ref.flux(1, reset=True)
+    ref.step(5)
+    assert np.array_equal(gpu.flux(1), ref.flux(1))
+    with pytest.raises(slpic.SlpicError):
+        slpic.Sim([inst], run, xs_argon).flux(0)

@@ -19,6 +19,7 @@ import oracle
 from synth import configs, xsec
 from synth.constants import QE, ME, M_AR
 from parity import compare_populations, STAT_INT
+from test_oracle_collisions import _renewal_mean
 
 pytestmark = pytest.mark.gpu
 
@@ -72,7 +73,7 @@ def test_slpic_and_pic_give_the_same_townsend_multiplication():
     xs = xsec.constant([(xsec.IONIZATION, sigma)], [0.0])
     insts = [_townsend_gap(0.0, n_seed), _townsend_gap(math.inf, n_seed)]
     sim = slpic.Sim(insts, configs.Run(precision=32, area=1e30),
-                    xs, flags=slpic.FLAG_PRODUCTS_AT_REST)
+                    xs, flags=slpic.FLAG_PRODUCTS_AT_REST | slpic.FLAG_FLUX)
     dt_s, dt_p = sim.scalars(0)["dt"], sim.scalars(1)["dt"]
     # Table I: the SLPIC step is sqrt(m_Ar / m_e) PIC steps
     assert dt_s / dt_p == pytest.approx(math.sqrt(M_AR / ME), rel=1e-12)
@@ -96,4 +97,22 @@ def test_slpic_and_pic_give_the_same_townsend_multiplication():
     # both discretizations sit within 15 % of the continuum value
     for m in M:
         assert m == pytest.approx(m_cont, rel=0.15)
+    # flux diagnostic: electrons only move toward the anode, so the flux
+    # through the anode node is the anode count and the flux through the
+    # plane at x per seed is the multiplication of a gap of length x (for
+    # SLPIC, the renewal equation of the discrete process)
+    w_j = configs.Run().w_j0
+    for k in range(2):
+        f = sim.flux(0, inst=k) / w_j
+        assert f[insts[k].cells] == anode[k] and f[0] == 0
+        assert np.all(np.diff(f) >= 0)
+    sc = sim.scalars(0)
+    P = -math.expm1(-sc["n_g"] * sigma * sc["v0"] * sc["dt"])
+    a = QE / ME * insts[0].V / insts[0].d
+    f = sim.flux(0, inst=0) / w_j / n_seed
+    for node in (16, 32, 48):
+        x = node * insts[0].d / insts[0].cells
+        want = _renewal_mean(P, sc["v0"] * sc["dt"], sc["v0"] ** 2 / (2 * a), x)
+        sdx = math.sqrt(want * (want - 1) / n_seed)
+        assert abs(f[node] - want) < 4 * sdx, (node, f[node], want)
     sim.close()
