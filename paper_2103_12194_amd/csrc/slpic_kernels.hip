@@ -359,6 +359,14 @@ __device__ __forceinline__ void unit3(R vx, R vy, R vz, R& hx, R& hy, R& hz) {
   else { hx = R(1); hy = R(0); hz = R(0); }
 }
 
+// Entry k of a per-channel table that no kernel writes, for a wave-uniform
+// k: a scalar load through the constant address space.
+template <typename T>
+__device__ __forceinline__ T chan_entry(const T* table, int k) {
+  using CT = const __attribute__((address_space(4))) T;
+  return ((CT*)table)[k];
+}
+
 // Channel choice of a collision candidate: the first channel k with
 // target < sum_{q<=k} n_g sigma_q(eps) slow, where sigma_q is interpolated
 // linearly between log-uniform nodes and is zero below the channel's
@@ -389,7 +397,7 @@ __device__ __forceinline__ int select_channel(const Ctx<R>& C, R eps, R scale, R
   int ch = -1;
   R sum = R(0);
   for (int k = 0; k < nc; ++k) {
-    const R v = eps < C.xs_thr[k] ? R(0) : a[k] + t * (b[k] - a[k]);
+    const R v = eps < chan_entry(C.xs_thr, k) ? R(0) : a[k] + t * (b[k] - a[k]);
     sum += scale * v;
     if (ch < 0 && target < sum) ch = k;
   }
@@ -1066,8 +1074,16 @@ __device__ void collide_electron(const Ctx<R>& C, IP& P, int inst, uint32_t step
     if (cum > numax * R(1.000001)) err |= ERR_NU_BOUND;
   }
   if (ch >= 0) {
-    const int kind = C.xs_kind[ch];
-    const R thr = C.xs_thr[ch];
+    // kind and threshold of the lane's channel, picked from the uniform
+    // per-channel entries (no dependent per-lane load)
+    int kind = 0;
+    R thr = R(0);
+    for (int q = 0; q < C.n_chan; ++q) {
+      const int kq = chan_entry(C.xs_kind, q);
+      const R tq = chan_entry(C.xs_thr, q);
+      kind = q == ch ? kq : kind;
+      thr = q == ch ? tq : thr;
+    }
     R hx, hy, hz, ox, oy, oz;
     unit3(m.vx, m.vy, m.vz, hx, hy, hz);
     // ionization: share eps - I between the scattered and the ejected
