@@ -1252,8 +1252,21 @@ __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp
   }
 }
 
+// The particle kernel reads its argument through the kernel-argument
+// segment (constant, invariant memory): the compiler then reloads fields
+// with scalar loads instead of keeping them all in scalar registers.
+__device__ __forceinline__ const void* kernarg_base() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_kernarg_segment_ptr();
+#else
+  return nullptr;
+#endif
+}
+
 template <typename R, int MODE>
-__global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 4 : 1) k_gen(Ctx<R> C) {
+__global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 4 : 1) k_gen(Ctx<R> C_arg) {
+  (void)C_arg;
+  const Ctx<R>& C = *reinterpret_cast<const Ctx<R>*>(kernarg_base());
   extern __shared__ uint32_t s_prefix[];  // 2 n_inst + 1 tile offsets (dynamic)
   __shared__ unsigned long long s_hist[2][HWIN];
   __shared__ uint32_t s_gen;
