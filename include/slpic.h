@@ -102,7 +102,10 @@ typedef struct slpic_instance {
                         step with N markers: N > 2 n_target keeps each output
                         marker with probability 1/2 and doubles w_j;
                         0 < N < n_target/2 clones each and halves w_j */
-  int64_t capacity;  /* marker slots per species, >= n_seed */
+  int64_t capacity;  /* marker slots per species, >= n_seed; the library
+                        splits them into output partitions and rounds each
+                        up to whole chunks of 64 slots (slpic_partitions
+                        reports the result) */
 } slpic_instance;
 
 /* Electron-neutral cross sections: piecewise linear in energy between

@@ -61,7 +61,7 @@ uint32_t prob_threshold(double P) {
 struct Layout {
   size_t ip, st, counts, tiles, cross, flux, ev, acc, E, E64, phi, rho, scratch, ring, inst_err, sort_hist, sort_cur,
       glob, xs_e, xs_sig, xs_thr, xs_kind;
-  size_t part[2][2][6];  // [buffer][species][array]
+  size_t blk[2][2];      // [buffer][species] chunk arrays of the markers
   size_t total;
   int total_nodes, max_tiles;
   int64_t total_cap;
@@ -96,7 +96,9 @@ bool make_layout(const slpic_config* cfg, const slpic_instance* inst, int n_inst
     L.node[i] = nodes;
     nodes += inst[i].cells + 1;
     const int P = partitions_for(inst[i].capacity);
-    const int64_t cp = (inst[i].capacity + P - 1) / P + (P > 1 ? BLOCK : 0);
+    // partitions start on marker-chunk boundaries
+    int64_t cp = (inst[i].capacity + P - 1) / P + (P > 1 ? BLOCK : 0);
+    cp = (cp + CH - 1) / CH * CH;
     L.parts[i] = P;
     L.cap_p[i] = cp;
     L.seg[i] = cap;
@@ -136,10 +138,10 @@ bool make_layout(const slpic_config* cfg, const slpic_instance* inst, int n_inst
   L.xs_sig = take(rs * (size_t)ng * nc);
   L.xs_thr = take(rs * nc);
   L.xs_kind = take(sizeof(int32_t) * nc);
-  const size_t sizes[6] = {4, rs, rs, rs, rs, 8};
+  // cap is a whole number of chunks (every partition is)
+  const size_t chunk_bytes = (size_t)CH * (4 + 4 * rs + 8);
   for (int b = 0; b < 2; ++b)
-    for (int s = 0; s < 2; ++s)
-      for (int a = 0; a < 6; ++a) L.part[b][s][a] = take(sizes[a] * (size_t)cap);
+    for (int s = 0; s < 2; ++s) L.blk[b][s] = take(chunk_bytes * (size_t)(cap / CH));
   L.total = o;
   return true;
 }
@@ -321,12 +323,7 @@ void fill_ctx(slpic_t* h, Ctx<R>& C) {
   C.ip = reinterpret_cast<const InstParams*>(w + L.ip);
   for (int b = 0; b < 2; ++b)
     for (int s = 0; s < 2; ++s) {
-      C.buf[b][s].cell = reinterpret_cast<int32_t*>(w + L.part[b][s][0]);
-      C.buf[b][s].off = reinterpret_cast<R*>(w + L.part[b][s][1]);
-      C.buf[b][s].vx = reinterpret_cast<R*>(w + L.part[b][s][2]);
-      C.buf[b][s].vy = reinterpret_cast<R*>(w + L.part[b][s][3]);
-      C.buf[b][s].vz = reinterpret_cast<R*>(w + L.part[b][s][4]);
-      C.buf[b][s].id = reinterpret_cast<uint64_t*>(w + L.part[b][s][5]);
+      C.buf[b][s].p = w + L.blk[b][s];
     }
   C.st = reinterpret_cast<InstState*>(w + L.st);
   C.counts = reinterpret_cast<uint32_t*>(w + L.counts);
@@ -545,28 +542,23 @@ int load_impl(slpic_t* h, int inst, int sp, int64_t n, const int32_t* cell, cons
   const Soa<R> B = buffer_of<R>(h, bsel, sp);
   for (int p = 0; p < P.parts; ++p) {
     const int64_t m = n / P.parts + (p < n % P.parts ? 1 : 0);
-    std::vector<int32_t> c(m);
-    std::vector<R> o(m), x(m), y(m), z(m);
-    std::vector<uint64_t> d(m);
+    // the partition's first chunks, packed on the host (slot q of the
+    // partition is slot q of this image)
+    const int64_t nch = (m + CH - 1) / CH;
+    std::vector<char> img((size_t)(nch * Soa<R>::kChunk), 0);
+    const Soa<R> H{img.data()};
     for (int64_t q = 0; q < m; ++q) {
       const int64_t k = q * P.parts + p;
-      c[q] = cell[k];
+      H.cell(q) = cell[k];
       R f = (R)off[k];
-      o[q] = f < R(1) ? f : std::nextafter(R(1), R(0));
-      x[q] = (R)vx[k];
-      y[q] = (R)vy[k];
-      z[q] = (R)vz[k];
-      d[q] = id[k];
+      H.off(q) = f < R(1) ? f : std::nextafter(R(1), R(0));
+      H.vx(q) = (R)vx[k];
+      H.vy(q) = (R)vy[k];
+      H.vz(q) = (R)vz[k];
+      H.id(q) = id[k];
     }
-    const int64_t at = P.seg + (int64_t)p * P.cap_p;
-    if (m) {
-      HIPCHK(h, hipMemcpy(B.cell + at, c.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice));
-      HIPCHK(h, hipMemcpy(B.off + at, o.data(), sizeof(R) * m, hipMemcpyHostToDevice));
-      HIPCHK(h, hipMemcpy(B.vx + at, x.data(), sizeof(R) * m, hipMemcpyHostToDevice));
-      HIPCHK(h, hipMemcpy(B.vy + at, y.data(), sizeof(R) * m, hipMemcpyHostToDevice));
-      HIPCHK(h, hipMemcpy(B.vz + at, z.data(), sizeof(R) * m, hipMemcpyHostToDevice));
-      HIPCHK(h, hipMemcpy(B.id + at, d.data(), sizeof(uint64_t) * m, hipMemcpyHostToDevice));
-    }
+    const int64_t at = P.seg + (int64_t)p * P.cap_p;  // a multiple of CH
+    if (m) HIPCHK(h, hipMemcpy(B.chunk(at), img.data(), img.size(), hipMemcpyHostToDevice));
     const uint32_t cnt = (uint32_t)m;
     HIPCHK(h, hipMemcpy(h->ws + count_offset(h, slot3, inst, sp, p), &cnt, sizeof(uint32_t),
                         hipMemcpyHostToDevice));
@@ -606,21 +598,20 @@ int read_impl(slpic_t* h, int inst, int sp, int64_t max_n, int64_t* n_out, int32
   const Soa<R> B = buffer_of<R>(h, bsel, sp);
   int64_t done = 0;
   for (int p = 0; p < P.parts; ++p) {
-    const int64_t m = cnt[p], at = P.seg + (int64_t)p * P.cap_p;
+    const int64_t m = cnt[p], at = P.seg + (int64_t)p * P.cap_p;  // at: a multiple of CH
     if (!m) continue;
-    std::vector<R> a(m);
-    auto get = [&](double* dst, const R* src) -> hipError_t {
-      if (!dst) return hipSuccess;
-      hipError_t e = hipMemcpy(a.data(), src + at, sizeof(R) * m, hipMemcpyDeviceToHost);
-      for (int64_t k = 0; k < m; ++k) dst[done + k] = (double)a[k];
-      return e;
-    };
-    if (cell) HIPCHK(h, hipMemcpy(cell + done, B.cell + at, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
-    HIPCHK(h, get(off, B.off));
-    HIPCHK(h, get(vx, B.vx));
-    HIPCHK(h, get(vy, B.vy));
-    HIPCHK(h, get(vz, B.vz));
-    if (id) HIPCHK(h, hipMemcpy(id + done, B.id + at, sizeof(uint64_t) * m, hipMemcpyDeviceToHost));
+    const int64_t nch = (m + CH - 1) / CH;
+    std::vector<char> img((size_t)(nch * Soa<R>::kChunk));
+    HIPCHK(h, hipMemcpy(img.data(), B.chunk(at), img.size(), hipMemcpyDeviceToHost));
+    const Soa<R> H{img.data()};
+    for (int64_t q = 0; q < m; ++q) {
+      if (cell) cell[done + q] = H.cell(q);
+      if (off) off[done + q] = (double)H.off(q);
+      if (vx) vx[done + q] = (double)H.vx(q);
+      if (vy) vy[done + q] = (double)H.vy(q);
+      if (vz) vz[done + q] = (double)H.vz(q);
+      if (id) id[done + q] = H.id(q);
+    }
     done += m;
   }
   return SLPIC_OK;

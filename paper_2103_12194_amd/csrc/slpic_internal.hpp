@@ -71,14 +71,28 @@ struct InstParams {
   uint32_t t_fixed_cx;
 };
 
+// Markers of one (buffer, species) in chunks of CH slots.  Within a chunk
+// each field's CH entries are contiguous (cell, off, vx, vy, vz, then id), so
+// one address serves every field of a slot, a wave's CH slots read or write
+// one contiguous segment per field, and only the chunk array's base is a
+// kernel argument.  Partitions start on chunk boundaries.
+constexpr int CH = 64;  // slots per chunk (the shifts below assume 64)
 template <typename R>
 struct Soa {
-  int32_t* cell;
-  R* off;
-  R* vx;
-  R* vy;
-  R* vz;
-  uint64_t* id;
+  char* p;  // chunk 0
+  static constexpr int64_t kChunk = (int64_t)CH * (4 + 4 * (int64_t)sizeof(R) + 8);
+  static constexpr int64_t kOff = 4 * CH, kVx = kOff + CH * (int64_t)sizeof(R),
+                           kVy = kVx + CH * (int64_t)sizeof(R), kVz = kVy + CH * (int64_t)sizeof(R),
+                           kId = kVz + CH * (int64_t)sizeof(R);
+  // slot indices are never negative: chunk and lane by shift and mask
+  __host__ __device__ char* chunk(int64_t s) const { return p + (int64_t)((uint64_t)s >> 6) * kChunk; }
+  __host__ __device__ static int64_t lane(int64_t s) { return (int64_t)((uint64_t)s & (CH - 1)); }
+  __host__ __device__ int32_t& cell(int64_t s) const { return *(int32_t*)(chunk(s) + lane(s) * 4); }
+  __host__ __device__ R& off(int64_t s) const { return *(R*)(chunk(s) + kOff + lane(s) * (int64_t)sizeof(R)); }
+  __host__ __device__ R& vx(int64_t s) const { return *(R*)(chunk(s) + kVx + lane(s) * (int64_t)sizeof(R)); }
+  __host__ __device__ R& vy(int64_t s) const { return *(R*)(chunk(s) + kVy + lane(s) * (int64_t)sizeof(R)); }
+  __host__ __device__ R& vz(int64_t s) const { return *(R*)(chunk(s) + kVz + lane(s) * (int64_t)sizeof(R)); }
+  __host__ __device__ uint64_t& id(int64_t s) const { return *(uint64_t*)(chunk(s) + kId + lane(s) * 8); }
 };
 
 // identical layout to the public slpic_stats

@@ -443,6 +443,15 @@ __device__ __forceinline__ size_t cidx(int n_inst, uint32_t slot, int inst, int 
   return ((((size_t)slot * n_inst + inst) * 2 + sp) * MAX_PART + p) * CSTRIDE;
 }
 
+// Marker chunks of one (buffer, species) as seen by a kernel: the base goes
+// through the global address space, so that loads and stores of marker
+// fields are global (not flat) accesses.
+template <typename R>
+__device__ __forceinline__ Soa<R> gbuf(const Ctx<R>& C, uint32_t b, int sp) {
+  using GC = __attribute__((address_space(1))) char;
+  return Soa<R>{(char*)(GC*)C.buf[b][sp].p};
+}
+
 // Marker count of an input partition of generation g.  Nothing writes the
 // input slot of the count ring while the particle kernel runs (reservations
 // go to slot g + 1), so it is read through the constant address space, with
@@ -1003,7 +1012,7 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
     if (te) base_e = atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 0, W.part), te);
     if (ti) base_i = atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 1, W.part), ti);
   }
-  const Soa<R> oe = C.buf[1 - bsel][0], oi = C.buf[1 - bsel][1];
+  const Soa<R> oe = gbuf(C, 1 - bsel, 0), oi = gbuf(C, 1 - bsel, 1);
   uint32_t pe = __builtin_amdgcn_readfirstlane(base_e) + pre_e;
   uint32_t pi = __builtin_amdgcn_readfirstlane(base_i) + pre_i;
   uint32_t werr = 0;
@@ -1015,12 +1024,12 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
       if (rep == 1 && !clone_e[j]) continue;
       if (pe < (uint32_t)P.cap_p) {
         const int64_t s = W.pbase + pe;
-        oe.cell[s] = o.e[j].cell;
-        oe.off[s] = o.e[j].off;
-        oe.vx[s] = o.e[j].vx;
-        oe.vy[s] = o.e[j].vy;
-        oe.vz[s] = o.e[j].vz;
-        oe.id[s] = rep ? clone_e[j] : o.e[j].id;
+        oe.cell(s) = o.e[j].cell;
+        oe.off(s) = o.e[j].off;
+        oe.vx(s) = o.e[j].vx;
+        oe.vy(s) = o.e[j].vy;
+        oe.vz(s) = o.e[j].vz;
+        oe.id(s) = rep ? clone_e[j] : o.e[j].id;
       } else {
         werr |= ERR_CAPACITY;
       }
@@ -1035,12 +1044,12 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
       if (rep == 1 && !clone_i[j]) continue;
       if (pi < (uint32_t)P.cap_p) {
         const int64_t s = W.pbase + pi;
-        oi.cell[s] = o.i[j].cell;
-        oi.off[s] = o.i[j].off;
-        oi.vx[s] = o.i[j].vx;
-        oi.vy[s] = o.i[j].vy;
-        oi.vz[s] = o.i[j].vz;
-        oi.id[s] = rep ? clone_i[j] : o.i[j].id;
+        oi.cell(s) = o.i[j].cell;
+        oi.off(s) = o.i[j].off;
+        oi.vx(s) = o.i[j].vx;
+        oi.vy(s) = o.i[j].vy;
+        oi.vz(s) = o.i[j].vz;
+        oi.id(s) = rep ? clone_i[j] : o.i[j].id;
       } else {
         werr |= ERR_CAPACITY;
       }
@@ -1375,7 +1384,7 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 4 : 1) k_gen(Ctx<R> C_
         // flush the old deposit window, anchor the new one a quarter window
         // below the tile's first marker
         if (win.inst >= 0) dep_flush(C, s_hist, win, s_evw);
-        int c0 = first0 < n0 ? C.buf[bsel][sp].cell[pb0 + first0] : 0;
+        int c0 = first0 < n0 ? gbuf(C, bsel, sp).cell(pb0 + first0) : 0;
         int anchor = c0 - HWIN / 4;
         const int top = P.cells + 1 - HWIN;
         anchor = anchor > top ? top : anchor;
@@ -1388,27 +1397,27 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 4 : 1) k_gen(Ctx<R> C_
       W.step = S0.step;
       W.pop = MODE == MODE_STEP ? S0.popmode : POP_NONE;
     }
-    const Soa<R> in = C.buf[bsel][sp];
+    const Soa<R> in = gbuf(C, bsel, sp);
 
     // loads inside the partitions need not wait for the counts
     Mk<R> m0, m1;
     if (idx0 < (uint32_t)P.cap_p) {
       const int64_t s = pb0 + idx0;
-      m0.cell = in.cell[s];
-      m0.off = in.off[s];
-      m0.vx = in.vx[s];
-      m0.vy = in.vy[s];
-      m0.vz = in.vz[s];
-      m0.id = in.id[s];
+      m0.cell = in.cell(s);
+      m0.off = in.off(s);
+      m0.vx = in.vx(s);
+      m0.vy = in.vy(s);
+      m0.vz = in.vz(s);
+      m0.id = in.id(s);
     }
     if (two && idx1 < (uint32_t)P.cap_p) {
       const int64_t s = pb1 + idx1;
-      m1.cell = in.cell[s];
-      m1.off = in.off[s];
-      m1.vx = in.vx[s];
-      m1.vy = in.vy[s];
-      m1.vz = in.vz[s];
-      m1.id = in.id[s];
+      m1.cell = in.cell(s);
+      m1.off = in.off(s);
+      m1.vx = in.vx(s);
+      m1.vy = in.vy(s);
+      m1.vz = in.vz(s);
+      m1.id = in.id(s);
     }
     LaneOut<R> o;
     o.me = o.mi = 0u;
@@ -1506,7 +1515,7 @@ __global__ void __launch_bounds__(BLOCK) k_sort_count(Ctx<R> C) {
     cur.place(t, P.parts, part, first);
     const uint32_t idx = first + (uint32_t)tid;
     if (idx < C.counts[cidx(C.n_inst, g % 3u, inst, sp, part)])
-      atomicAdd(&s_hist[C.buf[bsel][sp].cell[P.seg + (int64_t)part * P.cap_p + idx]], 1u);
+      atomicAdd(&s_hist[gbuf(C, bsel, sp).cell(P.seg + (int64_t)part * P.cap_p + idx)], 1u);
   }
   if (k_open >= 0) flush();
 }
@@ -1561,7 +1570,7 @@ __global__ void __launch_bounds__(BLOCK) k_sort_scatter(Ctx<R> C) {
     const int k = cur.kc, inst = k >> 1, sp = k & 1;
     const uint32_t run_end = min(t_end, cur.kend);
     IP& P = param(C.ip, inst);
-    const Soa<R> in = C.buf[bsel][sp], out = C.buf[1u - bsel][sp];
+    const Soa<R> in = gbuf(C, bsel, sp), out = gbuf(C, 1u - bsel, sp);
     const uint32_t n = pair_count(C, g, inst, sp);
     const uint32_t q = (n + (uint32_t)P.parts - 1) / (uint32_t)P.parts;
     // pass A: counts per cell
@@ -1571,7 +1580,7 @@ __global__ void __launch_bounds__(BLOCK) k_sort_scatter(Ctx<R> C) {
       cur.place(u, P.parts, part, first);
       const uint32_t idx = first + (uint32_t)tid;
       if (idx < C.counts[cidx(C.n_inst, g % 3u, inst, sp, part)])
-        atomicAdd(&s_cnt[in.cell[P.seg + (int64_t)part * P.cap_p + idx]], 1u);
+        atomicAdd(&s_cnt[in.cell(P.seg + (int64_t)part * P.cap_p + idx)], 1u);
     }
     __syncthreads();
     uint32_t* cursor = C.sort_cur + (size_t)sp * C.total_nodes + P.node;
@@ -1589,15 +1598,15 @@ __global__ void __launch_bounds__(BLOCK) k_sort_scatter(Ctx<R> C) {
       const uint32_t idx = first + (uint32_t)tid;
       if (idx < C.counts[cidx(C.n_inst, g % 3u, inst, sp, part)]) {
         const int64_t s = P.seg + (int64_t)part * P.cap_p + idx;
-        const int32_t cell = in.cell[s];
+        const int32_t cell = in.cell(s);
         const uint32_t rank = s_base[cell] + atomicAdd(&s_cnt[cell], 1u);
         const int64_t d = P.seg + (int64_t)(rank / q) * P.cap_p + rank % q;
-        out.cell[d] = cell;
-        out.off[d] = in.off[s];
-        out.vx[d] = in.vx[s];
-        out.vy[d] = in.vy[s];
-        out.vz[d] = in.vz[s];
-        out.id[d] = in.id[s];
+        out.cell(d) = cell;
+        out.off(d) = in.off(s);
+        out.vx(d) = in.vx(s);
+        out.vy(d) = in.vy(s);
+        out.vz(d) = in.vz(s);
+        out.id(d) = in.id(s);
       }
     }
     __syncthreads();
@@ -1641,25 +1650,25 @@ __global__ void k_seed(Ctx<R> C, int inst, int mode, int64_t n, double sigma_v, 
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   IP& P = param(C.ip, inst);
-  const Soa<R> o = C.buf[bsel][0];
+  const Soa<R> o = gbuf(C, bsel, 0);
   // seed k goes to partition k mod P, slot k / P
   const int64_t s = P.seg + (k % P.parts) * P.cap_p + k / P.parts;
-  o.id[s] = (uint64_t)k;
-  o.cell[s] = 0;
+  o.id(s) = (uint64_t)k;
+  o.cell(s) = 0;
   if (mode == 2) {
     const U4 r0 = draw((uint64_t)k, 0u, CH_SEED, C.seed, inst);
     const U4 r1 = draw((uint64_t)k, 0u, CH_SEED | (1u << 8), C.seed, inst);
-    o.off[s] = unif<R>(r0.x);
+    o.off(s) = unif<R>(r0.x);
     R a, b, c;
     normals3<R>(r1, (R)sigma_v, a, b, c);
-    o.vx[s] = a;
-    o.vy[s] = b;
-    o.vz[s] = c;
+    o.vx(s) = a;
+    o.vy(s) = b;
+    o.vz(s) = c;
   } else {
-    o.off[s] = R(0);
-    o.vx[s] = R(0);
-    o.vy[s] = R(0);
-    o.vz[s] = R(0);
+    o.off(s) = R(0);
+    o.vx(s) = R(0);
+    o.vy(s) = R(0);
+    o.vz(s) = R(0);
   }
 }
 

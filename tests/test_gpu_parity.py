@@ -186,7 +186,12 @@ def test_capacity_overflow_is_reported(xs_argon):
     with pytest.raises(slpic.SlpicError) as ei:
         gpu.sync()
     assert ei.value.code == -3
-    assert gpu.count(0) <= 1000 and gpu.count(1) <= 1000
+    # no species holds more than its slots (the capacity rounded up to
+    # whole 64-slot chunks per partition)
+    for sp in (0, 1):
+        occ, cap_p = gpu.partitions(sp)
+        assert cap_p % 64 == 0 and 1000 <= len(occ) * cap_p < 1000 + 64 * len(occ) + 256 * len(occ)
+        assert gpu.count(sp) <= len(occ) * cap_p
 
 
 def test_invalid_load_is_rejected(xs_argon):
