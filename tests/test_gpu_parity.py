@@ -351,3 +351,25 @@ def test_fp64_flux_through_nodes_matches_oracle(xs_argon):
     assert np.array_equal(gpu.flux(1), ref.flux(1))
     with pytest.raises(slpic.SlpicError):
         slpic.Sim([inst], run, xs_argon).flux(0)
+
+
+def test_bisection_round_of_256_instances_keeps_its_books():
+    """The 256-instance bisection round (32 pd x 8 voltages, 64-8192 cells)
+    at 1 % of its markers in one handle: every step of every instance keeps
+    the marker balance of the events it reports (entering - absorbed +
+    2 ionizations + emissions - roulette + splits = leaving), and nothing
+    overflows."""
+    xs = synth.argon_like()
+    w = configs.c5(xs.sigma_total_max(), precision=32, scale=0.01)
+    assert len(w.instances) == 256 and max(i.cells for i in w.instances) == 8192
+    gpu = slpic.Sim(w.instances, w.run, xs)
+    steps = 40
+    gpu.step(steps)
+    assert gpu.sync() == 0
+    for k in range(0, 256, 5):
+        h = gpu.history(0, steps, inst=k)
+        absorbed = h["abs_e_cathode"] + h["abs_e_anode"] + h["abs_i_cathode"] + h["abs_i_anode"]
+        out = h["n_in"] - absorbed + 2 * h["ionization"] + h["see"] - h["roulette"] + h["split"]
+        assert np.array_equal(out, h["n_e"] + h["n_i"]), k
+        assert np.array_equal(h["n_in"][1:], (h["n_e"] + h["n_i"])[:-1]), k
+        assert np.all(h["err"] == 0), k
