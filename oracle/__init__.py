@@ -82,6 +82,7 @@ def lib():
         L.or_last_stats.argtypes = [vp, vp]
         L.or_flux.argtypes = [vp, C.c_int, vp]
         L.or_flux_reset.argtypes = [vp]
+        L.or_set_source.argtypes = [vp, C.c_double]
         L.or_scalars.argtypes = [vp, vp]
         L.or_min_margin.restype = C.c_double
         L.or_min_margin.argtypes = [vp]
@@ -257,6 +258,12 @@ class Sim:
         if reset:
             lib().or_flux_reset(self.h)
         return out
+
+    def set_source(self, per_step):
+        """Continuous cathode source: per_step markers per step at the
+        initial flux weight (electrons at rest at x = 0); 0 switches it off."""
+        if lib().or_set_source(self.h, float(per_step)) != 0:
+            raise ValueError(f"source rate {per_step} outside [0, 2^24]")
 
     def stats(self):
         row = np.zeros(NSTAT)

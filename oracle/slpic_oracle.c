@@ -78,6 +78,7 @@ struct or_sim {
   double* flux[2];    /* time-integrated flux through each node */
   double stats[OR_NSTAT];
   double min_margin;
+  double src;         /* cathode source: markers per step at weight w_j0 */
   int err;
 };
 
@@ -794,6 +795,20 @@ static int one_step(or_sim* s) {
     collide_ion(s, &m);
     rc = push_back(&out_i, &m);
   }
+  /* continuous cathode source (or_set_source): electrons at rest at x = 0,
+   * as many as keep the physical rate at the step's flux weight */
+  if (s->src > 0 && !rc) {
+    const double want = s->src * (s->p.w_j0 / w_step);
+    int64_t n = (int64_t)floor(want);
+    uint32_t r[4];
+    draw_raw(s, 0, step, OR_CH_INJECT, 1, r);
+    if (unif(r[0]) < want - floor(want)) n += 1;
+    for (int64_t k = 0; k < n && !rc; ++k) {
+      draw_raw(s, (uint64_t)k, step, OR_CH_INJECT, 0, r);
+      marker ne = {0.0, 0.0, 0.0, 0.0, INFINITY, child_id(r[0], r[1])};
+      rc = push_back(&born_e, &ne);
+    }
+  }
   for (int64_t k = 0; k < born_e.n && !rc; ++k) rc = push_back(&out_e, &born_e.a[k]);
   for (int64_t k = 0; k < born_i.n && !rc; ++k) rc = push_back(&out_i, &born_i.a[k]);
   free(born_e.a);
@@ -883,6 +898,12 @@ void or_fields(const or_sim* s, double* rho, double* phi, double* E) {
 
 void or_flux(const or_sim* s, int species, double* out) {
   memcpy(out, s->flux[species == OR_ELECTRON ? 0 : 1], ((size_t)s->p.cells + 1) * sizeof(double));
+}
+
+int or_set_source(or_sim* s, double per_step) {
+  if (!(per_step >= 0.0 && per_step <= 16777216.0)) return -1;
+  s->src = per_step;
+  return 0;
 }
 
 void or_flux_reset(or_sim* s) {

@@ -27,7 +27,8 @@ enum { OR_ELECTRON = 0, OR_ION = 1 };
 /* Philox stream channels (fourth counter word = channel | sub << 8) */
 enum {
   OR_CH_COLL = 1, OR_CH_IONIZ = 2, OR_CH_IONBIRTH = 3, OR_CH_CX = 4,
-  OR_CH_SEE = 5, OR_CH_ROULETTE = 6, OR_CH_CHILD = 7, OR_CH_SEED = 8
+  OR_CH_SEE = 5, OR_CH_ROULETTE = 6, OR_CH_CHILD = 7, OR_CH_SEED = 8,
+  OR_CH_INJECT = 9
 };
 
 /* per-step statistics row */
@@ -108,6 +109,19 @@ void or_fields(const or_sim* s, double* rho, double* phi, double* E);
  * cathode (anode) ends in cell -1 (cells). */
 void or_flux(const or_sim* s, int species, double* out);
 void or_flux_reset(or_sim* s);
+/* Continuous cathode source: the seeding of Sec. IV (electrons at rest at
+ * x = 0) repeated every step, which gives the steady state in which Sec. II.B
+ * finds the speed-limited equations exact.  per_step is the number of
+ * markers a step injects at the initial flux weight w_j0, so the physical
+ * rate per_step w_j0 / dt stays fixed when population control changes w_j:
+ * at weight w_j a step injects per_step w_j0 / w_j markers, the integer part
+ * and one more with the probability of the fraction (Philox channel INJECT,
+ * sub 1, counter (0, 0, step)).  Marker k of the step takes the id made from
+ * Philox channel INJECT, sub 0, counter (k, 0, step).  Injected electrons
+ * join the step's output as the secondary electrons do and take part in its
+ * population control.  Returns -1 (and changes nothing) unless per_step is
+ * finite and in [0, 2^24]; 0 switches the source off. */
+int or_set_source(or_sim* s, double per_step);
 /* statistics of the last step, OR_NSTAT doubles */
 void or_last_stats(const or_sim* s, double* row);
 /* derived scalars: dx, dt, v0, n_g, nu_max_e, nu_max_cx, w_j, step */
