@@ -246,6 +246,24 @@ int slpic_read_fields(slpic_t* h, int inst, double* rho, double* phi, double* E)
  * SLPIC_FLAG_FLUX at create, else SLPIC_INVALID_ARG.  Synchronizes. */
 int slpic_read_flux(slpic_t* h, int inst, int species, double* flux, int reset);
 
+/* Continuous cathode source of one instance (the electrons at rest at x = 0
+ * with which Sec. IV starts a run, injected every step; a steady source
+ * gives the steady state in which Sec. II.B finds the speed-limited
+ * equations exact).  per_step: markers per step at the initial flux weight
+ * w_j0, so the physical rate per_step w_j0 / dt holds under population
+ * control: at flux weight w_j a step injects per_step w_j0 / w_j markers,
+ * the integer part and one more with the probability of the fraction
+ * (Philox channel 9, sub 1, counter (0, 0, step)); marker k of the step has
+ * the id made from channel 9, sub 0, counter (k, 0, step), with the top bit
+ * set.  The electrons join the step's output (after its pushes and
+ * collisions, as secondary electrons do), take part in its population
+ * control and deposit their charge on node 0.  0 switches the source off.
+ * Enqueued on the handle's stream: takes effect from the next step,
+ * captured graphs included.  SLPIC_INVALID_ARG unless 0 <= per_step <= 2^24
+ * (and finite).  A step whose injections overflow the instance's capacity
+ * reports SLPIC_CAPACITY_EXCEEDED like any other overflow. */
+int slpic_set_source(slpic_t* h, int inst, double per_step);
+
 /* Statistics rows of one instance for steps first_step+1 .. first_step+n
  * (row k describes step first_step+k+1), from a ring of the last 4096 steps.
  * Synchronizes. */

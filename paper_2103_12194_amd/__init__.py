@@ -73,7 +73,8 @@ class slpic_stats(C.Structure):
 _lib = None
 EXPORTS = ["slpic_workspace_bytes", "slpic_create", "slpic_step", "slpic_sync",
            "slpic_use_graph", "slpic_load_markers", "slpic_count",
-           "slpic_read_markers", "slpic_read_fields", "slpic_read_flux", "slpic_read_stats",
+           "slpic_read_markers", "slpic_read_fields", "slpic_read_flux", "slpic_set_source",
+           "slpic_read_stats",
            "slpic_scalars", "slpic_steps_done", "slpic_last_error",
            "slpic_destroy", "slpic_philox_device", "slpic_profile",
            "slpic_kernel_times", "slpic_partitions", "slpic_autotune",
@@ -101,6 +102,7 @@ def lib():
         L.slpic_read_markers.argtypes = [vp, i32, i32, i64, P(i64), vp, vp, vp, vp, vp, vp]
         L.slpic_read_fields.argtypes = [vp, i32, vp, vp, vp]
         L.slpic_read_flux.argtypes = [vp, i32, i32, vp, i32]
+        L.slpic_set_source.argtypes = [vp, i32, C.c_double]
         L.slpic_read_stats.argtypes = [vp, i32, i64, i32, vp]
         L.slpic_scalars.argtypes = [vp, i32, vp]
         L.slpic_steps_done.restype = i64
@@ -302,6 +304,12 @@ class Sim:
         _check(lib().slpic_read_fields(self.h, inst, _p(rho), _p(phi), _p(E)),
                self.h)
         return rho, phi, E
+
+    def set_source(self, per_step, inst=0):
+        """Continuous cathode source of one instance: per_step markers per
+        step at the initial flux weight (electrons at rest at x = 0), from
+        the next step on; 0 switches it off."""
+        _check(lib().slpic_set_source(self.h, inst, float(per_step)), self.h)
 
     def flux(self, species, inst=0, reset=False):
         """Time-integrated flux through each node since create or the last

@@ -1004,6 +1004,17 @@ int slpic_read_flux(slpic_t* h, int inst, int species, double* flux, int reset) 
   return SLPIC_OK;
 }
 
+int slpic_set_source(slpic_t* h, int inst, double per_step) {
+  if (!h || inst < 0 || inst >= h->n_inst) return fail(h, SLPIC_INVALID_ARG, "bad instance");
+  if (!(per_step >= 0.0 && per_step <= 16777216.0))
+    return fail(h, SLPIC_INVALID_ARG, "source rate outside [0, 2^24]");
+  h->ip[inst].src = per_step;
+  const size_t at = h->L.ip + sizeof(InstParams) * (size_t)inst + offsetof(InstParams, src);
+  HIPCHK(h, hipMemcpyAsync(h->ws + at, &h->ip[inst].src, sizeof(double), hipMemcpyHostToDevice,
+                           h->stream));
+  return SLPIC_OK;
+}
+
 int slpic_read_stats(slpic_t* h, int inst, int64_t first_step, int n, slpic_stats* rows) {
   if (!h || inst < 0 || inst >= h->n_inst || n < 0 || (n > 0 && !rows) || first_step < 0)
     return fail(h, SLPIC_INVALID_ARG, "bad stats arguments");

@@ -41,7 +41,7 @@ enum Err { ERR_CAPACITY = 1, ERR_NONFINITE = 2, ERR_NU_BOUND = 4 };
 // Philox stream channels: the fourth counter word is channel | sub << 8
 enum Chan {
   CH_COLL = 1, CH_IONIZ = 2, CH_IONBIRTH = 3, CH_CX = 4, CH_SEE = 5,
-  CH_ROULETTE = 6, CH_CHILD = 7, CH_SEED = 8
+  CH_ROULETTE = 6, CH_CHILD = 7, CH_SEED = 8, CH_INJECT = 9
 };
 
 enum PopMode { POP_NONE = 0, POP_ROULETTE = 1, POP_SPLIT = 2 };
@@ -58,6 +58,7 @@ struct InstParams {
   double qm_e, qm_i;        // signed charge over mass [C/kg]
   double vth_i;             // sqrt(k_B T / m_Ar)
   double w_j0;
+  double src;               // cathode source: markers per step at weight w_j0
   int64_t seg;              // first slot of the instance in each species array
   int64_t cap;              // markers per species (sum over partitions)
   int64_t cap_p;            // slots per partition: partition p of the instance

@@ -510,6 +510,94 @@ __device__ __forceinline__ void block_scan(const double (&v)[NV], double (&ex)[N
   __syncthreads();
 }
 
+// Continuous cathode source of a tail kernel (MODE_STEP): electrons at rest
+// at x = 0, per_step w_j0 / w_j of them at the step's flux weight w_j (the
+// integer part, and one more when a draw falls below the fraction), with
+// ids from the INJECT channel and the step's population control.  The
+// outputs follow the particle kernel's in the electron partitions, dealt
+// round-robin; partition counts, the fullest count, the electron total and
+// the event slots are updated.  Returns the fixed-point charge to add at
+// node 0 (each kept marker has beta = 1 and offset 0).  Called by all
+// threads (block-wide scans); pc holds the partition counts on entry.
+template <typename R>
+__device__ double inject(const Ctx<R>& C, IP& P, int inst, const InstState& cur, uint32_t g,
+                         uint32_t bout, uint32_t* pc, double* sh, unsigned long long* ev,
+                         uint32_t* n_e, uint32_t* mx_e, uint32_t* err) {
+  const int t = threadIdx.x;
+  const uint32_t step = cur.step;
+  const double want = P.src * (P.w_j0 / cur.w_j);
+  const double fl = floor(want);
+  const U4 rf = draw(0, step, CH_INJECT | (1u << 8), C.seed, inst);
+  int64_t n = (int64_t)fl + (unif<double>(rf.x) < want - fl ? 1 : 0);
+  if (n > P.cap) {  // more than the instance holds: an error, as in any overflow
+    n = P.cap;
+    if (t == 0) {
+      atomicOr(C.inst_err + inst, (uint32_t)ERR_CAPACITY);
+      atomicOr(err, (uint32_t)ERR_CAPACITY);
+    }
+  }
+  const int parts = P.parts, pop = cur.popmode;
+  const Soa<R> out = gbuf(C, bout, 0);
+  int64_t base = 0;  // outputs of the earlier rounds
+  for (int64_t k0 = 0; k0 < n; k0 += TBLOCK) {
+    const int64_t k = k0 + t;
+    uint64_t id[2] = {0, 0};
+    int m = 0;
+    if (k < n) {
+      const U4 r = draw((uint64_t)k, step, CH_INJECT, C.seed, inst);
+      id[0] = child(r.x, r.y);
+      m = 1;
+      if (pop == POP_ROULETTE) {
+        const U4 q = draw(id[0], step, CH_ROULETTE, C.seed, inst);
+        m = (q.x >> 9) < (1u << 22) ? 1 : 0;
+      } else if (pop == POP_SPLIT) {
+        const U4 q = draw(id[0], step, CH_CHILD | (1u << 8), C.seed, inst);
+        id[1] = child(q.x, q.y);
+        m = 2;
+      }
+    }
+    double v[1] = {(double)m}, ex[1], tot[1];
+    block_scan<1, TBLOCK / WAVE>(v, ex, tot, sh);
+    for (int j = 0; j < m; ++j) {
+      const int64_t o = base + (int64_t)ex[0] + j;
+      const int p = (int)(o % parts);
+      const int64_t at = (int64_t)pc[p] + o / parts;
+      if (at < P.cap_p) {
+        const int64_t sl = P.seg + p * P.cap_p + at;
+        out.cell(sl) = 0;
+        out.off(sl) = R(0);
+        out.vx(sl) = R(0);
+        out.vy(sl) = R(0);
+        out.vz(sl) = R(0);
+        out.id(sl) = id[j];
+      }
+    }
+    base += (int64_t)tot[0];
+  }
+  if (t == 0) {
+    if (pop == POP_ROULETTE) ev[EV_ROULETTE] += (unsigned long long)(n - base);
+    if (pop == POP_SPLIT) ev[EV_SPLIT] += (unsigned long long)n;
+  }
+  // partition p received the outputs o = p, p + parts, ...
+  int64_t kept = 0;
+  if (t < parts) {
+    const int64_t add = base > t ? (base - t - 1) / parts + 1 : 0;
+    int64_t c = (int64_t)pc[t] + add;
+    if (c > P.cap_p) {
+      c = P.cap_p;
+      atomicOr(C.inst_err + inst, (uint32_t)ERR_CAPACITY);
+      atomicOr(err, (uint32_t)ERR_CAPACITY);
+    }
+    kept = c - (int64_t)pc[t];
+    C.counts[cidx(C.n_inst, (g + 1) % 3u, inst, 0, t)] = (uint32_t)c;
+    atomicAdd(n_e, (uint32_t)kept);
+    atomicMax(mx_e, (uint32_t)c);
+  }
+  double vk[1] = {(double)kept}, exk[1], totk[1];
+  block_scan<1, TBLOCK / WAVE>(vk, exk, totk, sh);
+  return totk[0] * (double)(1ull << C.dep_shift);
+}
+
 // One workgroup of TBLOCK threads per instance, launched after the particle
 // kernel: charge density from the fixed-point deposit, Poisson solve,
 // statistics row, population-control decision for the next step and the
@@ -523,6 +611,7 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
   __shared__ uint32_t s_cnt[2][2];         // [in, out][species]
   __shared__ uint32_t s_mx[2];             // fullest output partition per species
   __shared__ uint32_t s_err;               // capacity errors found here
+  __shared__ uint32_t s_pc[MAX_PART];      // electron output partition counts
   __shared__ InstState s_cur;
   __shared__ uint32_t s_bs;
   const int inst = blockIdx.x, t = threadIdx.x;
@@ -604,6 +693,7 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
       }
       *co = c;
       *cf = 0u;
+      if (sp == 0) s_pc[p] = c;
       atomicAdd(&s_cnt[0][sp], cin);
       atomicAdd(&s_cnt[1][sp], c);
       atomicMax(&s_mx[sp], c);
@@ -611,6 +701,13 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
   }
   __syncthreads();
   const InstState cur = s_cur;
+  if (MODE == MODE_STEP && P.src > 0.0) {
+    const double q = inject(C, P, inst, cur, g, 1u - s_bs, s_pc, sh, s_ev, &s_cnt[1][0], &s_mx[0], &s_err);
+    if (t == 0) {
+      s_S[0] -= q;
+      se += q;
+    }
+  }
   const double factor = MODE == MODE_STEP
                             ? (cur.popmode == POP_ROULETTE ? 2.0 : (cur.popmode == POP_SPLIT ? 0.5 : 1.0))
                             : 1.0;
