@@ -1048,6 +1048,24 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
   const int removed = pop == POP_ROULETTE ? n_out - (cnt_e + cnt_i) : 0;
   const int split_added = pop == POP_SPLIT ? n_out : 0;
 
+  // compaction: prefix within the wave by bit-sliced ballots (cnt_e, cnt_i
+  // in 0..4), one reservation per wave and species on the partition's
+  // counter.  The reservations go out before the deposit and the event
+  // counts, which run while they return.
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const unsigned long long be0 = __ballot(cnt_e & 1), be1 = __ballot(cnt_e & 2),
+                           be2 = __ballot(cnt_e & 4);
+  const unsigned long long bi0 = __ballot(cnt_i & 1), bi1 = __ballot(cnt_i & 2),
+                           bi2 = QUEUE ? 0ull : __ballot(cnt_i & 4);
+  const uint32_t pre_e = __popcll(be0 & lt) + 2 * __popcll(be1 & lt) + 4 * __popcll(be2 & lt);
+  const uint32_t pre_i = __popcll(bi0 & lt) + 2 * __popcll(bi1 & lt) + 4 * __popcll(bi2 & lt);
+  const uint32_t te = __popcll(be0) + 2 * __popcll(be1) + 4 * __popcll(be2);
+  const uint32_t ti = __popcll(bi0) + 2 * __popcll(bi1) + 4 * __popcll(bi2);
+  uint32_t base_e = 0u, base_i = 0u;
+  if (MODE == MODE_STEP && lane == 0) {
+    if (te) base_e = atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 0, W.part), te);
+    if (ti) base_i = atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 1, W.part), ti);
+  }
   // deposit (fixed point, units of q w_j): every kept marker adds its two
   // linear weights to the LDS window (clones count twice)
   {
@@ -1092,23 +1110,6 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
   if (err) atomicOr(C.inst_err + inst, err);
 
   if (MODE != MODE_STEP) return;
-  // compaction: prefix within the wave by bit-sliced ballots (cnt_e, cnt_i
-  // in 0..4), one reservation per wave and species on the partition's
-  // counter
-  const unsigned long long lt = (1ull << lane) - 1ull;
-  const unsigned long long be0 = __ballot(cnt_e & 1), be1 = __ballot(cnt_e & 2),
-                           be2 = __ballot(cnt_e & 4);
-  const unsigned long long bi0 = __ballot(cnt_i & 1), bi1 = __ballot(cnt_i & 2),
-                           bi2 = QUEUE ? 0ull : __ballot(cnt_i & 4);
-  const uint32_t pre_e = __popcll(be0 & lt) + 2 * __popcll(be1 & lt) + 4 * __popcll(be2 & lt);
-  const uint32_t pre_i = __popcll(bi0 & lt) + 2 * __popcll(bi1 & lt) + 4 * __popcll(bi2 & lt);
-  const uint32_t te = __popcll(be0) + 2 * __popcll(be1) + 4 * __popcll(be2);
-  const uint32_t ti = __popcll(bi0) + 2 * __popcll(bi1) + 4 * __popcll(bi2);
-  uint32_t base_e = 0u, base_i = 0u;
-  if (lane == 0) {
-    if (te) base_e = atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 0, W.part), te);
-    if (ti) base_i = atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 1, W.part), ti);
-  }
   const Soa<R> oe = gbuf(C, 1 - bsel, 0), oi = gbuf(C, 1 - bsel, 1);
   uint32_t pe = __builtin_amdgcn_readfirstlane(base_e) + pre_e;
   uint32_t pi = __builtin_amdgcn_readfirstlane(base_i) + pre_i;
