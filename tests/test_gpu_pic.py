@@ -116,3 +116,75 @@ def test_slpic_and_pic_give_the_same_townsend_multiplication():
         sdx = math.sqrt(want * (want - 1) / n_seed)
         assert abs(f[node] - want) < 4 * sdx, (node, f[node], want)
     sim.close()
+
+
+def test_slpic_classifies_breakdown_like_pic_and_converges_with_the_speed_limit():
+    """Sec. IV (the ion-population figure at 1 Torr cm and its discussion):
+    SLPIC and PIC classify a gap above or below breakdown alike, but their
+    transients differ: PIC's seed electrons cross and ionize at once, so its
+    initial ion rise is steeper, and raising the speed limit brings the SLPIC
+    dynamics to PIC's.
+
+    Zero-threshold constant-cross-section ionization with products at rest,
+    so that the Townsend multiplication per generation is the same function
+    of the path in every discretization (no energy threshold to resolve),
+    and breakdown is crossed with gamma_se at fixed V:
+    gamma (exp(n sigma d) - 1) = 1 at gamma near 0.042.  16 replicas per
+    gamma; growth rates over [4, 10] ion crossing times; speed limits v0,
+    4 v0, 16 v0 (v0 = sqrt(2 e V / m_Ar)) and PIC.  The replicas are keyed
+    by instance, so the run is deterministic."""
+    from synth.constants import M_AR
+    from paper_2103_12194_amd import breakdown as bd
+    V, cells, R, tcs = 300.0, 64, 16, 10
+    gammas = (0.02, 0.10)
+    v0 = math.sqrt(2 * QE * V / M_AR)
+    xs = xsec.constant([(xsec.IONIZATION, 1e-20)], [0.0])
+    tc = bd.crossing_time(0.01, V)
+    out = {}
+    for mult in (1.0, 4.0, 16.0, math.inf):
+        insts = [configs.Instance(d=0.01, p_torr=1.0, V=V, cells=cells, gamma_se=g,
+                                  v_limit=mult * v0, seed_mode=configs.SEED_CATHODE,
+                                  n_seed=300, n_target=600, capacity=8192)
+                 for g in gammas for _ in range(R)]
+        sim = slpic.Sim(insts, configs.Run(precision=32), xs, flags=slpic.FLAG_PRODUCTS_AT_REST)
+        sim.use_graph(True)
+        dt = sim.scalars(0)["dt"]
+        n_total = int(math.ceil(tcs * tc / dt))
+        chunk = max(16, (n_total // 400) // 16 * 16)   # about 400 samples per run
+        t, pops, done = [], [], 0
+        while done < n_total:
+            sim.step(chunk)
+            done += chunk
+            t.append(done * dt)
+            pops.append([sim.stats(inst=k)["w_i"] for k in range(len(insts))])
+        assert sim.sync() == 0
+        sim.close()
+        t, pops = np.array(t), np.array(pops).T
+        for j, g in enumerate(gammas):
+            rates = [bd.growth_rate(t, pops[k], tc, window=(4.0, tcs))
+                     for k in range(j * R, (j + 1) * R)]
+            lam, se = bd.ensemble(rates)
+            early = pops[j * R:(j + 1) * R, np.searchsorted(t, 0.25 * tc)].mean()
+            out[mult, g] = (lam, se, early)
+            print(f"v_limit {mult} v0, gamma {g}: lambda t_c = {lam:+.3f} +- {se:.3f}, "
+                  f"mean ion count at t_c / 4 = {early:.3g}")
+    pic = math.inf
+    for g in gammas:
+        # the same classification at every speed limit, each at 3 sigma
+        for mult in (1.0, 4.0, 16.0, pic):
+            lam, se, _ = out[mult, g]
+            assert (lam < -3 * se) if g < 0.042 else (lam > 3 * se), (mult, g, lam, se)
+
+        def gap_to_pic(mult):
+            (a, sa, _), (b, sb, _) = out[mult, g], out[pic, g]
+            return abs(a - b), math.sqrt(sa ** 2 + sb ** 2)
+
+        # the transient dynamics differ at v0 and approach PIC's as the limit rises
+        d1, s1 = gap_to_pic(1.0)
+        d4, _ = gap_to_pic(4.0)
+        d16, s16 = gap_to_pic(16.0)
+        assert d1 > 3 * s1, (g, d1, s1)
+        assert d4 < d1 and d16 < d1
+        assert d16 < 3 * s16, (g, d16, s16)
+        # PIC's seed electrons ionize at once: a steeper initial rise
+        assert out[pic, g][2] > 3 * out[1.0, g][2]
