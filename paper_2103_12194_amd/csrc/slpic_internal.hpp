@@ -20,7 +20,9 @@ constexpr int CSTRIDE = 64;       // uint32 slots between compaction counters:
                                   // reservations of one (instance, species)
                                   // spread over memory channels
 constexpr int NSLOT = 1;          // copies of each global deposit node
-constexpr int HWIN = 1024;        // nodes in a workgroup's LDS deposit window
+constexpr int HWIN = 960;         // nodes in a workgroup's LDS deposit window
+                                  // (30 KB of LDS per workgroup in all: five
+                                  // workgroups per CU)
 
 // Tiles an (instance, species) takes in the tile space of a step: every
 // partition gets as many as the fullest one needs, so that tile j of the

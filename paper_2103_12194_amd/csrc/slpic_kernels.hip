@@ -943,20 +943,13 @@ struct LaneOut {
 
 constexpr int NWAVE = BLOCK / WAVE;
 // collision-queue slots per wave: fewer than WAVE wait between tiles, and a
-// tile pair adds at most 2 WAVE
-constexpr int QW = 3 * WAVE;
+// tile adds at most WAVE
+constexpr int QW = 2 * WAVE;
 
 // a wave-uniform or lane ring position a + b for a, b < QW
 __device__ __forceinline__ uint32_t ring(uint32_t a, uint32_t b) {
   const uint32_t s = a + b;
   return s >= (uint32_t)QW ? s - (uint32_t)QW : s;
-}
-
-// count event bits b in ev, or in ev2 for those ev already holds (the same
-// event for the lane's other marker)
-__device__ __forceinline__ void note(uint32_t& ev, uint32_t& ev2, uint32_t b) {
-  ev2 |= ev & b;
-  ev |= b;
 }
 
 // What a wave is working on: one (instance, species), and the output
@@ -990,15 +983,13 @@ __device__ __forceinline__ void next_output(Work& W, IP& P) {
 // Population control, charge deposit, event counts and stream compaction of
 // the markers each lane of one wave produced.  Called by all lanes of the
 // wave, independently of the other waves.  QUEUE: outputs of collided
-// candidates (collision events) rather than of a tile pair (wall and
-// emission events; a lane counts an event that both of its markers had once
-// in ev and once in ev2).  Event counts go to the wave's row evw of LDS
-// counters.
+// candidates (collision events) rather than of a tile (wall and emission
+// events).  Event counts go to the wave's row evw of LDS counters.
 template <typename R, int MODE, bool QUEUE>
 __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWin& win,
                                      unsigned long long (*hist)[HWIN], const LaneOut<R>& o,
-                                     uint32_t ev, uint32_t ev2, uint32_t err, uint32_t g,
-                                     uint32_t bsel, uint32_t* evw) {
+                                     uint32_t ev, uint32_t err, uint32_t g, uint32_t bsel,
+                                     uint32_t* evw) {
   const int lane = threadIdx.x & (WAVE - 1);
   IP& P = param(C.ip, W.inst);
   const int inst = W.inst, pop = W.pop;
@@ -1042,21 +1033,20 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
       }
     }
   }
-  // at most three outputs per lane (two from a tile pair, three from an
+  // at most three outputs per lane (one from a tile, three from an
   // ionization)
   const int n_out = __popc(o.me) + __popc(o.mi);
   const int removed = pop == POP_ROULETTE ? n_out - (cnt_e + cnt_i) : 0;
   const int split_added = pop == POP_SPLIT ? n_out : 0;
 
-  // compaction: prefix within the wave by bit-sliced ballots (cnt_e, cnt_i
-  // in 0..4), one reservation per wave and species on the partition's
-  // counter.  The reservations go out before the deposit and the event
-  // counts, which run while they return.
+  // compaction: prefix within the wave by bit-sliced ballots (cnt_e in
+  // 0..4, 4 only for a split ionization; cnt_i in 0..2), one reservation per
+  // wave and species on the partition's counter.  The reservations go out
+  // before the deposit and the event counts, which run while they return.
   const unsigned long long lt = (1ull << lane) - 1ull;
   const unsigned long long be0 = __ballot(cnt_e & 1), be1 = __ballot(cnt_e & 2),
-                           be2 = __ballot(cnt_e & 4);
-  const unsigned long long bi0 = __ballot(cnt_i & 1), bi1 = __ballot(cnt_i & 2),
-                           bi2 = QUEUE ? 0ull : __ballot(cnt_i & 4);
+                           be2 = QUEUE ? __ballot(cnt_e & 4) : 0ull;
+  const unsigned long long bi0 = __ballot(cnt_i & 1), bi1 = __ballot(cnt_i & 2), bi2 = 0ull;
   const uint32_t pre_e = __popcll(be0 & lt) + 2 * __popcll(be1 & lt) + 4 * __popcll(be2 & lt);
   const uint32_t pre_i = __popcll(bi0 & lt) + 2 * __popcll(bi1 & lt) + 4 * __popcll(bi2 & lt);
   const uint32_t te = __popcll(be0) + 2 * __popcll(be1) + 4 * __popcll(be2);
@@ -1094,11 +1084,9 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
   if (__ballot(ev != 0u)) {
     constexpr int q0 = QUEUE ? EV_ELASTIC : EV_ABS_E_CATH;
     constexpr int q1 = QUEUE ? EV_ABS_E_CATH : EV_ROULETTE;
-    const bool twice = !QUEUE && __ballot(ev2 != 0u);
 #pragma unroll
     for (int q = q0; q < q1; ++q) {
-      uint32_t n = (uint32_t)__popcll(__ballot((ev >> q) & 1u));
-      if (twice) n += (uint32_t)__popcll(__ballot((ev2 >> q) & 1u));
+      const uint32_t n = (uint32_t)__popcll(__ballot((ev >> q) & 1u));
       if (lane == 0 && n) atomicAdd(&evw[q], n);
     }
   }
@@ -1267,19 +1255,18 @@ __device__ void collide_ion(const Ctx<R>& C, IP& P, int inst, uint32_t step,
   o.mi = 1u;
 }
 
-// One marker of a tile, taken by slot H of its lane's outputs: gather at
-// x^n, null-collision draw, flight, walls and emission.  A collision
-// candidate sets cand and produces nothing yet; otherwise the marker, or the
-// electron its cathode impact emits, becomes output H.
-template <typename R, int MODE, int H>
+// One marker of a tile: gather at x^n, null-collision draw, flight, walls
+// and emission.  A collision candidate sets cand and produces nothing yet;
+// otherwise the marker, or the electron its cathode impact emits, becomes
+// the lane's output.
+template <typename R, int MODE>
 __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp,
                                         uint32_t g, uint32_t step, bool valid, Mk<R>& m,
-                                        LaneOut<R>& o, uint32_t& ev, uint32_t& ev2,
-                                        uint32_t& err, bool& cand) {
+                                        LaneOut<R>& o, uint32_t& ev, uint32_t& err, bool& cand) {
   if (!valid) return;
   if (MODE == MODE_REFRESH) {
-    if (sp == 0) { o.e[H] = m; o.me |= 1u << H; }
-    else { o.i[H] = m; o.mi |= 1u << H; }
+    if (sp == 0) { o.e[0] = m; o.me = 1u; }
+    else { o.i[0] = m; o.mi = 1u; }
     return;
   }
   // the null-collision draw does not depend on the field and overlaps the
@@ -1319,7 +1306,7 @@ __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp
   if (!finite) {
     err |= ERR_NONFINITE;
   } else if (out_lo) {
-    note(ev, ev2, 1u << (sp == 0 ? EV_ABS_E_CATH : EV_ABS_I_CATH));
+    ev |= 1u << (sp == 0 ? EV_ABS_E_CATH : EV_ABS_I_CATH);
     if (sp == 1) {
       // ion-induced secondary emission (Sec. IV): an electron at rest at
       // the cathode with probability gamma_se, or with the yield of
@@ -1330,18 +1317,18 @@ __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp
                            ? unif<R>(r.x) < impact_yield<R>(E, (R)P.qm_i, (R)P.dx, m)
                            : (r.x >> 9) < P.t_see;
       if (see) {
-        note(ev, ev2, 1u << EV_SEE);
+        ev |= 1u << EV_SEE;
         Mk<R> e;
         e.cell = 0;
         e.off = R(0);
         e.vx = e.vy = e.vz = R(0);
         e.id = child(r.z, r.w);
-        o.e[H] = e;
-        o.me |= 1u << H;
+        o.e[0] = e;
+        o.me = 1u;
       }
     }
   } else if (out_hi) {
-    note(ev, ev2, 1u << (sp == 0 ? EV_ABS_E_ANODE : EV_ABS_I_ANODE));
+    ev |= 1u << (sp == 0 ? EV_ABS_E_ANODE : EV_ABS_I_ANODE);
   } else {
     m.cell = cell;
     m.off = f;
@@ -1353,8 +1340,8 @@ __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp
     else tcand = sp == 0 ? P.t_null_e : (P.sigma_cx > 0.0 ? P.t_null_cx : 0u);
     cand = u < tcand;
     if (!cand) {
-      if (sp == 0) { o.e[H] = m; o.me |= 1u << H; }
-      else { o.i[H] = m; o.mi |= 1u << H; }
+      if (sp == 0) { o.e[0] = m; o.me = 1u; }
+      else { o.i[0] = m; o.mi = 1u; }
     }
   }
 }
@@ -1371,7 +1358,7 @@ __device__ __forceinline__ const void* kernarg_base() {
 }
 
 template <typename R, int MODE>
-__global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 4 : 1) k_gen(Ctx<R> C_arg) {
+__global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 5 : 1) k_gen(Ctx<R> C_arg) {
   (void)C_arg;
   const Ctx<R>& C = *reinterpret_cast<const Ctx<R>*>(kernarg_base());
   extern __shared__ uint32_t s_prefix[];  // 2 n_inst + 1 tile offsets (dynamic)
@@ -1443,7 +1430,7 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 4 : 1) k_gen(Ctx<R> C_
     q_head = ring(q_head, n);
     q_count -= n;
     next_output(W, param(C.ip, W.inst));
-    emit<R, MODE, true>(C, W, win, s_hist, o, ev, 0u, err, g, bsel, evw);
+    emit<R, MODE, true>(C, W, win, s_hist, o, ev, err, g, bsel, evw);
   };
   // append marker m to the queue at offset off (< QW) past its head
   auto q_put = [&](const Mk<R>& m, uint32_t off) {
@@ -1456,25 +1443,20 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 4 : 1) k_gen(Ctx<R> C_
     q_id[wv][s] = m.id;
   };
 
-  // A wave takes two tiles of its run at once, one marker of each per lane,
-  // when both belong to the same (instance, species): two independent
-  // loads, gathers and flights per lane, and one reservation per species
-  // for both.
+  // One tile at a time, one marker per lane: a single marker's registers
+  // leave room for five waves per SIMD, which hide more of the load and
+  // atomic latency than two markers per lane at four waves did.
   TileCursor cur;
-  for (uint32_t t = t_begin; t < t_end;) {
+  for (uint32_t t = t_begin; t < t_end; ++t) {
     cur.locate(s_prefix, nk, t);
     const int k = cur.kc, inst = k >> 1, sp = k & 1;
     IP& P = param(C.ip, inst);
-    const bool two = t + 1u < t_end && t + 1u < cur.kend;
-    int part0, part1 = 0;
-    uint32_t first0, first1 = 0u;
-    cur.place(t, P.parts, part0, first0);
-    if (two) cur.place(t + 1u, P.parts, part1, first1);
-    const uint32_t n0 = count_in(C.counts, C.n_inst, g, inst, sp, part0);
-    const uint32_t n1 = two ? count_in(C.counts, C.n_inst, g, inst, sp, part1) : 0u;
-    const uint32_t idx0 = first0 + (uint32_t)tid, idx1 = first1 + (uint32_t)tid;
-    const int64_t pb0 = P.seg + (int64_t)part0 * P.cap_p;
-    const int64_t pb1 = P.seg + (int64_t)part1 * P.cap_p;
+    int part;
+    uint32_t first;
+    cur.place(t, P.parts, part, first);
+    const uint32_t n = count_in(C.counts, C.n_inst, g, inst, sp, part);
+    const uint32_t idx = first + (uint32_t)tid;
+    const int64_t pb = P.seg + (int64_t)part * P.cap_p;
     if (inst != W.inst || sp != W.sp) {
       // new (instance, species): collide what is queued for the old one
       while (q_count > 0) run_queue(q_count < (uint32_t)WAVE ? q_count : (uint32_t)WAVE);
@@ -1482,7 +1464,7 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 4 : 1) k_gen(Ctx<R> C_
         // flush the old deposit window, anchor the new one a quarter window
         // below the tile's first marker
         if (win.inst >= 0) dep_flush(C, s_hist, win, s_evw);
-        int c0 = first0 < n0 ? gbuf(C, bsel, sp).cell(pb0 + first0) : 0;
+        int c0 = first < n ? gbuf(C, bsel, sp).cell(pb + first) : 0;
         int anchor = c0 - HWIN / 4;
         const int top = P.cells + 1 - HWIN;
         anchor = anchor > top ? top : anchor;
@@ -1497,47 +1479,31 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 4 : 1) k_gen(Ctx<R> C_
     }
     const Soa<R> in = gbuf(C, bsel, sp);
 
-    // loads inside the partitions need not wait for the counts
-    Mk<R> m0, m1;
-    if (idx0 < (uint32_t)P.cap_p) {
-      const int64_t s = pb0 + idx0;
-      m0.cell = in.cell(s);
-      m0.off = in.off(s);
-      m0.vx = in.vx(s);
-      m0.vy = in.vy(s);
-      m0.vz = in.vz(s);
-      m0.id = in.id(s);
-    }
-    if (two && idx1 < (uint32_t)P.cap_p) {
-      const int64_t s = pb1 + idx1;
-      m1.cell = in.cell(s);
-      m1.off = in.off(s);
-      m1.vx = in.vx(s);
-      m1.vy = in.vy(s);
-      m1.vz = in.vz(s);
-      m1.id = in.id(s);
+    // loads inside the partition need not wait for its count
+    Mk<R> m;
+    if (idx < (uint32_t)P.cap_p) {
+      const int64_t s = pb + idx;
+      m.cell = in.cell(s);
+      m.off = in.off(s);
+      m.vx = in.vx(s);
+      m.vy = in.vy(s);
+      m.vz = in.vz(s);
+      m.id = in.id(s);
     }
     LaneOut<R> o;
     o.me = o.mi = 0u;
-    uint32_t ev = 0, ev2 = 0, err = 0;
-    bool cand0 = false, cand1 = false;
-    advance<R, MODE, 0>(C, P, inst, sp, g, W.step, idx0 < n0, m0, o, ev, ev2, err, cand0);
-    // the second marker's arithmetic after the first's (its loads are in
-    // flight meanwhile): interleaving the two flights costs registers
-    __builtin_amdgcn_sched_barrier(0);
-    advance<R, MODE, 1>(C, P, inst, sp, g, W.step, two && idx1 < n1, m1, o, ev, ev2, err, cand1);
+    uint32_t ev = 0, err = 0;
+    bool cand = false;
+    advance<R, MODE>(C, P, inst, sp, g, W.step, idx < n, m, o, ev, err, cand);
     if (MODE == MODE_STEP) {
       // append the wave's candidates to its queue (fewer than WAVE wait)
-      const unsigned long long b0 = __ballot(cand0), b1 = __ballot(cand1);
-      const uint32_t c0 = (uint32_t)__popcll(b0);
-      if (cand0) q_put(m0, q_count + (uint32_t)__popcll(b0 & lt));
-      if (cand1) q_put(m1, q_count + c0 + (uint32_t)__popcll(b1 & lt));
-      q_count += c0 + (uint32_t)__popcll(b1);
+      const unsigned long long b = __ballot(cand);
+      if (cand) q_put(m, q_count + (uint32_t)__popcll(b & lt));
+      q_count += (uint32_t)__popcll(b);
     }
     next_output(W, P);
-    emit<R, MODE, false>(C, W, win, s_hist, o, ev, ev2, err, g, bsel, evw);
+    emit<R, MODE, false>(C, W, win, s_hist, o, ev, err, g, bsel, evw);
     while (MODE == MODE_STEP && q_count >= (uint32_t)WAVE) run_queue((uint32_t)WAVE);
-    t += two ? 2u : 1u;
   }
   while (q_count > 0) run_queue(q_count < (uint32_t)WAVE ? q_count : (uint32_t)WAVE);
   if (win.inst >= 0) dep_flush(C, s_hist, win, s_evw);
