@@ -906,6 +906,9 @@ __device__ void tile_prefix(const Ctx<R>& C, uint32_t g, uint32_t* s_prefix, dou
 struct TileCursor {
   int kc = -1;
   uint32_t kbeg = 0, kend = 0;
+  uint32_t next = 0xffffffffu;  // tile whose place is in (part, chunk)
+  uint32_t per_part = 0, chunk = 0;
+  int part = 0;
   __device__ void locate(const uint32_t* s_prefix, int nk, uint32_t t) {
     if (kc < 0) {
       int lo = 0, hi = nk;
@@ -922,14 +925,27 @@ struct TileCursor {
       ++kc;
       kbeg = kend;
       kend = s_prefix[kc + 1];
+      next = 0xffffffffu;
     }
   }
-  // partition and first slot of tile t (after locate(t)) for P partitions
-  __device__ void place(uint32_t t, int parts, int& part, uint32_t& first) const {
-    const uint32_t per_part = (kend - kbeg) / (uint32_t)parts;  // tiles per partition
-    const uint32_t j = t - kbeg;
-    part = (int)(j / per_part);
-    first = (j % per_part) * BLOCK;
+  // partition and first slot of tile t (after locate(t)) for P partitions,
+  // P a power of two.  A workgroup walks its tiles in order, so the place of
+  // the next tile follows from this one's; the division runs only on the
+  // first tile of a pair.
+  __device__ void place(uint32_t t, int parts, int& part_out, uint32_t& first) {
+    if (t != next) {
+      per_part = (kend - kbeg) >> __builtin_ctz((uint32_t)parts);  // tiles per partition
+      const uint32_t j = t - kbeg;
+      part = (int)(j / per_part);
+      chunk = j - (uint32_t)part * per_part;
+    }
+    part_out = part;
+    first = chunk * BLOCK;
+    next = t + 1u;
+    if (++chunk == per_part) {
+      chunk = 0;
+      ++part;
+    }
   }
 };
 
