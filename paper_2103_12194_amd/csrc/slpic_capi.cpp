@@ -234,6 +234,7 @@ InstParams derive(const slpic_config* cfg, const slpic_instance& I, const slpic_
   else if (I.v_limit > 0) P.v0 = I.v_limit;
   else P.v0 = std::sqrt(2.0 * kQE * std::fabs(I.V) / kMAR);  // Sec. IV speed limit
   P.limited = std::isfinite(P.v0) ? 1 : 0;
+  P.inv_v0 = P.limited ? 1.0 / P.v0 : 0.0;
   if (I.dt > 0) P.dt = I.dt;
   else if (P.limited) P.dt = cfg->cfl * P.dx / P.v0;
   else P.dt = cfg->cfl * P.dx / std::sqrt(2.0 * kQE * std::fabs(I.V) / kME);

@@ -61,6 +61,7 @@ struct InstParams {
   double vth_i;             // sqrt(k_B T / m_Ar)
   double w_j0;
   double src;               // cathode source: markers per step at weight w_j0
+  double inv_v0;            // 1 / v0 (0 for PIC)
   int64_t seg;              // first slot of the instance in each species array
   int64_t cap;              // markers per species (sum over partitions)
   int64_t cap_p;            // slots per partition: partition p of the instance

@@ -206,11 +206,12 @@ __device__ __forceinline__ R time_span(R s0, R len, R c, R inv_v0, R ss) {
   return t;
 }
 
-// Exact speed-limited flight over dt in the uniform acceleration a along x.
-// Returns the displacement, the new v_x and, when v_x changes sign inside the
-// flight, the displacement of the turning point.
+// Exact speed-limited flight over dt in the uniform acceleration a along x
+// (inv_v0 = 1 / v0, precomputed per instance).  Returns the displacement, the
+// new v_x and, when v_x changes sign inside the flight, the displacement of
+// the turning point.
 template <typename R>
-__device__ void flight(R vx, R c, R a, R dt, R v0, int limited, R& disp, R& vx1,
+__device__ void flight(R vx, R c, R a, R dt, R v0, R inv_v0, int limited, R& disp, R& vx1,
                        bool& turns, R& turn_disp) {
   R dv;  // change of v_x (= a tau)
   R tau;
@@ -227,7 +228,7 @@ __device__ void flight(R vx, R c, R a, R dt, R v0, int limited, R& disp, R& vx1,
     //   time_span(s0, delta) = |a| dt
     const R sg = a > R(0) ? R(1) : R(-1);
     const R at = a * sg, s0 = sg * vx;
-    const R rhs = at * dt, inv_v0 = R(1) / v0;
+    const R rhs = at * dt;
     const R ss = c < v0 ? Fm<R>::sqrt(v0 * v0 - c * c) : R(0);
     const R w0 = Fm<R>::sqrt(w0sq);
     R lo = R(0), hi = rhs, delta;
@@ -319,6 +320,12 @@ __device__ __forceinline__ R beta_fast(R v2, R v0, int limited) {
   if (!limited) return R(1);
   const R v = Fm<R>::sqrt(v2);
   return v > v0 ? Fm<R>::div(v0, v) : R(1);
+}
+// FP32: one reciprocal square root instead of a square root and a
+// reciprocal
+__device__ __forceinline__ float beta_fast(float v2, float v0, int limited) {
+  if (!limited) return 1.0f;
+  return v2 > v0 * v0 ? v0 * __builtin_amdgcn_rsqf(v2) : 1.0f;
 }
 
 // ---------------------------------------------------------------- collisions
@@ -1097,13 +1104,21 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
   }
 
   // events: wave totals by ballot; removed and split_added are in 0..3
-  if (__ballot(ev != 0u)) {
-    constexpr int q0 = QUEUE ? EV_ELASTIC : EV_ABS_E_CATH;
-    constexpr int q1 = QUEUE ? EV_ABS_E_CATH : EV_ROULETTE;
+  if (QUEUE) {
+    if (__ballot(ev != 0u)) {
 #pragma unroll
-    for (int q = q0; q < q1; ++q) {
-      const uint32_t n = (uint32_t)__popcll(__ballot((ev >> q) & 1u));
-      if (lane == 0 && n) atomicAdd(&evw[q], n);
+      for (int q = EV_ELASTIC; q < EV_ABS_E_CATH; ++q) {
+        const uint32_t n = (uint32_t)__popcll(__ballot((ev >> q) & 1u));
+        if (lane == 0 && n) atomicAdd(&evw[q], n);
+      }
+    }
+  } else {
+    // wall and emission events are rare: the lanes that have one count it
+    uint32_t b = ev;
+    while (b) {
+      const int q = __builtin_ctz(b);
+      atomicAdd(&evw[q], 1u);
+      b &= b - 1u;
     }
   }
   if (pop != POP_NONE) {
@@ -1295,7 +1310,7 @@ __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp
   const R c = Fm<R>::sqrt(m.vy * m.vy + m.vz * m.vz);
   R disp, vx1, tdisp;
   bool turns;
-  flight<R>(m.vx, c, a, (R)P.dt, (R)P.v0, P.limited, disp, vx1, turns, tdisp);
+  flight<R>(m.vx, c, a, (R)P.dt, (R)P.v0, (R)P.inv_v0, P.limited, disp, vx1, turns, tdisp);
   const R inv_dx = (R)P.inv_dx;
   R f = m.off + disp * inv_dx;
   const R fl = m_floor(f);
