@@ -19,8 +19,13 @@ Prints one JSON line:
   plain       the same instances stepped one handle at a time (n_inst = 1)
   cpu_baseline the FP64 oracle on a bounded sample of the same instances
 
+  configs     (--all-configs) the other workloads, each timed on its own:
+              the plain FP64 gap (1 cm, 64 cells, 1e4 seeds), the 512-cell
+              2 cm gap (1e6 seeds), the 4096-cell 5 cm gap (1e7 seeds, cell
+              sort every 16 steps) and the 256-instance bisection round
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-plain]
-       [--no-cpu] [--graph] [--scale S]
+       [--no-cpu] [--graph] [--scale S] [--pic] [--all-configs]
        python bench.py --copy-calibration   (plain device copy of 1 GiB,
        for scaling HBM counters)
 """
@@ -82,6 +87,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--pic", action="store_true",
                     help="also compare SLPIC with plain PIC on one gap")
+    ap.add_argument("--all-configs", action="store_true",
+                    help="also time the single-gap and bisection-round workloads")
     return ap.parse_args()
 
 
@@ -217,6 +224,39 @@ def pic_leg(xs):
     return out
 
 
+def configs_leg(xs):
+    """Throughput of the other workloads, each from its seeded state after a
+    warmup that lets its population settle: (name, workload, warmup,
+    timed steps)."""
+    import paper_2103_12194_amd as slpic
+    from synth import configs
+    legs = [("C1 plain FP64 gap", configs.c1(), 200, 400),
+            ("C2 512-cell gap, 300 V", configs.c2(300.0), 200, 200),
+            ("C3 4096-cell gap, sort every 16 steps", configs.c3(), 2048, 64),
+            ("C5 256-instance bisection round", configs.c5(xs.sigma_total_max()), 100, 50)]
+    out = {}
+    for name, w, warm, steps in legs:
+        sim = slpic.Sim(w.instances, w.run, xs)
+        sim.step(warm)
+        sim.sync()
+        s0, secs, (gen_ms, tail_ms, nk) = time_steps(sim, steps, profile=True)
+        ps = history_total(sim, s0, steps)
+        bytes_per = 2.0 * (4 + 3 * 8 + 8 + 8) if w.run.precision == 64 else BYTES_PER_MARKER_STEP
+        achieved = bytes_per * ps / nk / (gen_ms / nk * 1e-3) / 1e9
+        out[name] = {"value": ps / secs, "unit": "particle-steps/s", "n_inst": len(w.instances),
+                     "dtype": "f64" if w.run.precision == 64 else "f32",
+                     "warmup": warm, "steps": steps, "ms_per_step": secs * 1e3 / steps,
+                     "kernel_ms": gen_ms / nk, "tail_kernel_ms": tail_ms / nk,
+                     "markers_per_step": ps / steps, "bytes_per_marker_step": bytes_per,
+                     "achieved_GBs": round(achieved, 1),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4)}
+        print(f"# {name}: {ps / secs:.3e} particle-steps/s, particle kernel "
+              f"{gen_ms / nk:.3f} ms, {ps / steps:.3e} markers/step", file=sys.stderr, flush=True)
+        sim.close()
+        del sim
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -279,6 +319,7 @@ def main():
         print(f"# plain leg: {plain['value']:.3e} particle-steps/s", file=sys.stderr, flush=True)
 
     pic = pic_leg(xs) if args.pic else None
+    others = configs_leg(xs) if args.all_configs else None
 
     cpu = None
     if not args.no_cpu:
@@ -304,6 +345,8 @@ def main():
     }
     if pic is not None:
         line["pic"] = pic
+    if others is not None:
+        line["configs"] = others
     print(json.dumps(line), flush=True)
     return 0
 
