@@ -1,19 +1,22 @@
 // HIP kernels (gfx950) of the speed-limited PIC / Monte Carlo collision step.
 //
-// One launch of k_gen<R, MODE_STEP> advances every marker of every instance
-// by one step: gather, speed-limited free flight (Eqs. 8-9 with beta of
+// A step is two launches.  k_gen<R, MODE_STEP> advances every marker of
+// every instance: gather, speed-limited free flight (Eqs. 8-9 with beta of
 // Eq. 11, solved exactly for the gathered field), wall absorption and
 // ion-induced secondary emission, null-collision MCC with the SLPIC rate of
 // Eqs. (15)-(16), population control, stream compaction of survivors and new
-// markers, and the linear charge deposit.  The workgroup that completes the
-// last tile of an instance then solves that instance's Poisson problem in
-// FP64 and writes its statistics row.
+// markers, and the linear charge deposit in fixed point.  k_tail, one
+// workgroup per instance, then turns the deposit into the charge density,
+// solves the instance's Poisson problem in FP64, writes its statistics row,
+// decides the next step's population control, injects the cathode source
+// and advances the generation.
 //
-// Memory layout: structure-of-arrays markers (int32 cell, R offset in the
-// cell, R v_x, v_y, v_z, uint64 id) in two ping-pong buffers per species;
-// each instance owns a fixed segment [seg, seg + cap) of every array.
-// Work unit: a tile of 256 consecutive markers of one (instance, species);
-// tiles are dealt round-robin to the workgroups of the launch.
+// Memory layout: markers (int32 cell, R offset in the cell, R v_x, v_y, v_z,
+// uint64 id) in chunks of 64 slots, each field contiguous within a chunk, in
+// two ping-pong buffers per species; each instance owns a segment of output
+// partitions.  Work unit: a tile of 256 markers of one (instance, species),
+// one marker per lane of four waves; each workgroup takes a contiguous run
+// of tiles.
 #include <hip/hip_runtime.h>
 
 #include "slpic_internal.hpp"
