@@ -1307,7 +1307,12 @@ __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp
   // gather
   const R* E = C.E + (size_t)(g % 2u) * C.total_nodes + P.node;
   const R e0 = E[m.cell], e1 = E[m.cell + 1];
+  __builtin_amdgcn_sched_barrier(0);  // the gather goes out before the draw
   const U4 rn = draw(m.id, step, sp == 0 ? (uint32_t)CH_COLL : (uint32_t)CH_CX, C.seed, inst);
+  // only the first word is used, at the end of the step; the empty asm
+  // keeps the compiler from sinking the ten rounds there, after the flight
+  uint32_t rnx = rn.x;
+  asm volatile("" : "+v"(rnx));
   const R Ep = e0 + m.off * (e1 - e0);
   const R a = (R)(sp == 0 ? P.qm_e : P.qm_i) * Ep;
   const R c = Fm<R>::sqrt(m.vy * m.vy + m.vz * m.vz);
@@ -1368,7 +1373,7 @@ __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp
     m.off = f;
     m.vx = vx1;
     // null-collision test: candidates go to the queue
-    const uint32_t u = rn.x >> 9;
+    const uint32_t u = rnx >> 9;
     uint32_t tcand;
     if (C.fixed) tcand = sp == 0 ? (C.n_chan > 0 ? P.t_fixed[C.n_chan - 1] : 0u) : P.t_fixed_cx;
     else tcand = sp == 0 ? P.t_null_e : (P.sigma_cx > 0.0 ? P.t_null_cx : 0u);
