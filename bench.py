@@ -141,11 +141,13 @@ def time_steps(sim, steps, profile):
 
 
 def plain_leg(w, xs, steps, warmup):
-    """Each instance in a handle of its own, stepped alone."""
+    """Each instance in a handle of its own, stepped alone, with the Philox
+    stream it has in the batch: it repeats the batched run draw for draw."""
+    import dataclasses
     import paper_2103_12194_amd as slpic
     ps, secs = 0, 0.0
-    for inst in w.instances:
-        sim = slpic.Sim([inst], w.run, xs)
+    for k, inst in enumerate(w.instances):
+        sim = slpic.Sim([dataclasses.replace(inst, stream=k)], w.run, xs)
         sim.step(warmup)
         s0, dt, _ = time_steps(sim, steps, profile=False)
         ps += history_total(sim, s0, steps)

@@ -71,7 +71,7 @@ enum { SLPIC_FLAG_PRODUCTS_AT_REST = 1, SLPIC_FLAG_SEE_ENERGY = 2, SLPIC_FLAG_FL
 typedef struct slpic_config {
   int32_t precision;     /* 32: FP32 particles, FP64 field and totals;
                             64: FP64 throughout */
-  uint32_t seed;         /* Philox key word 0 (word 1 = instance index) */
+  uint32_t seed;         /* Philox key word 0 (word 1: slpic_instance.stream) */
   uint32_t flags;        /* SLPIC_FLAG_* */
   int32_t resort_period; /* cell sort of the markers before every step whose
                             count of completed steps is a multiple of it
@@ -106,6 +106,11 @@ typedef struct slpic_instance {
                         splits them into output partitions and rounds each
                         up to whole chunks of 64 slots (slpic_partitions
                         reports the result) */
+  int64_t stream;    /* Philox key word 1 of every draw of this instance
+                        (seeding included), in [0, 2^32); < 0: the
+                        instance's index in the batch.  Instances with equal
+                        seed, stream and inputs evolve identically whatever
+                        batch they are in. */
 } slpic_instance;
 
 /* Electron-neutral cross sections: piecewise linear in energy between

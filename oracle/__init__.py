@@ -176,7 +176,8 @@ class Sim:
     """One gap instance stepped by the oracle.
 
     inst: synth.configs.Instance, run: synth.configs.Run,
-    xs: synth.CrossSections, instance_index: Philox key word 1.
+    xs: synth.CrossSections, instance_index: Philox key word 1 (the
+    instance's index in a batch), unless inst.stream >= 0 sets it.
     """
 
     def __init__(self, inst, run, xs, instance_index=0, flags=0):
@@ -199,7 +200,8 @@ class Sim:
             fixed_prob_cx=xs.fixed_prob_cx, n_seed=inst.n_seed,
             n_target=inst.n_target, cells=inst.cells,
             seed_mode=inst.seed_mode, seed=run.seed & 0xFFFFFFFF,
-            instance=instance_index, flags=flags, pad0=0,
+            instance=inst.stream if getattr(inst, "stream", -1) >= 0 else instance_index,
+            flags=flags, pad0=0,
             n_chan=xs.n_chan, n_grid=xs.n_grid,
             energies=e.ctypes.data_as(dp), sigma=sg.ctypes.data_as(dp),
             threshold_eV=th.ctypes.data_as(dp),

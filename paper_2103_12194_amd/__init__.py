@@ -46,7 +46,8 @@ class slpic_instance(C.Structure):
                 ("gamma_se", C.c_double), ("v_limit", C.c_double),
                 ("dt", C.c_double), ("cells", C.c_int32),
                 ("seed_mode", C.c_int32), ("n_seed", C.c_int64),
-                ("n_target", C.c_int64), ("capacity", C.c_int64)]
+                ("n_target", C.c_int64), ("capacity", C.c_int64),
+                ("stream", C.c_int64)]
 
 
 class slpic_xs(C.Structure):
@@ -148,7 +149,7 @@ def make_instances(insts):
                                 gamma_se=i.gamma_se, v_limit=i.v_limit,
                                 dt=i.dt, cells=i.cells, seed_mode=i.seed_mode,
                                 n_seed=i.n_seed, n_target=i.n_target,
-                                capacity=cap)
+                                capacity=cap, stream=getattr(i, "stream", -1))
     return arr
 
 

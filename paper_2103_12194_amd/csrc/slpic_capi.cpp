@@ -187,6 +187,7 @@ std::string validate(const slpic_config* cfg, const slpic_instance* inst, int n_
     if (!(I.d > 0) || I.cells < 2 || !(I.p_torr >= 0)) return "instance needs d > 0, cells >= 2, p >= 0";
     if (!(I.gamma_se >= 0 && I.gamma_se <= 1)) return "gamma_se must be in [0, 1]";
     if (I.seed_mode < 0 || I.seed_mode > 2) return "unknown seed mode";
+    if (I.stream > 0xffffffffll) return "stream must be below 2^32 (or negative: the batch index)";
     if (I.n_seed < 0 || I.n_target < 0) return "n_seed and n_target must be >= 0";
     if (I.capacity < I.n_seed || I.capacity < 1 || I.capacity > 0x7fffffff)
       return "capacity must be in [max(1, n_seed), 2^31)";
@@ -256,6 +257,7 @@ InstParams derive(const slpic_config* cfg, const slpic_instance& I, const slpic_
   P.t_null_e = prob_threshold(-std::expm1(-P.nu_max_e * P.dt));
   P.t_null_cx = prob_threshold(-std::expm1(-P.nu_max_cx * P.dt));
   P.t_see = prob_threshold(I.gamma_se);
+  P.key = I.stream >= 0 ? (uint32_t)I.stream : (uint32_t)i;
   if (xs->fixed_prob) {
     double cum = 0.0;
     for (int k = 0; k < xs->n_chan; ++k) {

@@ -71,6 +71,7 @@ struct InstParams {
   int32_t limited;          // 0: plain PIC (beta == 1)
   int32_t parts;            // partitions P, a power of two (tile j reads j mod P)
   uint32_t t_null_e, t_null_cx, t_see;
+  uint32_t key;             // Philox key word 1 of the instance's draws
   uint32_t t_fixed[MAX_CHAN];
   uint32_t t_fixed_cx;
 };

@@ -537,7 +537,7 @@ __device__ double inject(const Ctx<R>& C, IP& P, int inst, const InstState& cur,
   const uint32_t step = cur.step;
   const double want = P.src * (P.w_j0 / cur.w_j);
   const double fl = floor(want);
-  const U4 rf = draw(0, step, CH_INJECT | (1u << 8), C.seed, inst);
+  const U4 rf = draw(0, step, CH_INJECT | (1u << 8), C.seed, P.key);
   int64_t n = (int64_t)fl + (unif<double>(rf.x) < want - fl ? 1 : 0);
   if (n > P.cap) {  // more than the instance holds: an error, as in any overflow
     n = P.cap;
@@ -554,14 +554,14 @@ __device__ double inject(const Ctx<R>& C, IP& P, int inst, const InstState& cur,
     uint64_t id[2] = {0, 0};
     int m = 0;
     if (k < n) {
-      const U4 r = draw((uint64_t)k, step, CH_INJECT, C.seed, inst);
+      const U4 r = draw((uint64_t)k, step, CH_INJECT, C.seed, P.key);
       id[0] = child(r.x, r.y);
       m = 1;
       if (pop == POP_ROULETTE) {
-        const U4 q = draw(id[0], step, CH_ROULETTE, C.seed, inst);
+        const U4 q = draw(id[0], step, CH_ROULETTE, C.seed, P.key);
         m = (q.x >> 9) < (1u << 22) ? 1 : 0;
       } else if (pop == POP_SPLIT) {
-        const U4 q = draw(id[0], step, CH_CHILD | (1u << 8), C.seed, inst);
+        const U4 q = draw(id[0], step, CH_CHILD | (1u << 8), C.seed, P.key);
         id[1] = child(q.x, q.y);
         m = 2;
       }
@@ -1031,13 +1031,13 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
   for (int j = 0; j < 2; ++j) {
     if (!(o.me >> j & 1u)) continue;
     if (pop == POP_ROULETTE) {
-      const U4 r = draw_cold(o.e[j].id, step, CH_ROULETTE, C.seed, inst);
+      const U4 r = draw_cold(o.e[j].id, step, CH_ROULETTE, C.seed, P.key);
       if ((r.x >> 9) < (1u << 22)) { keep_e |= 1u << j; ++cnt_e; }
     } else {
       keep_e |= 1u << j;
       ++cnt_e;
       if (pop == POP_SPLIT) {
-        const U4 r = draw_cold(o.e[j].id, step, CH_CHILD | (1u << 8), C.seed, inst);
+        const U4 r = draw_cold(o.e[j].id, step, CH_CHILD | (1u << 8), C.seed, P.key);
         clone_e[j] = child(r.x, r.y);
         ++cnt_e;
       }
@@ -1047,13 +1047,13 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
   for (int j = 0; j < 2; ++j) {
     if (!(o.mi >> j & 1u)) continue;
     if (pop == POP_ROULETTE) {
-      const U4 r = draw_cold(o.i[j].id, step, CH_ROULETTE, C.seed, inst);
+      const U4 r = draw_cold(o.i[j].id, step, CH_ROULETTE, C.seed, P.key);
       if ((r.x >> 9) < (1u << 22)) { keep_i |= 1u << j; ++cnt_i; }
     } else {
       keep_i |= 1u << j;
       ++cnt_i;
       if (pop == POP_SPLIT) {
-        const U4 r = draw_cold(o.i[j].id, step, CH_CHILD | (1u << 8), C.seed, inst);
+        const U4 r = draw_cold(o.i[j].id, step, CH_CHILD | (1u << 8), C.seed, P.key);
         clone_i[j] = child(r.x, r.y);
         ++cnt_i;
       }
@@ -1185,7 +1185,7 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
 template <typename R>
 __device__ void collide_electron(const Ctx<R>& C, IP& P, int inst, uint32_t step,
                                  Mk<R>& m, LaneOut<R>& o, uint32_t& ev, uint32_t& err) {
-  const U4 r = draw(m.id, step, CH_COLL, C.seed, inst);
+  const U4 r = draw(m.id, step, CH_COLL, C.seed, P.key);
   const R v2 = m.vx * m.vx + m.vy * m.vy + m.vz * m.vz;
   const R eps = v2 * (R)(0.5 * ME / QE);
   int ch = -1;
@@ -1221,7 +1221,7 @@ __device__ void collide_electron(const Ctx<R>& C, IP& P, int inst, uint32_t step
     R eej = R(0), esc = R(0);
     U4 q = U4{0u, 0u, 0u, 0u};
     if (ioniz) {
-      q = draw_cold(m.id, step, CH_IONIZ, C.seed, inst);
+      q = draw_cold(m.id, step, CH_IONIZ, C.seed, P.key);
       R eav = eps - thr;
       eav = eav > R(0) ? eav : R(0);
       const R B = (R)C.ion_B;
@@ -1243,8 +1243,8 @@ __device__ void collide_electron(const Ctx<R>& C, IP& P, int inst, uint32_t step
     ev |= 1u << (kind == 0 ? EV_ELASTIC : (kind == 1 ? EV_EXCIT : EV_IONIZ));
     if (ioniz) {
       // the ejected electron and the ion at the primary's position
-      const U4 b = draw_cold(m.id, step, CH_IONBIRTH, C.seed, inst);
-      const U4 cid = draw_cold(m.id, step, CH_CHILD, C.seed, inst);
+      const U4 b = draw_cold(m.id, step, CH_IONBIRTH, C.seed, P.key);
+      const U4 cid = draw_cold(m.id, step, CH_CHILD, C.seed, P.key);
       R jx, jy, jz;
       turn(hx, hy, hz, vs_cos(eej, unif<R>(q.y)), unif<R>(q.z), jx, jy, jz);
       const R spj = Fm<R>::sqrt(eej * (R)(2.0 * QE / ME));
@@ -1270,7 +1270,7 @@ __device__ void collide_ion(const Ctx<R>& C, IP& P, int inst, uint32_t step,
                             Mk<R>& m, LaneOut<R>& o, uint32_t& ev, uint32_t& err) {
   bool hit = true;  // fixed-event candidates always exchange
   if (!C.fixed) {
-    const U4 r = draw(m.id, step, CH_CX, C.seed, inst);
+    const U4 r = draw(m.id, step, CH_CX, C.seed, P.key);
     const R v2 = m.vx * m.vx + m.vy * m.vy + m.vz * m.vz;
     const R sp1 = Fm<R>::sqrt(v2);
     const R v0 = (R)P.v0;
@@ -1281,7 +1281,7 @@ __device__ void collide_ion(const Ctx<R>& C, IP& P, int inst, uint32_t step,
     hit = unif<R>(r.y) * numax < nu;
   }
   if (hit) {
-    const U4 b = draw_cold(m.id, step, CH_CX | (1u << 8), C.seed, inst);
+    const U4 b = draw_cold(m.id, step, CH_CX | (1u << 8), C.seed, P.key);
     normals3<R>(b, (R)P.vth_i, m.vx, m.vy, m.vz);
     ev |= 1u << EV_CX;
   }
@@ -1308,7 +1308,7 @@ __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp
   const R* E = C.E + (size_t)(g % 2u) * C.total_nodes + P.node;
   const R e0 = E[m.cell], e1 = E[m.cell + 1];
   __builtin_amdgcn_sched_barrier(0);  // the gather goes out before the draw
-  const U4 rn = draw(m.id, step, sp == 0 ? (uint32_t)CH_COLL : (uint32_t)CH_CX, C.seed, inst);
+  const U4 rn = draw(m.id, step, sp == 0 ? (uint32_t)CH_COLL : (uint32_t)CH_CX, C.seed, P.key);
   // only the first word is used, at the end of the step; the empty asm
   // keeps the compiler from sinking the ten rounds there, after the flight
   uint32_t rnx = rn.x;
@@ -1351,7 +1351,7 @@ __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp
       // the cathode with probability gamma_se, or with the yield of
       // Eq. (17) at the impact energy; v_x^2 - 2 a x is constant along
       // the flight, so the ion reaches x = 0 with v_x^2 = vx^2 - 2 a x
-      const U4 r = draw_cold(m.id, step, CH_SEE, C.seed, inst);
+      const U4 r = draw_cold(m.id, step, CH_SEE, C.seed, P.key);
       const bool see = (C.flags & 2u)
                            ? unif<R>(r.x) < impact_yield<R>(E, (R)P.qm_i, (R)P.dx, m)
                            : (r.x >> 9) < P.t_see;
@@ -1759,8 +1759,8 @@ __global__ void k_seed(Ctx<R> C, int inst, int mode, int64_t n, double sigma_v, 
   o.id(s) = (uint64_t)k;
   o.cell(s) = 0;
   if (mode == 2) {
-    const U4 r0 = draw((uint64_t)k, 0u, CH_SEED, C.seed, inst);
-    const U4 r1 = draw((uint64_t)k, 0u, CH_SEED | (1u << 8), C.seed, inst);
+    const U4 r0 = draw((uint64_t)k, 0u, CH_SEED, C.seed, P.key);
+    const U4 r1 = draw((uint64_t)k, 0u, CH_SEED | (1u << 8), C.seed, P.key);
     o.off(s) = unif<R>(r0.x);
     R a, b, c;
     normals3<R>(r1, (R)sigma_v, a, b, c);

@@ -44,6 +44,7 @@ class Instance:
     n_seed: int = 0
     n_target: int = 0        # population-control target (0 = off)
     capacity: int = 0        # markers per species (0 -> derived)
+    stream: int = -1         # Philox key word 1; < 0 -> the index in its batch
 
     def speed_limit(self):
         if self.v_limit > 0:
