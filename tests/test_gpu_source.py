@@ -156,3 +156,32 @@ def test_set_source_rejects_bad_arguments(xs_argon):
     sim.set_source(0.0)
     sim.step(2)
     assert sim.sync() == 0
+
+
+def test_source_overflowing_the_capacity_is_reported_and_stays_in_bounds():
+    """A source larger than the instance holds: the injections that do not
+    fit are dropped (never written past a partition), the step reports
+    SLPIC_CAPACITY_EXCEEDED, and a neighbouring instance in the same batch
+    is untouched (it equals the same instance stepped alone)."""
+    import dataclasses
+    small = configs.Instance(d=0.01, p_torr=1.0, V=300.0, cells=64, gamma_se=0.0,
+                             seed_mode=configs.SEED_NONE, capacity=1000)
+    other = _gap(n_seed=500, n_target=0, capacity=20000)
+    xs = xsec.fixed_event([0.0, 0.0, 0.0], probs_cx=0.0)
+    run = configs.Run(precision=32)
+    sim = slpic.Sim([small, other], run, xs)
+    sim.set_source(700.0, inst=0)      # more than the capacity within two steps
+    alone = slpic.Sim([dataclasses.replace(other, stream=1)], run, xs)
+    sim.step(6)
+    alone.step(6)
+    with pytest.raises(slpic.SlpicError) as ei:
+        sim.sync()
+    assert ei.value.code == -3
+    assert alone.sync() == 0
+    occ, cap_p = sim.partitions(0, inst=0)
+    assert np.all(np.asarray(occ) <= cap_p)
+    assert sim.count(0, 0) <= len(occ) * cap_p
+    # the neighbour is exactly what it is alone
+    for sp in (0, 1):
+        compare_populations(alone.read(sp), sim.read(sp, 1), 0.0, 0.0,
+                            alone.scalars()["v0"], label=f"neighbour sp {sp}")
