@@ -84,11 +84,15 @@ def test_workspace_size_and_validation(built, xs_argon):
     assert _ws(built, [big], w.run, xs_argon) > n1
     r32 = configs.Run(precision=32)
     assert _ws(built, w.instances, r32, xs_argon) < n1
+    # any Philox stream below 2^32, or the batch index (negative), is valid
+    for st in (-1, 0, (1 << 32) - 1):
+        assert _ws(built, [configs.replace(w.instances[0], stream=st)], w.run, xs_argon) == n1
     # invalid setups report 0
     bad = [configs.replace(w.instances[0], cells=1),
            configs.replace(w.instances[0], gamma_se=1.5),
            configs.replace(w.instances[0], d=0.0),
-           configs.replace(w.instances[0], capacity=5, n_seed=10)]
+           configs.replace(w.instances[0], capacity=5, n_seed=10),
+           configs.replace(w.instances[0], stream=1 << 32)]
     for b in bad:
         assert _ws(built, [b], w.run, xs_argon) == 0
     assert _ws(built, w.instances, configs.Run(precision=16), xs_argon) == 0
