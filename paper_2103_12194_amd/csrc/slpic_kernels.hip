@@ -962,9 +962,12 @@ struct TileCursor {
 // ---------------------------------------------------------------- main kernel
 template <typename R>
 struct LaneOut {
-  Mk<R> e[2];        // electrons produced by this lane (before population control)
-  Mk<R> i[2];        // ions produced by this lane
-  uint32_t me, mi;   // which slots of e[] / i[] are set (bit j: slot j)
+  Mk<R> e[2];        // electrons produced by this lane (before population
+                     // control): the marker or its emitted electron, and an
+                     // ionization's ejected electron
+  Mk<R> i;           // the ion produced by this lane: the marker or an
+                     // ionization's new ion
+  uint32_t me, mi;   // me: which slots of e[] are set (bit j: slot j); mi: i is set
 };
 
 constexpr int NWAVE = BLOCK / WAVE;
@@ -1025,7 +1028,7 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
 
   // population control: each output is kept (roulette) or doubled (split)
   uint32_t keep_e = 0, keep_i = 0;
-  uint64_t clone_e[2] = {0, 0}, clone_i[2] = {0, 0};
+  uint64_t clone_e[2] = {0, 0}, clone_i = 0;
   int cnt_e = 0, cnt_i = 0;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -1043,18 +1046,16 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
       }
     }
   }
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    if (!(o.mi >> j & 1u)) continue;
+  if (o.mi) {
     if (pop == POP_ROULETTE) {
-      const U4 r = draw_cold(o.i[j].id, step, CH_ROULETTE, C.seed, P.key);
-      if ((r.x >> 9) < (1u << 22)) { keep_i |= 1u << j; ++cnt_i; }
+      const U4 r = draw_cold(o.i.id, step, CH_ROULETTE, C.seed, P.key);
+      if ((r.x >> 9) < (1u << 22)) { keep_i = 1u; ++cnt_i; }
     } else {
-      keep_i |= 1u << j;
+      keep_i = 1u;
       ++cnt_i;
       if (pop == POP_SPLIT) {
-        const U4 r = draw_cold(o.i[j].id, step, CH_CHILD | (1u << 8), C.seed, P.key);
-        clone_i[j] = child(r.x, r.y);
+        const U4 r = draw_cold(o.i.id, step, CH_CHILD | (1u << 8), C.seed, P.key);
+        clone_i = child(r.x, r.y);
         ++cnt_i;
       }
     }
@@ -1072,11 +1073,11 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
   const unsigned long long lt = (1ull << lane) - 1ull;
   const unsigned long long be0 = __ballot(cnt_e & 1), be1 = __ballot(cnt_e & 2),
                            be2 = QUEUE ? __ballot(cnt_e & 4) : 0ull;
-  const unsigned long long bi0 = __ballot(cnt_i & 1), bi1 = __ballot(cnt_i & 2), bi2 = 0ull;
+  const unsigned long long bi0 = __ballot(cnt_i & 1), bi1 = __ballot(cnt_i & 2);
   const uint32_t pre_e = __popcll(be0 & lt) + 2 * __popcll(be1 & lt) + 4 * __popcll(be2 & lt);
-  const uint32_t pre_i = __popcll(bi0 & lt) + 2 * __popcll(bi1 & lt) + 4 * __popcll(bi2 & lt);
+  const uint32_t pre_i = __popcll(bi0 & lt) + 2 * __popcll(bi1 & lt);
   const uint32_t te = __popcll(be0) + 2 * __popcll(be1) + 4 * __popcll(be2);
-  const uint32_t ti = __popcll(bi0) + 2 * __popcll(bi1) + 4 * __popcll(bi2);
+  const uint32_t ti = __popcll(bi0) + 2 * __popcll(bi1);
   uint32_t base_e = 0u, base_i = 0u;
   if (MODE == MODE_STEP && lane == 0) {
     if (te) base_e = atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 0, W.part), te);
@@ -1095,12 +1096,10 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
       dep_add(C.acc, C.acc, hist, win, 0, P.node, C.total_nodes, e.cell,
               fixed_pt<R>(b * (R(1) - e.off), shift) * mul, fixed_pt<R>(b * e.off, shift) * mul);
     }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      if (!(keep_i >> q & 1u)) continue;
-      const Mk<R>& e = o.i[q];
+    if (keep_i) {
+      const Mk<R>& e = o.i;
       const R b = beta_fast(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
-      const unsigned long long mul = clone_i[q] ? 2ull : 1ull;
+      const unsigned long long mul = clone_i ? 2ull : 1ull;
       dep_add(C.acc, C.acc, hist, win, 1, P.node, C.total_nodes, e.cell,
               fixed_pt<R>(b * (R(1) - e.off), shift) * mul, fixed_pt<R>(b * e.off, shift) * mul);
     }
@@ -1156,20 +1155,18 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
       ++pe;
     }
   }
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    if (!(keep_i >> j & 1u)) continue;
+  if (keep_i) {
 #pragma unroll
     for (int rep = 0; rep < 2; ++rep) {
-      if (rep == 1 && !clone_i[j]) continue;
+      if (rep == 1 && !clone_i) continue;
       if (pi < (uint32_t)P.cap_p) {
         const int64_t s = W.pbase + pi;
-        oi.cell(s) = o.i[j].cell;
-        oi.off(s) = o.i[j].off;
-        oi.vx(s) = o.i[j].vx;
-        oi.vy(s) = o.i[j].vy;
-        oi.vz(s) = o.i[j].vz;
-        oi.id(s) = rep ? clone_i[j] : o.i[j].id;
+        oi.cell(s) = o.i.cell;
+        oi.off(s) = o.i.off;
+        oi.vx(s) = o.i.vx;
+        oi.vy(s) = o.i.vy;
+        oi.vz(s) = o.i.vz;
+        oi.id(s) = rep ? clone_i : o.i.id;
       } else {
         werr |= ERR_CAPACITY;
       }
@@ -1255,7 +1252,7 @@ __device__ void collide_electron(const Ctx<R>& C, IP& P, int inst, uint32_t step
       normals3<R>(b, (R)P.vth_i, i2.vx, i2.vy, i2.vz);
       i2.id = child(cid.z, cid.w);
       o.e[1] = e2;
-      o.i[0] = i2;
+      o.i = i2;
       o.mi = 1u;
     }
   }
@@ -1285,7 +1282,7 @@ __device__ void collide_ion(const Ctx<R>& C, IP& P, int inst, uint32_t step,
     normals3<R>(b, (R)P.vth_i, m.vx, m.vy, m.vz);
     ev |= 1u << EV_CX;
   }
-  o.i[0] = m;
+  o.i = m;
   o.mi = 1u;
 }
 
@@ -1300,7 +1297,7 @@ __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp
   if (!valid) return;
   if (MODE == MODE_REFRESH) {
     if (sp == 0) { o.e[0] = m; o.me = 1u; }
-    else { o.i[0] = m; o.mi = 1u; }
+    else { o.i = m; o.mi = 1u; }
     return;
   }
   // the null-collision draw does not depend on the field and overlaps the
@@ -1380,7 +1377,7 @@ __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp
     cand = u < tcand;
     if (!cand) {
       if (sp == 0) { o.e[0] = m; o.me = 1u; }
-      else { o.i[0] = m; o.mi = 1u; }
+      else { o.i = m; o.mi = 1u; }
     }
   }
 }
