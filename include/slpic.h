@@ -36,6 +36,8 @@ extern "C" {
 
 #define SLPIC_ABI_VERSION 1
 #define SLPIC_MAX_PARTITIONS 16
+/* bytes of the per-device static workspace used by slpic_create_static */
+#define SLPIC_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
 
 typedef enum slpic_status {
   SLPIC_OK = 0,
@@ -160,6 +162,27 @@ size_t slpic_workspace_bytes(const slpic_config* cfg, const slpic_instance* inst
 int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
                  const slpic_xs* xs, void* dev_workspace, size_t ws_bytes,
                  void* hip_stream, slpic_t** out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): create a
+ * handle exactly as slpic_create does, but with its device workspace in a
+ * static array that the library holds on each device until the process ends,
+ * SLPIC_STATIC_WORKSPACE_BYTES (64 MiB) per device.  The library allocates
+ * no device memory for it, here or in any later call on the handle, and the
+ * caller passes none.  The array of the current device is used; a handle
+ * made this way computes exactly what an slpic_create handle of the same
+ * setup computes.
+ *   - SLPIC_WORKSPACE_TOO_SMALL if slpic_workspace_bytes of the setup
+ *     exceeds SLPIC_STATIC_WORKSPACE_BYTES (nothing is launched);
+ *   - SLPIC_INVALID_ARG while another handle made by this call on the same
+ *     device is alive: the array holds one handle's state at a time, so
+ *     handles on one device cannot overlap (slpic_destroy frees the array
+ *     for the next create; its contents then stay as the last handle left
+ *     them, and create re-initialises everything a step reads);
+ *   - otherwise as slpic_create.
+ * Not thread-safe with respect to other calls on the handle. */
+int slpic_create_static(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
+                        const slpic_xs* xs, void* hip_stream, slpic_t** out);
 
 /* Enqueue n_steps steps of every instance on the handle's stream and return
  * without waiting.  Errors raised on the device are reported by slpic_sync. */

@@ -72,7 +72,7 @@ class slpic_stats(C.Structure):
 
 
 _lib = None
-EXPORTS = ["slpic_workspace_bytes", "slpic_create", "slpic_step", "slpic_sync",
+EXPORTS = ["slpic_workspace_bytes", "slpic_create", "slpic_create_static", "slpic_step", "slpic_sync",
            "slpic_use_graph", "slpic_load_markers", "slpic_count",
            "slpic_read_markers", "slpic_read_fields", "slpic_read_flux", "slpic_set_source",
            "slpic_read_stats",
@@ -95,6 +95,8 @@ def lib():
         L.slpic_workspace_bytes.argtypes = [P(slpic_config), P(slpic_instance), i32, P(slpic_xs)]
         L.slpic_create.argtypes = [P(slpic_config), P(slpic_instance), i32, P(slpic_xs), vp,
                                    C.c_size_t, vp, P(vp)]
+        L.slpic_create_static.argtypes = [P(slpic_config), P(slpic_instance), i32, P(slpic_xs),
+                                          vp, P(vp)]
         L.slpic_step.argtypes = [vp, i32]
         L.slpic_sync.argtypes = [vp]
         L.slpic_use_graph.argtypes = [vp, i32]
@@ -182,7 +184,10 @@ class Sim:
     energies, sigma, threshold_eV, kind, sigma_cx, fixed_prob, fixed_prob_cx.
     """
 
-    def __init__(self, insts, run, xs, flags=0, stream=None):
+    def __init__(self, insts, run, xs, flags=0, stream=None, static_workspace=False):
+        """static_workspace: take the device workspace from the library's
+        per-device static array (slpic_create_static) instead of allocating
+        one with torch; at most one such Sim per device at a time."""
         import torch
         if not torch.cuda.is_available():
             raise SlpicError(-5, "no HIP device")
@@ -199,16 +204,22 @@ class Sim:
         if nbytes == 0:
             raise SlpicError(-1, "invalid parameters for the workspace")
         self.nbytes = int(nbytes)
-        self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device="cuda")
         # a stream of its own (default priority): graph capture is refused on
         # the legacy default stream
         self.stream = stream if stream is not None else torch.cuda.Stream()
-        self.workspace.record_stream(self.stream)
         h = C.c_void_p()
-        rc = L.slpic_create(C.byref(self.cfg), self.inst, self.n_inst,
-                            C.byref(self.xs.c), C.c_void_p(self.workspace.data_ptr()),
-                            self.nbytes, C.c_void_p(self.stream.cuda_stream),
-                            C.byref(h))
+        if static_workspace:
+            self.workspace = None
+            rc = L.slpic_create_static(C.byref(self.cfg), self.inst, self.n_inst,
+                                       C.byref(self.xs.c), C.c_void_p(self.stream.cuda_stream),
+                                       C.byref(h))
+        else:
+            self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device="cuda")
+            self.workspace.record_stream(self.stream)
+            rc = L.slpic_create(C.byref(self.cfg), self.inst, self.n_inst,
+                                C.byref(self.xs.c), C.c_void_p(self.workspace.data_ptr()),
+                                self.nbytes, C.c_void_p(self.stream.cuda_stream),
+                                C.byref(h))
         _check(rc, None)
         self.h = h
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -31,6 +32,7 @@ inline size_t sort_lds_bytes(int n_inst, int max_cells, int arrays) {
 template <typename R> hipError_t launch_sort(const Ctx<R>&, hipStream_t);
 hipError_t launch_philox_test(const uint32_t*, uint32_t, uint32_t, int64_t, uint32_t*,
                               hipStream_t);
+hipError_t static_workspace(int dev, char** ptr);
 }  // namespace slpic
 
 using namespace slpic;
@@ -59,7 +61,7 @@ uint32_t prob_threshold(double P) {
 }
 
 struct Layout {
-  size_t ip, st, counts, tiles, cross, flux, ev, acc, E, E64, phi, rho, scratch, ring, inst_err, sort_hist, sort_cur,
+  size_t ip, st, counts, tiles, cross, flux, ev, acc, E, E64, phi, rho, ring, inst_err, sort_hist, sort_cur,
       glob, xs_e, xs_sig, xs_thr, xs_kind;
   size_t blk[2][2];      // [buffer][species] chunk arrays of the markers
   size_t total;
@@ -76,6 +78,8 @@ struct Layout {
 // partition's capacity.  Each partition gets an equal share of the capacity
 // plus one tile of slack.
 static_assert(MAX_PART == SLPIC_MAX_PARTITIONS, "partition cap of the public header");
+static_assert(STATIC_WS_BYTES == SLPIC_STATIC_WORKSPACE_BYTES,
+              "static workspace size of the public header");
 
 int partitions_for(int64_t cap) {
   int p = 1;
@@ -124,7 +128,6 @@ bool make_layout(const slpic_config* cfg, const slpic_instance* inst, int n_inst
   L.E64 = take(8 * 2 * (size_t)nodes);
   L.phi = take(8 * 2 * (size_t)nodes);
   L.rho = take(8 * 2 * (size_t)nodes);
-  L.scratch = take(8 * (size_t)nodes);
   L.ring = take(sizeof(StatsRow) * RING * (size_t)n_inst);
   L.inst_err = take(sizeof(uint32_t) * n_inst);
   L.sort_hist = take(sizeof(uint32_t) * 2 * (size_t)nodes);
@@ -278,6 +281,7 @@ struct slpic_handle {
   int n_inst = 0;
   Layout L;
   char* ws = nullptr;
+  int static_dev = -1;   // device whose static workspace this handle holds, or -1
   hipStream_t stream = nullptr;
   Ctx<float> c32;
   Ctx<double> c64;
@@ -336,7 +340,6 @@ void fill_ctx(slpic_t* h, Ctx<R>& C) {
   C.E64 = reinterpret_cast<double*>(w + L.E64);
   C.phi = reinterpret_cast<double*>(w + L.phi);
   C.rho = reinterpret_cast<double*>(w + L.rho);
-  C.scratch = reinterpret_cast<double*>(w + L.scratch);
   C.ring = reinterpret_cast<StatsRow*>(w + L.ring);
   C.inst_err = reinterpret_cast<uint32_t*>(w + L.inst_err);
   C.sort_hist = reinterpret_cast<uint32_t*>(w + L.sort_hist);
@@ -622,19 +625,17 @@ int read_impl(slpic_t* h, int inst, int sp, int64_t max_n, int64_t* n_out, int32
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-size_t slpic_workspace_bytes(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
-                             const slpic_xs* xs) {
-  if (!validate(cfg, inst, n_inst, xs).empty()) return 0;
-  Layout L;
-  if (!make_layout(cfg, inst, n_inst, xs, L)) return 0;
-  return L.total;
-}
+// Handles holding each device's static workspace (slpic_create_static):
+// at most one at a time per device.
+std::mutex g_static_mu;
+bool g_static_busy[MAX_DEVICES] = {};
 
-int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
-                 const slpic_xs* xs, void* dev_workspace, size_t ws_bytes, void* hip_stream,
-                 slpic_t** out) {
+// Create on a given device workspace (slpic_create, slpic_create_static).
+int create_impl(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
+                const slpic_xs* xs, void* dev_workspace, size_t ws_bytes, void* hip_stream,
+                slpic_t** out) {
   if (!out) return fail(nullptr, SLPIC_INVALID_ARG, "out is NULL");
   *out = nullptr;
   const std::string v = validate(cfg, inst, n_inst, xs);
@@ -753,6 +754,61 @@ int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst
   }
   *out = h;
   return SLPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t slpic_workspace_bytes(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
+                             const slpic_xs* xs) {
+  if (!validate(cfg, inst, n_inst, xs).empty()) return 0;
+  Layout L;
+  if (!make_layout(cfg, inst, n_inst, xs, L)) return 0;
+  return L.total;
+}
+
+int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
+                 const slpic_xs* xs, void* dev_workspace, size_t ws_bytes, void* hip_stream,
+                 slpic_t** out) {
+  return create_impl(cfg, inst, n_inst, xs, dev_workspace, ws_bytes, hip_stream, out);
+}
+
+int slpic_create_static(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
+                        const slpic_xs* xs, void* hip_stream, slpic_t** out) {
+  if (!out) return fail(nullptr, SLPIC_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  const std::string v = validate(cfg, inst, n_inst, xs);
+  if (!v.empty()) return fail(nullptr, SLPIC_INVALID_ARG, v);
+  Layout L;
+  if (!make_layout(cfg, inst, n_inst, xs, L)) return fail(nullptr, SLPIC_INVALID_ARG, "too many tiles");
+  if (L.total > SLPIC_STATIC_WORKSPACE_BYTES)
+    return fail(nullptr, SLPIC_WORKSPACE_TOO_SMALL,
+                "the setup needs " + std::to_string(L.total) +
+                    " workspace bytes, more than the static workspace's " +
+                    std::to_string((size_t)SLPIC_STATIC_WORKSPACE_BYTES));
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(nullptr, SLPIC_INVALID_ARG, "device index too large");
+  char* ws = nullptr;
+  e = static_workspace(dev, &ws);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "static workspace address");
+  {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_busy[dev])
+      return fail(nullptr, SLPIC_INVALID_ARG,
+                  "the static workspace of this device is held by another handle");
+    g_static_busy[dev] = true;
+  }
+  const int rc = create_impl(cfg, inst, n_inst, xs, ws, SLPIC_STATIC_WORKSPACE_BYTES, hip_stream, out);
+  if (rc == SLPIC_OK) {
+    (*out)->static_dev = dev;
+  } else {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static_busy[dev] = false;
+  }
+  return rc;
 }
 
 int slpic_use_graph(slpic_t* h, int enable) {
@@ -1068,6 +1124,10 @@ void slpic_destroy(slpic_t* h) {
   (void)hipStreamSynchronize(h->stream);
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
   release_events(h);
+  if (h->static_dev >= 0) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static_busy[h->static_dev] = false;
+  }
   delete h;
 }
 

@@ -20,9 +20,13 @@ constexpr int CSTRIDE = 64;       // uint32 slots between compaction counters:
                                   // reservations of one (instance, species)
                                   // spread over memory channels
 constexpr int NSLOT = 1;          // copies of each global deposit node
+constexpr int MAX_DEVICES = 64;   // devices a process can hold a static workspace on
 constexpr int HWIN = 960;         // nodes in a workgroup's LDS deposit window
                                   // (30 KB of LDS per workgroup in all: five
                                   // workgroups per CU)
+
+// bytes of the static workspace on each device (slpic_create_static)
+constexpr size_t STATIC_WS_BYTES = (size_t)64 << 20;
 
 // Tiles an (instance, species) takes in the tile space of a step: every
 // partition gets as many as the fullest one needs, so that tile j of the
@@ -139,7 +143,6 @@ struct Ctx {
   double* E64;               // [2][total_nodes]
   double* phi;               // [2][total_nodes]
   double* rho;               // [2][total_nodes]
-  double* scratch;           // [total_nodes]
   StatsRow* ring;            // [n_inst][RING]
   uint32_t* inst_err;        // [n_inst], sticky
   Global* g;

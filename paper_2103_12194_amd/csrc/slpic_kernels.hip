@@ -19,6 +19,8 @@
 // of tiles.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "slpic_internal.hpp"
 
 namespace slpic {
@@ -1849,6 +1851,36 @@ hipError_t launch_philox_test(const uint32_t* ctr, uint32_t k0, uint32_t k1, int
   hipLaunchKernelGGL(k_philox_test, dim3((unsigned)blocks), dim3(BLOCK), 0, s, ctr, k0, k1, n,
                      out);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- static workspace
+// Workspace of the handles made by slpic_create_static, for callers that
+// cannot allocate device memory: a file-scope device array, which the code
+// object holds on every device it is loaded on until the process ends.  Host
+// code never passes the array's name to a launch or a copy (on the host it
+// is only a stand-in for the symbol): each device's address of it comes from
+// hipGetSymbolAddress, looked up once per device with that device current and
+// kept here.
+static __device__ __align__(256) char scratch[STATIC_WS_BYTES];
+
+hipError_t static_workspace(int dev, char** ptr) {
+  static std::mutex mu;
+  static char* addr[MAX_DEVICES] = {};
+  if (dev < 0 || dev >= MAX_DEVICES || !ptr) return hipErrorInvalidValue;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev) return hipErrorInvalidDevice;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p || ((uintptr_t)p & 255)) return hipErrorInvalidSymbol;
+    addr[dev] = static_cast<char*>(p);
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 }  // namespace slpic
