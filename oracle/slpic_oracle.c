@@ -303,8 +303,11 @@ double or_see_yield(double eps) {
 /* Turn unit vector vh by polar angle chi and azimuth phi.  The azimuth is
  * measured in the frame e1 = normalize(vh x a), e2 = vh x e1, where a is the
  * coordinate axis along which |vh| has its smallest component (ties go to the
- * lower index).  Returns the gap between the two smallest |components|, the
- * margin of that choice. */
+ * lower index).  Returns the margin of that choice: the gap between the two
+ * smallest |components|, which rounding in another precision could close;
+ * but infinity when both are exactly zero (a velocity along one axis, as an
+ * electron released at rest has in the 1D field), a tie that resolves to
+ * the same axis in any precision. */
 static double rotate(const double vh[3], double cosx, double phi, double out[3]) {
   double a0 = fabs(vh[0]), a1 = fabs(vh[1]), a2 = fabs(vh[2]);
   int ax = 0;
@@ -327,7 +330,7 @@ static double rotate(const double vh[3], double cosx, double phi, double out[3])
   double sinx = sqrt(fmax(0.0, 1.0 - cosx * cosx));
   double cp = cos(phi), sp = sin(phi);
   for (int k = 0; k < 3; ++k) out[k] = cosx * vh[k] + sinx * (cp * e1[k] + sp * e2[k]);
-  return second - amin;
+  return (amin == 0.0 && second == 0.0) ? INFINITY : second - amin;
 }
 
 static void unit_of(const double v[3], double vh[3]) {
@@ -375,42 +378,47 @@ static void note_margin(or_sim* s, marker* m, double margin) {
 /* Field: charge deposit with linear weights, density weight w_p = beta w_j
  * (Sec. III), and the Dirichlet Poisson problem phi(0) = 0, phi(d) = V. */
 void or_poisson(int N, double dx, double V, const double* rho, double* phi, double* E) {
-  /* By linearity phi = V i/N + psi, where psi solves the same difference
-   * equation with psi[0] = psi[N] = 0 and the space charge as its source:
-   *   -psi[i-1] + 2 psi[i] - psi[i+1] = rho[i] dx^2 / eps0,  i = 1..N-1,
-   * solved by the Thomas algorithm.  Differencing only psi keeps the
-   * vacuum field -V/d exact instead of recovering it from differences of
-   * a potential of size V. */
-  int m = N - 1;
-  double* psi = (double*)calloc((size_t)N + 1, sizeof(double));
-  double* cp = (double*)malloc(sizeof(double) * (m > 0 ? m : 1));
-  double* dp = (double*)malloc(sizeof(double) * (m > 0 ? m : 1));
-  for (int k = 0; k < m; ++k) {
-    double b = rho[k + 1] * dx * dx / EPS0;
-    double diag = 2.0, off = -1.0;
-    if (k == 0) {
-      cp[k] = off / diag;
-      dp[k] = b / diag;
-    } else {
-      double den = diag - off * cp[k - 1];
-      cp[k] = off / den;
-      dp[k] = (b - off * dp[k - 1]) / den;
-    }
+  /* Discrete Green's function of the Dirichlet problem.  By linearity
+   * phi_i = V i/N + psi_i, where psi solves the same difference equation
+   * with psi_0 = psi_N = 0 and the space charge as its source,
+   *   -psi_{i-1} + 2 psi_i - psi_{i+1} = rho_i dx^2 / eps0,  i = 1..N-1,
+   * whose solution is psi_i = (dx^2/eps0) sum_j G_ij rho_j with
+   * G_ij = min(i,j) (N - max(i,j)) / N.  Differencing G over i gives the
+   * field between nodes directly from sums of rho:
+   *   E_{i+1/2} = -(phi_{i+1} - phi_i)/dx
+   *             = -V/(N dx) - (dx/eps0) (R_i - M/N),
+   *   R_i = sum_{j=i+1}^{N-1} rho_j,   M = sum_{j=1}^{N-1} j rho_j,
+   * so E is not taken from differences of psi (which would cost digits on
+   * long grids) and the vacuum field -V/d stays exact. */
+  const double k = dx / EPS0;
+  double M = 0.0;
+  for (int j = 1; j < N; ++j) M += (double)j * rho[j];
+  double* Eh = (double*)malloc(sizeof(double) * (size_t)N);  /* E_{i+1/2}, i = 0..N-1 */
+  const double Ev = -V / ((double)N * dx);
+  double R = 0.0;  /* R_i, built from the top */
+  for (int i = N - 1; i >= 0; --i) {
+    if (i + 1 <= N - 1) R += rho[i + 1];
+    Eh[i] = Ev - k * (R - M / (double)N);
   }
-  if (m > 0) psi[m] = dp[m - 1];
-  for (int k = m - 2; k >= 0; --k) psi[k + 1] = dp[k] - cp[k] * psi[k + 2];
-  free(cp);
-  free(dp);
-  for (int i = 0; i <= N; ++i) phi[i] = V * (double)i / (double)N + psi[i];
-  phi[0] = 0.0;
-  phi[N] = V;
-  /* E = -dphi/dx: central differences inside, Gauss's law over the half
+  /* node fields: the central difference inside, Gauss's law over the half
    * cell at each electrode */
-  double Ev = -V / ((double)N * dx);
-  for (int i = 1; i < N; ++i) E[i] = Ev + (psi[i - 1] - psi[i + 1]) / (2.0 * dx);
-  E[0] = Ev + (psi[0] - psi[1]) / dx - rho[0] * dx / (2.0 * EPS0);
-  E[N] = Ev + (psi[N - 1] - psi[N]) / dx + rho[N] * dx / (2.0 * EPS0);
-  free(psi);
+  for (int i = 1; i < N; ++i) E[i] = 0.5 * (Eh[i - 1] + Eh[i]);
+  E[0] = Eh[0] - rho[0] * dx / (2.0 * EPS0);
+  E[N] = Eh[N - 1] + rho[N] * dx / (2.0 * EPS0);
+  free(Eh);
+  /* potential: psi_i = (dx^2/eps0) [ (N-i)/N A_i + i/N B_i ] with
+   * A_i = sum_{j=1}^{i} j rho_j and B_i = sum_{j=i+1}^{N-1} (N-j) rho_j */
+  double B = 0.0;
+  for (int j = 1; j < N; ++j) B += (double)(N - j) * rho[j];
+  double A = 0.0;
+  phi[0] = 0.0;
+  for (int i = 1; i < N; ++i) {
+    A += (double)i * rho[i];
+    B -= (double)(N - i) * rho[i];
+    const double psi = dx * k * (((double)(N - i) / N) * A + ((double)i / N) * B);
+    phi[i] = V * (double)i / (double)N + psi;
+  }
+  phi[N] = V;
 }
 
 static void locate(const or_sim* s, double x, int* ci, double* f) {

@@ -95,3 +95,48 @@ def test_deposit_linear_weights_single_marker():
     want[3] = -QE * wp * 0.75 / (2.0 * dx)
     want[4] = -QE * wp * 0.25 / (2.0 * dx)
     np.testing.assert_allclose(rho, want, rtol=1e-14)
+
+
+def _long_double_field(N, dx, V, rho):
+    """E of the same discrete problem solved in extended precision (x87 long
+    double, 64-bit mantissa) by elimination on the tridiagonal system."""
+    ld = np.longdouble
+    eps0 = ld(8.8541878128e-12)
+    r = np.asarray(rho, dtype=ld)
+    dx, V = ld(dx), ld(V)
+    b = r * dx * dx / eps0
+    m = N - 1
+    cp = np.zeros(m, dtype=ld)
+    dp = np.zeros(m, dtype=ld)
+    for k in range(m):
+        den = ld(2) if k == 0 else ld(2) + cp[k - 1]
+        cp[k] = ld(-1) / den
+        dp[k] = (b[k + 1] + (dp[k - 1] if k else ld(0))) / den
+    psi = np.zeros(N + 1, dtype=ld)
+    psi[m] = dp[m - 1]
+    for k in range(m - 2, -1, -1):
+        psi[k + 1] = dp[k] - cp[k] * psi[k + 2]
+    Ev = -V / (ld(N) * dx)
+    E = np.empty(N + 1, dtype=ld)
+    E[1:N] = Ev + (psi[0:N - 1] - psi[2:N + 1]) / (2 * dx)
+    E[0] = Ev + (psi[0] - psi[1]) / dx - r[0] * dx / (2 * eps0)
+    E[N] = Ev + (psi[N - 1] - psi[N]) / dx + r[N] * dx / (2 * eps0)
+    return E
+
+
+@pytest.mark.parametrize("N", [1024, 8192])
+def test_field_is_accurate_to_rounding_on_long_grids(N):
+    # the marker pushes see E, so on long grids it must keep FP64 accuracy:
+    # within a few 1e-16 of the extended-precision solution of the same
+    # problem, for a space charge that moves the field by a tenth of V/d
+    assert np.finfo(np.longdouble).eps < 1e-18
+    rng = np.random.default_rng(N)
+    d, V = 0.01, 500.0
+    dx = d / N
+    rho = rng.normal(0.0, 1.0, N + 1) + 0.3 * np.sin(np.linspace(0, 7, N + 1))
+    rho *= 0.1 * (V / d) * 8.8541878128e-12 / d / np.abs(rho).mean()
+    _, E = oracle.poisson(N, dx, V, rho)
+    ref = _long_double_field(N, dx, V, rho)
+    err = float(np.abs(E - ref).max() / np.abs(ref).max())
+    print(N, "relative error of E", err)
+    assert err < 1e-15
