@@ -12,10 +12,15 @@ the first cell, kT_e = 1 eV) and are resident in HBM before timing starts.
 
 Prints one JSON line:
   value       particle-steps/s = sum over timed steps and instances of the
-              markers entering the step, over the wall time of the steps
+              markers entering the step, over the wall time of the steps,
+              replayed from the captured HIP graph (16 steps per graph;
+              captured before the timed region)
   roofline    particle kernel: 56 algorithmic bytes per marker-step (28-byte
               record read + 28-byte record written) over its average
-              HIP-event duration, against 8 TB/s
+              HIP-event duration, against 8 TB/s, from the same number of
+              steps launched one by one right after the timed ones; traffic
+              is the committed counter summary's HBM bytes per marker-step
+              times the markers of one of these launches
   plain       the same instances stepped one handle at a time (n_inst = 1)
   cpu_baseline the FP64 oracle on a bounded sample of the same instances
 
@@ -25,7 +30,7 @@ Prints one JSON line:
               sort every 16 steps) and the 256-instance bisection round
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-plain]
-       [--no-cpu] [--graph] [--scale S] [--pic] [--all-configs]
+       [--no-cpu] [--scale S] [--pic] [--all-configs]
        python bench.py --copy-calibration   (plain device copy of 1 GiB,
        for scaling HBM counters)
 """
@@ -79,8 +84,6 @@ def parse():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--scale", type=float, default=1.0,
                     help="marker-count scale of the sweep (1 = full size)")
-    ap.add_argument("--graph", action="store_true",
-                    help="also time graph replay of the same steps")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -155,6 +158,24 @@ def plain_leg(w, xs, steps, warmup):
         sim.close()
         del sim
     return ps, secs
+
+
+def host_cpu():
+    """Logical CPUs the process may use and the CPU model of the host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"logical_cpus": os.cpu_count(), "usable_cpus": usable, "model": model}
 
 
 def cpu_leg(w, xs, budget_s):
@@ -285,26 +306,32 @@ def main():
     sim.step(args.warmup)
     sim.sync()
     print(f"# warmup {args.warmup} steps done", file=sys.stderr, flush=True)
-    s0, secs, (gen_ms, tail_ms, nk) = time_steps(sim, args.steps, profile=True)
+    # the timed steps: graph replay (captured here, outside the timed region)
+    sim.use_graph(True)
+    s0, secs, _ = time_steps(sim, args.steps, profile=False)
     ps = history_total(sim, s0, args.steps)
     value = ps / secs
-    print(f"# timed {args.steps} steps: {secs * 1e3 / args.steps:.3f} ms/step, "
+    sim.use_graph(False)
+    # kernel durations: the same number of steps launched one by one with
+    # HIP events around each kernel on the handle's stream
+    e0, esecs, (gen_ms, tail_ms, nk) = time_steps(sim, args.steps, profile=True)
+    eps_ = history_total(sim, e0, args.steps)
+    print(f"# timed {args.steps} steps (graph): {secs * 1e3 / args.steps:.3f} ms/step; "
+          f"then {args.steps} eager steps: {esecs * 1e3 / args.steps:.3f} ms/step, "
           f"particle kernel {gen_ms / nk:.3f} ms, tail {tail_ms / nk:.3f} ms",
           file=sys.stderr, flush=True)
-    graph = None
-    if args.graph:
-        sim.use_graph(True)
-        sg, gsecs, _ = time_steps(sim, args.steps, profile=False)
-        graph = {"value": history_total(sim, sg, args.steps) / gsecs,
-                 "ms_per_step": gsecs * 1e3 / args.steps}
+    eager = {"value": eps_ / esecs, "ms_per_step": esecs * 1e3 / args.steps}
 
-    per_launch = BYTES_PER_MARKER_STEP * ps / nk
+    per_launch = BYTES_PER_MARKER_STEP * eps_ / nk
     achieved = per_launch / (gen_ms / nk * 1e-3) / 1e9
     tr = measured_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if tr is None else tr[0],
+                "traffic": None if tr is None else tr[1] * eps_ / nk,
+                "traffic_per_marker_step": None if tr is None else tr[1],
+                "traffic_source": "profiles/k_gen_c4_traffic.txt (rocprofv3 FETCH_SIZE + "
+                                  "WRITE_SIZE per marker-step, scaled to this launch)",
                 "kernel": "k_gen (particle kernel)",
                 "bytes_per_launch": per_launch,
                 "kernel_ms": gen_ms / nk, "tail_kernel_ms": tail_ms / nk}
@@ -327,6 +354,7 @@ def main():
     if not args.no_cpu:
         rate, desc, threads = cpu_leg(w, xs, args.cpu_seconds)
         cpu = {"value": rate, "unit": "particle-steps/s", "cores": threads,
+               "threads": threads, "host": host_cpu(),
                "kind": "oracle", "sample": desc}
 
     line = {
@@ -342,7 +370,7 @@ def main():
                                "FP64 Poisson and totals; one launch pair per step",
                    "n_inst": len(w.instances), "marker_scale": args.scale,
                    "markers_per_step": n_markers, "parallelism": "none (1 GPU)"},
-        "roofline": roofline, "plain": plain, "graph": graph,
+        "roofline": roofline, "plain": plain, "eager": eager,
         "cpu_baseline": cpu,
     }
     if pic is not None:

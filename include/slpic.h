@@ -202,8 +202,10 @@ int slpic_sort(slpic_t* h);
  * SLPIC_NU_BOUND_EXCEEDED) or SLPIC_OK. */
 int slpic_sync(slpic_t* h);
 
-/* Use a captured HIP graph of period_steps steps for slpic_step (1) or plain
- * launches (0).  Default 0. */
+/* Use a captured HIP graph of 16 steps for slpic_step (1) or plain launches
+ * (0).  Default 0.  Enabling captures the graph at once (capture runs
+ * nothing), unless kernel timing is on; slpic_step replays it for every
+ * whole period of its steps and launches the rest one by one. */
 int slpic_use_graph(slpic_t* h, int enable);
 
 /* Launch shape.  The particle kernel runs on a grid of workgroups that each

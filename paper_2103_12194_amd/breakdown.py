@@ -147,3 +147,55 @@ def instance_rates(sim, instances, steps, pops, window=(15.0, 30.0)):
         dt = sim.scalars(k)["dt"]
         out.append(growth_rate(steps * dt, pops[k], crossing_time(inst.d, inst.V), window))
     return np.array(out)
+
+
+def paired_difference(rates_a, rates_b):
+    """Mean and standard error of the replica-by-replica differences a - b of
+    two ensembles run with the same replica seeds (paired samples: the
+    correlation between a_k and b_k cancels in the difference).  Replicas
+    that died out on both sides are left out; one that died out on one side
+    only makes the difference -inf or +inf."""
+    a = np.asarray(rates_a, dtype=np.float64)
+    b = np.asarray(rates_b, dtype=np.float64)
+    if a.shape != b.shape or a.size == 0:
+        raise ValueError("paired ensembles must have the same, nonzero size")
+    both = np.isneginf(a) & np.isneginf(b)
+    a, b = a[~both], b[~both]
+    if np.any(~np.isfinite(a)) or np.any(~np.isfinite(b)):
+        return (-math.inf if np.any(np.isneginf(a)) else math.inf), 0.0
+    d = a - b
+    if d.size < 2:
+        return float(d.mean()) if d.size else 0.0, math.inf
+    return float(d.mean()), float(d.std(ddof=1) / math.sqrt(d.size))
+
+
+def paired_breakdown_difference(V, rates_a, rates_b, n_boot=2000, seed=1):
+    """Difference of the breakdown voltages (zero_crossing of the ensemble
+    means) of two paired ensembles, with its standard error from a paired
+    bootstrap: replicas are resampled with the same indices on both sides.
+
+    V: voltages [n_v]; rates_a, rates_b: growth rates [n_v, R] with replica k
+    of every voltage run from the same seeds on both sides.  Returns
+    (Vb_a - Vb_b, se) or None if either side has no zero crossing."""
+    ra = np.asarray(rates_a, dtype=np.float64)
+    rb = np.asarray(rates_b, dtype=np.float64)
+    if ra.shape != rb.shape or ra.ndim != 2 or ra.shape[0] != len(V):
+        raise ValueError("rates must be [n_voltages, replicas] on both sides")
+
+    def vb(r):
+        z = zero_crossing(V, r.mean(axis=1), np.zeros(len(V)))
+        return None if z is None else z[0]
+    va, vb0 = vb(ra), vb(rb)
+    if va is None or vb0 is None:
+        return None
+    rng = np.random.default_rng(seed)
+    R = ra.shape[1]
+    diffs = []
+    for _ in range(n_boot):
+        k = rng.integers(0, R, size=R)
+        a, b = vb(ra[:, k]), vb(rb[:, k])
+        if a is not None and b is not None:
+            diffs.append(a - b)
+    if len(diffs) < n_boot // 2:
+        return None
+    return va - vb0, float(np.std(diffs, ddof=1))

@@ -811,9 +811,31 @@ int slpic_create_static(const slpic_config* cfg, const slpic_instance* inst, int
   return rc;
 }
 
+// Captures graph_period steps (with the cell sorts due in them) as a HIP
+// graph; nothing runs until the graph is launched.
+static int capture_graph(slpic_t* h) {
+  hipGraph_t gr;
+  HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < h->graph_period; ++k) {
+    hipError_t e = sort_due(h, h->steps + k) ? launch_sort_any(h) : hipSuccess;
+    if (e == hipSuccess) e = launch_pair_any(h, MODE_STEP);
+    if (e != hipSuccess) {
+      (void)hipStreamEndCapture(h->stream, &gr);
+      return hip_fail(h, e, "graph capture");
+    }
+  }
+  HIPCHK(h, hipStreamEndCapture(h->stream, &gr));
+  HIPCHK(h, hipGraphInstantiate(&h->graph, gr, nullptr, nullptr, 0));
+  (void)hipGraphDestroy(gr);
+  h->graph_phase = sort_phase(h);
+  return SLPIC_OK;
+}
+
 int slpic_use_graph(slpic_t* h, int enable) {
   if (!h) return SLPIC_INVALID_ARG;
   h->use_graph = enable != 0;
+  // capture now, so that the first replayed steps do not pay for it
+  if (h->use_graph && !h->graph && !h->profiling) return capture_graph(h);
   return SLPIC_OK;
 }
 
@@ -827,20 +849,8 @@ int slpic_step(slpic_t* h, int n_steps) {
                        (!h->graph || h->graph_phase == sort_phase(h));
     if (graph) {
       if (!h->graph) {
-        hipGraph_t gr;
-        HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < h->graph_period; ++k) {
-          hipError_t e = sort_due(h, h->steps + k) ? launch_sort_any(h) : hipSuccess;
-          if (e == hipSuccess) e = launch_pair_any(h, MODE_STEP);
-          if (e != hipSuccess) {
-            (void)hipStreamEndCapture(h->stream, &gr);
-            return hip_fail(h, e, "graph capture");
-          }
-        }
-        HIPCHK(h, hipStreamEndCapture(h->stream, &gr));
-        HIPCHK(h, hipGraphInstantiate(&h->graph, gr, nullptr, nullptr, 0));
-        (void)hipGraphDestroy(gr);
-        h->graph_phase = sort_phase(h);
+        const int rc = capture_graph(h);
+        if (rc) return rc;
       }
       HIPCHK(h, hipGraphLaunch(h->graph, h->stream));
       h->gen += h->graph_period;

@@ -84,9 +84,10 @@ template <> struct Fm<float> {
       return x * (1.0f - x * (0.5f - x * (0.33333334f - x * (0.25f - x * 0.2f))));
     return log(1.0f + x);
   }
-  // exp(y) - 1 for y >= 0: series below 2^-5, else exp(y) - 1 (2e-6 at most)
+  // exp(y) - 1: series for |y| below 2^-5, else exp(y) - 1 (the result is
+  // then at least 0.03 in magnitude: 2e-6 relative at most)
   static __device__ __forceinline__ float expm1(float y) {
-    if (y < 0.03125f)
+    if (__builtin_fabsf(y) < 0.03125f)
       return y * (1.0f + y * 0.5f * (1.0f + y * 0.33333334f * (1.0f + y * 0.25f * (1.0f + y * 0.2f))));
     return __builtin_amdgcn_exp2f(y * 1.44269504f) - 1.0f;
   }
@@ -334,19 +335,37 @@ __device__ __forceinline__ float beta_fast(float v2, float v0, int limited) {
 }
 
 // ---------------------------------------------------------------- collisions
+// A scattering angle as 1 - cos chi and 1 + cos chi, each formed without
+// cancellation, so that sin chi = sqrt((1 - cos chi)(1 + cos chi)) keeps its
+// relative accuracy at forward and backward angles alike.
 template <typename R>
-__device__ __forceinline__ R vs_cos(R eps, R u) {
-  // Vahedi-Surendra: cos chi = (2 + eps - 2 (1 + eps)^u) / eps
-  //                          = 1 - 2 expm1(u log1p(eps)) / eps
-  if (!(eps > R(0))) return R(1) - R(2) * u;
-  return R(1) - Fm<R>::div(R(2) * Fm<R>::expm1(u * Fm<R>::log1p(eps)), eps);
+struct Chi {
+  R omc, opc;
+};
+
+// Vahedi-Surendra angle law, cos chi = (2 + eps - 2 (1 + eps)^u) / eps:
+//   1 - cos chi = 2 expm1(u L) / eps,
+//   1 + cos chi = -2 (1 + eps) expm1(-(1 - u) L) / eps,   L = log1p(eps);
+// eps -> 0 gives the isotropic law.  1 - u is exact for the uniforms used.
+template <typename R>
+__device__ __forceinline__ Chi<R> vs_angle(R eps, R u) {
+  if (!(eps > R(0))) return Chi<R>{R(2) * u, R(2) * (R(1) - u)};
+  const R L = Fm<R>::log1p(eps);
+  const R k = Fm<R>::div(R(2), eps);
+  return Chi<R>{k * Fm<R>::expm1(u * L), -(k + R(2)) * Fm<R>::expm1(-(R(1) - u) * L)};
 }
 
-// Turn unit vector (hx, hy, hz) by chi (cos given) and azimuth 2 pi u; the
+// isotropic scattering: cos chi = 1 - 2u
+template <typename R>
+__device__ __forceinline__ Chi<R> iso_angle(R u) {
+  return Chi<R>{R(2) * u, R(2) * (R(1) - u)};
+}
+
+// Turn unit vector (hx, hy, hz) by the angle chi and azimuth 2 pi u; the
 // azimuth is measured from e1 = normalize(h x a), a the axis of the smallest
 // |component| of h (ties to the lower index), e2 = h x e1.
 template <typename R>
-__device__ __forceinline__ void turn(R hx, R hy, R hz, R cosx, R u, R& ox, R& oy, R& oz) {
+__device__ __forceinline__ void turn(R hx, R hy, R hz, Chi<R> chi, R u, R& ox, R& oy, R& oz) {
   const R ax = hx < R(0) ? -hx : hx, ay = hy < R(0) ? -hy : hy, az = hz < R(0) ? -hz : hz;
   R e1x, e1y, e1z;
   if (ay < ax && ay <= az) { e1x = -hz; e1y = R(0); e1z = hx; }       // axis y
@@ -355,7 +374,8 @@ __device__ __forceinline__ void turn(R hx, R hy, R hz, R cosx, R u, R& ox, R& oy
   const R n = Fm<R>::sqrt(e1x * e1x + e1y * e1y + e1z * e1z);
   e1x = Fm<R>::div(e1x, n); e1y = Fm<R>::div(e1y, n); e1z = Fm<R>::div(e1z, n);
   const R e2x = hy * e1z - hz * e1y, e2y = hz * e1x - hx * e1z, e2z = hx * e1y - hy * e1x;
-  R sn = R(1) - cosx * cosx;
+  const R cosx = chi.omc <= R(1) ? R(1) - chi.omc : chi.opc - R(1);
+  R sn = chi.omc * chi.opc;
   sn = sn > R(0) ? Fm<R>::sqrt(sn) : R(0);
   R sp, cp;
   Fm<R>::sincos2pi(u, &sp, &cp);
@@ -1231,12 +1251,12 @@ __device__ void collide_electron(const Ctx<R>& C, IP& P, int inst, uint32_t step
     // the primary leaves by one rotation whatever the channel: the
     // Vahedi-Surendra angle at its energy for elastic scattering and
     // ionization, isotropic for excitation
-    const R cx = kind == 1 ? R(1) - R(2) * unif<R>(r.z) : vs_cos(kind == 0 ? eps : esc, unif<R>(r.z));
+    const Chi<R> chi = kind == 1 ? iso_angle(unif<R>(r.z)) : vs_angle(kind == 0 ? eps : esc, unif<R>(r.z));
     R e1;
-    if (kind == 0) e1 = eps * (R(1) - R(2.0 * ME / MAR) * (R(1) - cx));
+    if (kind == 0) e1 = eps * (R(1) - R(2.0 * ME / MAR) * chi.omc);
     else if (kind == 1) e1 = eps - thr > R(0) ? eps - thr : R(0);
     else e1 = esc;
-    turn(hx, hy, hz, cx, unif<R>(r.w), ox, oy, oz);
+    turn(hx, hy, hz, chi, unif<R>(r.w), ox, oy, oz);
     const R sp1 = Fm<R>::sqrt(e1 * (R)(2.0 * QE / ME));
     m.vx = sp1 * ox; m.vy = sp1 * oy; m.vz = sp1 * oz;
     ev |= 1u << (kind == 0 ? EV_ELASTIC : (kind == 1 ? EV_EXCIT : EV_IONIZ));
@@ -1245,7 +1265,7 @@ __device__ void collide_electron(const Ctx<R>& C, IP& P, int inst, uint32_t step
       const U4 b = draw_cold(m.id, step, CH_IONBIRTH, C.seed, P.key);
       const U4 cid = draw_cold(m.id, step, CH_CHILD, C.seed, P.key);
       R jx, jy, jz;
-      turn(hx, hy, hz, vs_cos(eej, unif<R>(q.y)), unif<R>(q.z), jx, jy, jz);
+      turn(hx, hy, hz, vs_angle(eej, unif<R>(q.y)), unif<R>(q.z), jx, jy, jz);
       const R spj = Fm<R>::sqrt(eej * (R)(2.0 * QE / ME));
       Mk<R> e2 = m;
       e2.vx = spj * jx; e2.vy = spj * jy; e2.vz = spj * jz;

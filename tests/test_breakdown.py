@@ -102,3 +102,38 @@ def test_bracket_and_bisection_round():
         vs = bd.bisection_voltages(lo, hi, 8)
         lo, hi = bd.bracket(vs, [x > Vb for x in vs])
     assert lo < Vb < hi and hi - lo == pytest.approx(900.0 / 7 ** 6)
+
+
+def test_paired_difference_cancels_shared_noise():
+    # two ensembles that share replica noise: the paired standard error
+    # sees only the part that differs
+    rng = np.random.default_rng(3)
+    common = rng.normal(0.0, 1.0, 400)
+    a = common + 0.01 + rng.normal(0.0, 0.001, 400)
+    b = common
+    d, se = bd.paired_difference(a, b)
+    assert d == pytest.approx(0.01, abs=4 * 0.001 / 20)
+    assert se == pytest.approx(0.001 / 20, rel=0.2)
+    # replicas extinct on both sides drop out; on one side only, +-inf
+    a2 = np.append(a, -math.inf)
+    b2 = np.append(b, -math.inf)
+    assert bd.paired_difference(a2, b2)[0] == pytest.approx(d)
+    assert bd.paired_difference(np.append(a, -math.inf), np.append(b, 0.0))[0] == -math.inf
+
+
+def test_paired_breakdown_difference_on_linear_rates():
+    # lambda(V) = (V - 600) / 200 + replica noise shared by both sides, and
+    # side a shifted by 0.01 (so V_b moves down by 2 V)
+    rng = np.random.default_rng(4)
+    V = [500.0, 700.0]
+    noise = rng.normal(0.0, 0.05, (2, 50))
+    b = np.array([[(v - 600.0) / 200.0] * 50 for v in V]) + noise
+    a = b + 0.01
+    d, se = bd.paired_breakdown_difference(V, a, b)
+    vb_b = bd.zero_crossing(V, b.mean(1), [0, 0])[0]
+    vb_a = bd.zero_crossing(V, a.mean(1), [0, 0])[0]
+    assert d == pytest.approx(vb_a - vb_b) and d == pytest.approx(-2.0, abs=0.01)
+    # the shared noise cancels: the paired error is far below either
+    # ensemble's own (propagated from the replica spread)
+    own = bd.zero_crossing(V, b.mean(1), b.std(1, ddof=1) / math.sqrt(50))[1]
+    assert own > 1.0 and se < own / 20

@@ -1,0 +1,98 @@
+"""FP64 parity with the oracle at the grid sizes and partition counts the
+batched sweeps run: gaps of 1024 to 8192 cells in one batch, markers spread
+over each whole gap, with space charge strong enough that the deposit and
+the Poisson solve shape the field (Eq. (7) deposit with density weight
+w_p = beta w_j, Sec. III).
+
+This exercises the paths small gaps never reach: deposits outside a
+workgroup's 960-node LDS window, the window re-anchored per instance, the
+tail kernel's scans with several nodes per thread (N + 1 > 1024) and its
+second accumulator round (N + 1 > 5120), 8 and 16 output partitions per
+(instance, species), population control at that size, and (with
+resort_period 4) the cell sort, each against an independent oracle run per
+instance.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import configs
+from parity import compare_populations, STAT_INT
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a HIP device", allow_module_level=True)
+
+import paper_2103_12194_amd as slpic  # noqa: E402
+
+# cells, p [Torr] (a quarter mean free path per cell), V (Eq. (1) estimate
+# at that pd), electrons, ions, population target, capacity per species
+SPEC = [(1024, 4.7, 280.0, 20000, 8000, 0, 140000),
+        (2048, 9.4, 450.0, 24000, 9000, 12000, 90000),
+        (4096, 18.7, 750.0, 20000, 8000, 0, 300000),
+        (8192, 37.4, 1300.0, 16000, 6000, 0, 70000)]
+STEPS = 10
+
+
+def _setup():
+    insts, pops = [], []
+    for k, (cells, p, V, ne, ni, nt, cap) in enumerate(SPEC):
+        insts.append(configs.Instance(d=0.01, p_torr=p, V=V, cells=cells, gamma_se=0.2,
+                                      seed_mode=configs.SEED_NONE, n_target=nt,
+                                      capacity=cap))
+        pops.append(synth.markers.mixed(100 + k, ne, ni, cells, e_hi=100.0))
+    return insts, pops
+
+
+@pytest.mark.parametrize("resort_period", [0, 4])
+def test_large_gaps_match_independent_oracles_step_by_step(resort_period, xs_argon):
+    insts, pops = _setup()
+    # a flux weight at which the markers' space charge moves the field by
+    # 0.1-3 % of V/d: about 1e8 times the field tolerance below
+    run = configs.Run(precision=64, w_j0=2e7, resort_period=resort_period)
+    print(f"full-size parity, resort_period={resort_period}", flush=True)
+    gpu = slpic.Sim(insts, run, xs_argon)
+    refs = [oracle.Sim(x, run, xs_argon, instance_index=k) for k, x in enumerate(insts)]
+    for k, (e, i) in enumerate(pops):
+        for sim, kw in ((gpu, {"inst": k}), (refs[k], {})):
+            sim.load(0, e, **kw)
+            sim.load(1, i, **kw)
+    parts = [gpu.partitions(0, k)[0].size for k in range(len(insts))]
+    assert parts == [16, 8, 16, 8], parts
+    for k, x in enumerate(insts):
+        E_g, E_o = gpu.fields(inst=k)[2], refs[k].fields()[2]
+        vac = x.V / x.d
+        # the space charge is felt, and the loaded field agrees
+        assert np.abs(E_o + vac).max() > 1e-3 * vac, k
+        assert np.allclose(E_g, E_o, rtol=0, atol=1e-11 * np.abs(E_o).max()), k
+    roulette = 0
+    for n in range(STEPS):
+        gpu.step(1)
+        for r in refs:
+            r.step(1)
+        for k in range(len(insts)):
+            sg, so = gpu.stats(inst=k), refs[k].stats()
+            for key in STAT_INT:
+                assert sg[key] == so[key], (n, k, key, sg[key], so[key])
+            assert sg["w_j"] == so["w_j"]
+            assert sg["w_e"] == pytest.approx(so["w_e"], rel=1e-9)
+            assert sg["w_i"] == pytest.approx(so["w_i"], rel=1e-9)
+            roulette += so["roulette"]
+        if n in (0, STEPS - 1):
+            for k in range(len(insts)):
+                rho_g, _, E_g = gpu.fields(inst=k)
+                rho_o, _, E_o = refs[k].fields()
+                assert np.allclose(rho_g, rho_o, rtol=0, atol=1e-11 * np.abs(rho_o).max()), (n, k)
+                assert np.allclose(E_g, E_o, rtol=0, atol=1e-11 * np.abs(E_o).max()), (n, k)
+    assert gpu.sync() == 0
+    assert roulette > 0
+    for k, x in enumerate(insts):
+        v0 = gpu.scalars(k)["v0"]
+        for sp in (0, 1):
+            w = compare_populations(gpu.read(sp, k), refs[k].read(sp), 1e-12 * x.cells,
+                                    1e-12, v0, label=f"inst {k} sp {sp}")
+            print("full size", resort_period, k, sp, w)
