@@ -56,6 +56,7 @@ class _Params(C.Structure):
         ("threshold_eV", C.POINTER(C.c_double)),
         ("kind", C.POINTER(C.c_int32)),
         ("fixed_prob", C.POINTER(C.c_double)),
+        ("split_frac", C.c_double),
     ]
 
 
@@ -78,6 +79,7 @@ def lib():
         L.or_count.restype = C.c_int64
         L.or_count.argtypes = [vp, C.c_int]
         L.or_read.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp]
+        L.or_read_weights.argtypes = [vp, C.c_int, vp]
         L.or_fields.argtypes = [vp, vp, vp, vp]
         L.or_last_stats.argtypes = [vp, vp]
         L.or_flux.argtypes = [vp, C.c_int, vp]
@@ -206,7 +208,8 @@ class Sim:
             energies=e.ctypes.data_as(dp), sigma=sg.ctypes.data_as(dp),
             threshold_eV=th.ctypes.data_as(dp),
             kind=kd.ctypes.data_as(C.POINTER(C.c_int32)),
-            fixed_prob=fp.ctypes.data_as(dp) if fp is not None else None)
+            fixed_prob=fp.ctypes.data_as(dp) if fp is not None else None,
+            split_frac=float(getattr(run, "split_frac", 0.0)))
         self.cells = inst.cells
         self.h = lib().or_create(C.byref(P))
         if not self.h:
@@ -244,6 +247,8 @@ class Sim:
         lib().or_read(self.h, species, *[_ptr(out[k]) for k in
                                          ("cell", "off", "vx", "vy", "vz",
                                           "id", "tie")])
+        out["w"] = np.zeros(n)
+        lib().or_read_weights(self.h, species, _ptr(out["w"]))
         return out
 
     def fields(self):

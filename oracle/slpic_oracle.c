@@ -16,6 +16,10 @@
  *   whole-marker events .............. Sec. III (colliding a fraction of pairs
  *                                      with the full weight); products carry
  *                                      the primary's flux weight (Sec. III)
+ *   weight splitting ................. Sec. III (every colliding pair splits
+ *                                      the primary: w_j,p0 = w_j,p1 + W_j,c),
+ *                                      with per-marker flux weights, as the
+ *                                      split_frac option (see collide_electron)
  *   density weight w_p = beta w_j .... after every kick or collision (Sec. III)
  *   setup ............................ Sec. IV: absorbing electrodes, cathode
  *                                      at x = 0, ion-induced secondary
@@ -58,6 +62,7 @@
 typedef struct {
   double x, vx, vy, vz, tie;
   uint64_t id;
+  double w;  /* the marker's flux weight in units of the instance's w_j */
 } marker;
 
 typedef struct {
@@ -74,7 +79,8 @@ struct or_sim {
   uint32_t step;
   mlist e, i;
   double *Q, *rho, *phi, *E;
-  int64_t* cross[2];  /* net upward crossings of each node in this step */
+  double* cross[2];   /* net upward crossings of each node in this step, each
+                        counted with the marker's relative weight */
   double* flux[2];    /* time-integrated flux through each node */
   double stats[OR_NSTAT];
   double min_margin;
@@ -441,7 +447,7 @@ static void deposit_and_solve(or_sim* s) {
     for (int64_t k = 0; k < l->n; ++k) {
       const marker* m = &l->a[k];
       double v = sqrt(m->vx * m->vx + m->vy * m->vy + m->vz * m->vz);
-      double wp = or_beta(v, s->v0) * s->w_j; /* density weight */
+      double wp = or_beta(v, s->v0) * s->w_j * m->w; /* density weight */
       int ci;
       double f;
       locate(s, m->x, &ci, &f);
@@ -547,7 +553,7 @@ or_sim* or_create(const or_params* p) {
   s->phi = (double*)calloc(N + 1, sizeof(double));
   s->E = (double*)calloc(N + 1, sizeof(double));
   for (int sp = 0; sp < 2; ++sp) {
-    s->cross[sp] = (int64_t*)calloc(N + 1, sizeof(int64_t));
+    s->cross[sp] = (double*)calloc(N + 1, sizeof(double));
     s->flux[sp] = (double*)calloc(N + 1, sizeof(double));
   }
 
@@ -556,6 +562,7 @@ or_sim* or_create(const or_params* p) {
     marker m = {0};
     m.id = (uint64_t)k;
     m.tie = INFINITY;
+    m.w = 1.0;
     if (p->seed_mode == OR_SEED_MAXWELL_CELL0) {
       uint32_t r[4];
       double v[3];
@@ -590,6 +597,7 @@ int or_load(or_sim* s, int species, int64_t n, const int32_t* cell, const double
     m.vx = vx[k]; m.vy = vy[k]; m.vz = vz[k];
     m.id = id[k];
     m.tie = INFINITY;
+    m.w = 1.0;
     if (push_back(l, &m)) return -1;
   }
   deposit_and_solve(s);
@@ -597,9 +605,46 @@ int or_load(or_sim* s, int species, int64_t n, const int32_t* cell, const double
 }
 
 /* ------------------------------------------------------------------ */
+/* Collision strategy (Sec. III).  The paper notes that Monte Carlo
+ * strategies which give the same expected number of collisions W_c are
+ * interchangeable: split every colliding primary (w_j,p0 = w_j,p1 + W_j,c,
+ * the collided part W_j,c carrying the products), or collide a fraction of
+ * the pairs with the primary's whole weight.  Both are written here through
+ * one split fraction s:
+ *   - a marker becomes a collision candidate with probability
+ *     q = min(1, P/s), P the per-step candidate probability (the
+ *     null-collision probability, or the fixed-event total);
+ *   - a candidate that collides moves the fraction f = max(s, P) of its flux
+ *     weight into the collision: q f = P, so the expected collided weight is
+ *     that of every candidate colliding whole with probability P;
+ *   - s = 1 (or s <= 0) is the whole-marker strategy (q = P, f = 1); with
+ *     f < 1 the primary keeps w (1 - f) and its velocity and id as the
+ *     uncollided part, and a new marker of weight w f (id from channel
+ *     CHILD, sub 2) leaves with the scattered velocity; ionization products
+ *     carry w f.
+ * Flux weights are conserved in every event (Sec. III). */
+static double split_frac(const or_sim* s) {
+  const double sf = s->p.split_frac;
+  return (sf > 0.0 && sf < 1.0) ? sf : 1.0;
+}
+
+/* the uncollided part stays as m (weight w (1 - f)); the scattered part is
+ * returned in *sc with the new velocity and weight w f and a new id */
+static void split_off(or_sim* s, marker* m, double f, const double v_new[3], marker* sc) {
+  uint32_t r[4];
+  draw_raw(s, m->id, s->step, OR_CH_CHILD, 2, r);
+  *sc = *m;
+  sc->vx = v_new[0];
+  sc->vy = v_new[1];
+  sc->vz = v_new[2];
+  sc->id = child_id(r[0], r[1]);
+  sc->w = m->w * f;
+  m->w = m->w * (1.0 - f);
+}
+
 /* Electron-neutral collision (Sec. III and Sec. IV).  The marker's channel is
  * drawn with per-step probability P_null nu'_k / nu'_max, the finite-step
- * form of Eq. (16); the whole marker takes part (Sec. III). */
+ * form of Eq. (16), split as above. */
 static int collide_electron(or_sim* s, marker* m, mlist* born_e, mlist* born_i) {
   uint32_t step = s->step;
   uint32_t r[4];
@@ -610,14 +655,30 @@ static int collide_electron(or_sim* s, marker* m, mlist* born_e, mlist* born_i) 
   double speed = sqrt(v2);
   double eps = 0.5 * ME * v2 / QE;
   int nc = s->p.n_chan, ch = -1;
+  const double sf = split_frac(s);
+  double f = 1.0;
   if (s->fixed) {
-    double cum = 0.0;
-    for (int k = 0; k < nc; ++k) {
-      cum += s->fixed[k];
-      if (ch < 0 && u0 < cum) ch = k;
+    double tot = 0.0;
+    for (int k = 0; k < nc; ++k) tot += s->fixed[k];
+    if (sf >= 1.0) {
+      double cum = 0.0;
+      for (int k = 0; k < nc; ++k) {
+        cum += s->fixed[k];
+        if (ch < 0 && u0 < cum) ch = k;
+      }
+    } else {
+      if (!(u0 < fmin(1.0, tot / sf))) return 0;
+      f = fmax(sf, tot);
+      /* channel k of a candidate with probability fixed_k / tot */
+      double cum = 0.0;
+      for (int k = 0; k < nc; ++k) {
+        cum += s->fixed[k];
+        if (ch < 0 && u1 < cum / tot) ch = k;
+      }
     }
   } else {
-    if (!(u0 < s->P_null_e)) return 0;
+    if (!(u0 < (sf >= 1.0 ? s->P_null_e : fmin(1.0, s->P_null_e / sf)))) return 0;
+    if (sf < 1.0) f = fmax(sf, s->P_null_e);
     double slow = fmin(speed, s->v0);
     double target = u1 * s->nu_max_e, cum = 0.0, margin = INFINITY;
     for (int k = 0; k < nc; ++k) {
@@ -632,6 +693,7 @@ static int collide_electron(or_sim* s, marker* m, mlist* born_e, mlist* born_i) 
   if (ch < 0) return 0;
   int kind = s->kind[ch];
   double thr = s->thr[ch], vout[3], mrot;
+  const double w_coll = m->w * (f < 1.0 ? f : 1.0);  /* weight of the collided part */
   if (kind == OR_ELASTIC) {
     double cosx = or_vs_cos_chi(eps, unif(r[2]));
     double eps1 = eps * (1.0 - 2.0 * ME / MAR * (1.0 - cosx));
@@ -659,12 +721,18 @@ static int collide_electron(or_sim* s, marker* m, mlist* born_e, mlist* born_i) 
                            TWO_PI * unif(q[2]), vej);
     if (m2 < mrot) mrot = m2;
     maxwellian(b, sqrt(KB * s->p.T_gas / MAR), vi);
-    marker ne = {m->x, vej[0], vej[1], vej[2], m->tie, child_id(c[0], c[1])};
-    marker ni = {m->x, vi[0], vi[1], vi[2], m->tie, child_id(c[2], c[3])};
+    marker ne = {m->x, vej[0], vej[1], vej[2], m->tie, child_id(c[0], c[1]), w_coll};
+    marker ni = {m->x, vi[0], vi[1], vi[2], m->tie, child_id(c[2], c[3]), w_coll};
     note_margin(s, &ne, mrot);
     note_margin(s, &ni, mrot);
     if (push_back(born_e, &ne) || push_back(born_i, &ni)) return -1;
     s->stats[OR_ST_IONIZ] += 1;
+  }
+  if (f < 1.0) {
+    marker sc;
+    split_off(s, m, f, vout, &sc);
+    note_margin(s, &sc, mrot);
+    return push_back(born_e, &sc);
   }
   note_margin(s, m, mrot);
   m->vx = vout[0];
@@ -673,16 +741,27 @@ static int collide_electron(or_sim* s, marker* m, mlist* born_e, mlist* born_i) 
   return 0;
 }
 
-/* Ar+ charge exchange: the ion leaves with a neutral's thermal velocity. */
-static void collide_ion(or_sim* s, marker* m) {
+/* Ar+ charge exchange: the ion leaves with a neutral's thermal velocity
+ * (split as above). */
+static int collide_ion(or_sim* s, marker* m, mlist* born_i) {
   uint32_t r[4];
   draw_raw(s, m->id, s->step, OR_CH_CX, 0, r);
   double u0 = unif(r[0]), u1 = unif(r[1]);
+  const double sf = split_frac(s);
+  double f = 1.0;
   int hit;
   if (s->fixed) {
-    hit = u0 < s->p.fixed_prob_cx;
+    const double P = s->p.fixed_prob_cx;
+    if (sf >= 1.0) {
+      hit = u0 < P;
+    } else {
+      hit = u0 < fmin(1.0, P / sf);
+      f = fmax(sf, P);
+    }
   } else {
-    if (!(s->p.sigma_cx > 0) || !(u0 < s->P_null_cx)) return;
+    if (!(s->p.sigma_cx > 0)) return 0;
+    if (!(u0 < (sf >= 1.0 ? s->P_null_cx : fmin(1.0, s->P_null_cx / sf)))) return 0;
+    if (sf < 1.0) f = fmax(sf, s->P_null_cx);
     double speed = sqrt(m->vx * m->vx + m->vy * m->vy + m->vz * m->vz);
     double nu = s->n_g * s->p.sigma_cx * fmin(speed, s->v0);
     if (nu > s->nu_max_cx * (1.0 + 1e-12)) s->err |= OR_ERR_NU_BOUND;
@@ -690,13 +769,19 @@ static void collide_ion(or_sim* s, marker* m) {
     note_margin(s, m, fabs(target - nu) / s->nu_max_cx);
     hit = target < nu;
   }
-  if (!hit) return;
+  if (!hit) return 0;
   uint32_t b[4];
   double vi[3];
   draw_raw(s, m->id, s->step, OR_CH_CX, 1, b);
   maxwellian(b, sqrt(KB * s->p.T_gas / MAR), vi);
-  m->vx = vi[0]; m->vy = vi[1]; m->vz = vi[2];
   s->stats[OR_ST_CX] += 1;
+  if (f < 1.0) {
+    marker sc;
+    split_off(s, m, f, vi, &sc);
+    return push_back(born_i, &sc);
+  }
+  m->vx = vi[0]; m->vy = vi[1]; m->vz = vi[2];
+  return 0;
 }
 
 /* Push one marker; returns 0 inside, 1 absorbed at the cathode, 2 at the anode.
@@ -732,7 +817,7 @@ static int push(or_sim* s, marker* m, double qm) {
  * speed.  Net crossings of the nodes between the cells before and after the
  * flight; absorbed markers end in cell -1 (cathode, w == 1) or cells (anode,
  * w == 2). */
-static void note_crossings(or_sim* s, int sp, double x0, double x1, int w) {
+static void note_crossings(or_sim* s, int sp, double x0, double x1, int w, double wt) {
   if (!(s->p.flags & OR_FLAG_FLUX)) return;
   if (w == 0 && !isfinite(x1)) return;  /* a non-finite state is an error, not a crossing */
   const int64_t N = s->p.cells;
@@ -745,8 +830,8 @@ static void note_crossings(or_sim* s, int sp, double x0, double x1, int w) {
     c1 = (int64_t)floor(x1 / s->dx);
     c1 = c1 < 0 ? 0 : (c1 > N - 1 ? N - 1 : c1);
   }
-  for (int64_t k = c0 + 1; k <= c1; ++k) s->cross[sp][k] += 1;
-  for (int64_t k = c1 + 1; k <= c0; ++k) s->cross[sp][k] -= 1;
+  for (int64_t k = c0 + 1; k <= c1; ++k) s->cross[sp][k] += wt;
+  for (int64_t k = c1 + 1; k <= c0; ++k) s->cross[sp][k] -= wt;
 }
 
 static int one_step(or_sim* s) {
@@ -766,7 +851,7 @@ static int one_step(or_sim* s) {
     marker m = s->e.a[k];
     const double xe0 = m.x;
     int w = push(s, &m, -QE / ME);
-    note_crossings(s, OR_ELECTRON, xe0, m.x, w);
+    note_crossings(s, OR_ELECTRON, xe0, m.x, w, m.w);
     if (w == 1) { s->stats[OR_ST_ABS_E_CATH] += 1; continue; }
     if (w == 2) { s->stats[OR_ST_ABS_E_ANODE] += 1; continue; }
     rc = collide_electron(s, &m, &born_e, &born_i);
@@ -776,7 +861,7 @@ static int one_step(or_sim* s) {
     marker m = s->i.a[k];
     const double x0 = m.x, vx0 = m.vx, a0 = QE / MAR * gather(s, m.x);
     int w = push(s, &m, QE / MAR);
-    note_crossings(s, OR_ION, x0, m.x, w);
+    note_crossings(s, OR_ION, x0, m.x, w, m.w);
     if (w == 1) {
       /* ion-induced secondary emission at the cathode (Sec. IV): an electron
        * at rest at x = 0 with probability gamma_se, or with the yield of
@@ -793,15 +878,15 @@ static int one_step(or_sim* s) {
         note_margin(s, &m, fabs(unif(r[0]) - gam));
       }
       if (unif(r[0]) < gam) {
-        marker ne = {0.0, 0.0, 0.0, 0.0, m.tie, child_id(r[2], r[3])};
+        marker ne = {0.0, 0.0, 0.0, 0.0, m.tie, child_id(r[2], r[3]), m.w};
         rc = push_back(&born_e, &ne);
         s->stats[OR_ST_SEE] += 1;
       }
       continue;
     }
     if (w == 2) { s->stats[OR_ST_ABS_I_ANODE] += 1; continue; }
-    collide_ion(s, &m);
-    rc = push_back(&out_i, &m);
+    rc = collide_ion(s, &m, &born_i);
+    if (!rc) rc = push_back(&out_i, &m);
   }
   /* continuous cathode source (or_set_source): electrons at rest at x = 0,
    * as many as keep the physical rate at the step's flux weight */
@@ -813,7 +898,7 @@ static int one_step(or_sim* s) {
     if (unif(r[0]) < want - floor(want)) n += 1;
     for (int64_t k = 0; k < n && !rc; ++k) {
       draw_raw(s, (uint64_t)k, step, OR_CH_INJECT, 0, r);
-      marker ne = {0.0, 0.0, 0.0, 0.0, INFINITY, child_id(r[0], r[1])};
+      marker ne = {0.0, 0.0, 0.0, 0.0, INFINITY, child_id(r[0], r[1]), 1.0};
       rc = push_back(&born_e, &ne);
     }
   }
@@ -855,7 +940,7 @@ static int one_step(or_sim* s) {
   if (s->p.flags & OR_FLAG_FLUX)
     for (int sp = 0; sp < 2; ++sp)
       for (int k = 0; k <= s->p.cells; ++k) {
-        s->flux[sp][k] += w_step * (double)s->cross[sp][k];
+        s->flux[sp][k] += w_step * s->cross[sp][k];
         s->cross[sp][k] = 0;
       }
   deposit_and_solve(s);
@@ -894,6 +979,12 @@ int or_read(const or_sim* s, int species, int32_t* cell, double* off, double* vx
     if (id) id[k] = m->id;
     if (tie) tie[k] = m->tie;
   }
+  return 0;
+}
+
+int or_read_weights(const or_sim* s, int species, double* w) {
+  const mlist* l = species == OR_ELECTRON ? &s->e : &s->i;
+  for (int64_t k = 0; k < l->n; ++k) w[k] = l->a[k].w;
   return 0;
 }
 

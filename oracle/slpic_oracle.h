@@ -82,6 +82,10 @@ typedef struct {
   const double* threshold_eV; /* [n_chan] */
   const int32_t* kind;        /* [n_chan] */
   const double* fixed_prob;   /* [n_chan] or NULL */
+  /* collision strategy (Sec. III): 0 or 1 collides whole markers; s in
+   * (0, 1) splits a colliding marker, moving the fraction max(s, P) of its
+   * flux weight into the collision (see collide_electron) */
+  double split_frac;
 } or_params;
 
 typedef struct or_sim or_sim;
@@ -98,6 +102,8 @@ int64_t or_count(const or_sim* s, int species);
  * along each marker's history (NULL to skip any output array) */
 int or_read(const or_sim* s, int species, int32_t* cell, double* off,
             double* vx, double* vy, double* vz, uint64_t* id, double* tie);
+/* flux weights of a species' markers in units of w_j, in or_read's order */
+int or_read_weights(const or_sim* s, int species, double* w);
 /* node arrays of length cells+1 (NULL to skip) */
 void or_fields(const or_sim* s, double* rho, double* phi, double* E);
 /* Time-integrated flux through each node (cells + 1 doubles, node 0 the

@@ -66,6 +66,8 @@ class Run:
     resort_period: int = 0   # cell sort every n steps (0 = never)
     ion_B_eV: float = 10.0   # ionization energy-sharing parameter
     kTe_seed_eV: float = 1.0
+    split_frac: float = 0.0  # collision strategy: 0 (or 1) whole markers;
+                             # in (0, 1) weight splitting (per-marker w_j)
 
 
 @dataclass
