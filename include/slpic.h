@@ -84,6 +84,22 @@ typedef struct slpic_config {
   double cfl;            /* v0 dt / dx in (0, 1] when dt is derived */
   double ion_B_eV;       /* ionization energy-sharing parameter [eV] */
   double kTe_seed_eV;    /* temperature of Maxwellian seed electrons [eV] */
+  double split_frac;     /* collision strategy (Sec. III), in [0, 1].  0 or 1:
+                            whole markers -- a candidate collides with its
+                            full flux weight, every marker of an instance
+                            shares w_j.  s in (0, 1): weight splitting --
+                            markers carry their own flux weight; a marker is
+                            a candidate with probability q = min(1, P / s)
+                            (P the null-collision, or fixed-event, candidate
+                            probability) and a colliding candidate moves the
+                            fraction f = max(s, P) of its weight into the
+                            collision: the primary stays with 1 - f of its
+                            weight, velocity and id, a new marker (id from
+                            Philox channel 7, sub 2) leaves with f and the
+                            scattered velocity, and ionization products
+                            carry f.  The expected collided weight equals the
+                            whole-marker one (q f = P).  Not available with
+                            SLPIC_FLAG_FLUX. */
 } slpic_config;
 
 /* One independent gap (p, d, V). */
@@ -259,6 +275,14 @@ int slpic_partitions(slpic_t* h, int inst, int species, int32_t* parts, int64_t*
 int slpic_read_markers(slpic_t* h, int inst, int species, int64_t max_n,
                        int64_t* n, int32_t* cell, double* off, double* vx,
                        double* vy, double* vz, uint64_t* id);
+
+/* Flux weights (in units of the instance's w_j, as in slpic_scalars) of the
+ * markers of one species of one instance, in slpic_read_markers' order:
+ * host array w of at least max_n entries; *n receives the count.  Only with
+ * weight splitting (split_frac in (0, 1)), else SLPIC_INVALID_ARG.
+ * Synchronizes. */
+int slpic_read_weights(slpic_t* h, int inst, int species, int64_t max_n, int64_t* n,
+                       double* w);
 
 /* Node arrays (cells + 1 each, host, NULL to skip) of one instance: charge
  * density [C/m^3], potential [V] and field [V/m].  Synchronizes. */

@@ -38,7 +38,8 @@ class slpic_config(C.Structure):
                 ("flags", C.c_uint32), ("resort_period", C.c_int32),
                 ("T_gas", C.c_double), ("area", C.c_double),
                 ("w_j0", C.c_double), ("cfl", C.c_double),
-                ("ion_B_eV", C.c_double), ("kTe_seed_eV", C.c_double)]
+                ("ion_B_eV", C.c_double), ("kTe_seed_eV", C.c_double),
+                ("split_frac", C.c_double)]
 
 
 class slpic_instance(C.Structure):
@@ -79,7 +80,7 @@ EXPORTS = ["slpic_workspace_bytes", "slpic_create", "slpic_create_static", "slpi
            "slpic_scalars", "slpic_steps_done", "slpic_last_error",
            "slpic_destroy", "slpic_philox_device", "slpic_profile",
            "slpic_kernel_times", "slpic_partitions", "slpic_autotune",
-           "slpic_grid", "slpic_sort"]
+           "slpic_grid", "slpic_sort", "slpic_read_weights"]
 
 
 def lib():
@@ -104,6 +105,7 @@ def lib():
         L.slpic_count.argtypes = [vp, i32, i32, P(i64)]
         L.slpic_read_markers.argtypes = [vp, i32, i32, i64, P(i64), vp, vp, vp, vp, vp, vp]
         L.slpic_read_fields.argtypes = [vp, i32, vp, vp, vp]
+        L.slpic_read_weights.argtypes = [vp, i32, i32, i64, P(i64), vp]
         L.slpic_read_flux.argtypes = [vp, i32, i32, vp, i32]
         L.slpic_set_source.argtypes = [vp, i32, C.c_double]
         L.slpic_read_stats.argtypes = [vp, i32, i64, i32, vp]
@@ -140,7 +142,8 @@ def make_config(run, flags=0):
                         flags=flags, resort_period=run.resort_period,
                         T_gas=run.T_gas, area=run.area, w_j0=run.w_j0,
                         cfl=run.cfl, ion_B_eV=run.ion_B_eV,
-                        kTe_seed_eV=run.kTe_seed_eV)
+                        kTe_seed_eV=run.kTe_seed_eV,
+                        split_frac=float(getattr(run, "split_frac", 0.0)))
 
 
 def make_instances(insts):
@@ -308,6 +311,11 @@ class Sim:
             self.h, inst, species, n, C.byref(got),
             *[_p(out[k]) for k in ("cell", "off", "vx", "vy", "vz", "id")]),
             self.h)
+        if 0.0 < self.cfg.split_frac < 1.0:
+            # flux weights (units of w_j), in the same order
+            out["w"] = np.zeros(n)
+            _check(lib().slpic_read_weights(self.h, inst, species, n, C.byref(got),
+                                            _p(out["w"])), self.h)
         return out
 
     def fields(self, inst=0):

@@ -20,7 +20,7 @@ template <typename R> hipError_t launch_particles(const Ctx<R>&, int, hipStream_
 template <typename R> hipError_t launch_tail(const Ctx<R>&, int, hipStream_t);
 template <typename R>
 hipError_t launch_seed(const Ctx<R>&, int, int, int64_t, double, uint32_t, hipStream_t);
-template <typename R> hipError_t occupancy_gen(int*, size_t);
+template <typename R> hipError_t occupancy_gen(int*, size_t, bool);
 // dynamic LDS of the particle kernel: tile offsets of the (instance,
 // species) pairs
 inline size_t gen_lds_bytes(int n_inst) { return ((size_t)(2 * n_inst + 1) * 4 + 15) & ~size_t(15); }
@@ -60,10 +60,15 @@ uint32_t prob_threshold(double P) {
   return (uint32_t)t;
 }
 
+// Weight splitting (Sec. III) is on for a split fraction strictly between 0
+// and 1; 0 and 1 collide whole markers.
+bool splitting(const slpic_config* cfg) { return cfg->split_frac > 0.0 && cfg->split_frac < 1.0; }
+
 struct Layout {
-  size_t ip, st, counts, tiles, cross, flux, ev, acc, E, E64, phi, rho, ring, inst_err, sort_hist, sort_cur,
+  size_t ip, st, counts, tiles, cross, flux, ev, maxw, acc, E, E64, phi, rho, ring, inst_err, sort_hist, sort_cur,
       glob, xs_e, xs_sig, xs_thr, xs_kind;
   size_t blk[2][2];      // [buffer][species] chunk arrays of the markers
+  size_t wt[2][2];       // [buffer][species] marker flux weights (splitting), or 0
   size_t total;
   int total_nodes, max_tiles;
   int64_t total_cap;
@@ -123,6 +128,7 @@ bool make_layout(const slpic_config* cfg, const slpic_instance* inst, int n_inst
   L.st = take(sizeof(InstState) * 2 * n_inst);
   L.counts = take(sizeof(uint32_t) * CSTRIDE * 3 * 2 * MAX_PART * (size_t)n_inst);
   L.ev = take(sizeof(unsigned long long) * NEV * NSLOT * (size_t)n_inst);
+  L.maxw = take(sizeof(uint32_t) * (size_t)n_inst);
   L.acc = take(sizeof(unsigned long long) * 2 * NSLOT * (size_t)nodes);
   L.E = take(rs * 2 * nodes);
   L.E64 = take(8 * 2 * (size_t)nodes);
@@ -145,6 +151,8 @@ bool make_layout(const slpic_config* cfg, const slpic_instance* inst, int n_inst
   const size_t chunk_bytes = (size_t)CH * (4 + 4 * rs + 8);
   for (int b = 0; b < 2; ++b)
     for (int s = 0; s < 2; ++s) L.blk[b][s] = take(chunk_bytes * (size_t)(cap / CH));
+  for (int b = 0; b < 2; ++b)
+    for (int s = 0; s < 2; ++s) L.wt[b][s] = splitting(cfg) ? take(rs * (size_t)cap) : 0;
   L.total = o;
   return true;
 }
@@ -158,6 +166,9 @@ std::string validate(const slpic_config* cfg, const slpic_instance* inst, int n_
   if (!(cfg->cfl > 0 && cfg->cfl <= 1)) return "cfl must be in (0, 1]";
   if (!(cfg->ion_B_eV > 0)) return "ion_B_eV must be > 0";
   if (cfg->resort_period < 0) return "resort_period must be >= 0";
+  if (!(cfg->split_frac >= 0.0 && cfg->split_frac <= 1.0)) return "split_frac must be in [0, 1]";
+  if (splitting(cfg) && (cfg->flags & SLPIC_FLAG_FLUX))
+    return "the flux diagnostic is not available with weight splitting";
   if (cfg->flags & ~(uint32_t)(SLPIC_FLAG_PRODUCTS_AT_REST | SLPIC_FLAG_SEE_ENERGY | SLPIC_FLAG_FLUX))
     return "unknown flags";
   if (xs->n_chan < 0 || xs->n_chan > MAX_CHAN) return "n_chan must be in 0..8";
@@ -257,18 +268,37 @@ InstParams derive(const slpic_config* cfg, const slpic_instance& I, const slpic_
   P.parts = L.parts[i];
   P.n_target = I.n_target;
   P.node = L.node[i];
-  P.t_null_e = prob_threshold(-std::expm1(-P.nu_max_e * P.dt));
-  P.t_null_cx = prob_threshold(-std::expm1(-P.nu_max_cx * P.dt));
+  // collision strategy (Sec. III): candidates with q = min(1, P / s), the
+  // fraction f = max(s, P) of a colliding candidate's flux weight collides;
+  // whole markers: q = P, f = 1
+  const bool split = splitting(cfg);
+  const double sf = cfg->split_frac;
+  auto cand = [&](double Pc) { return split ? std::min(1.0, Pc / sf) : Pc; };
+  auto frac = [&](double Pc) { return split ? std::max(sf, Pc) : 1.0; };
+  const double Pn_e = -std::expm1(-P.nu_max_e * P.dt), Pn_cx = -std::expm1(-P.nu_max_cx * P.dt);
+  P.t_null_e = prob_threshold(cand(Pn_e));
+  P.t_null_cx = prob_threshold(cand(Pn_cx));
+  P.f_e = frac(Pn_e);
+  P.f_cx = frac(Pn_cx);
   P.t_see = prob_threshold(I.gamma_se);
   P.key = I.stream >= 0 ? (uint32_t)I.stream : (uint32_t)i;
   if (xs->fixed_prob) {
+    double tot = 0.0;
+    for (int k = 0; k < xs->n_chan; ++k) tot += xs->fixed_prob[k];
     double cum = 0.0;
     for (int k = 0; k < xs->n_chan; ++k) {
       cum += xs->fixed_prob[k];
       P.t_fixed[k] = prob_threshold(cum);
+      P.t_fsplit[k] = tot > 0.0 ? prob_threshold(cum / tot) : 0u;
     }
-    P.t_fixed_cx = prob_threshold(xs->fixed_prob_cx);
+    P.t_cand_fixed_e = split ? prob_threshold(cand(tot))
+                             : (xs->n_chan > 0 ? P.t_fixed[xs->n_chan - 1] : 0u);
+    P.f_e = frac(tot);
+    P.t_fixed_cx = prob_threshold(cand(xs->fixed_prob_cx));
+    P.f_cx = frac(xs->fixed_prob_cx);
   }
+  P.g_e = 1.0 - P.f_e;
+  P.g_cx = 1.0 - P.f_cx;
   return P;
 }
 
@@ -335,6 +365,7 @@ void fill_ctx(slpic_t* h, Ctx<R>& C) {
   C.st = reinterpret_cast<InstState*>(w + L.st);
   C.counts = reinterpret_cast<uint32_t*>(w + L.counts);
   C.ev = reinterpret_cast<unsigned long long*>(w + L.ev);
+  C.maxw = reinterpret_cast<uint32_t*>(w + L.maxw);
   C.acc = reinterpret_cast<unsigned long long*>(w + L.acc);
   C.E = reinterpret_cast<R*>(w + L.E);
   C.E64 = reinterpret_cast<double*>(w + L.E64);
@@ -348,6 +379,9 @@ void fill_ctx(slpic_t* h, Ctx<R>& C) {
   C.cross = reinterpret_cast<int32_t*>(w + L.cross);
   C.flux = reinterpret_cast<double*>(w + L.flux);
   C.g = reinterpret_cast<Global*>(w + L.glob);
+  C.split = splitting(&h->cfg) ? 1 : 0;
+  for (int b = 0; b < 2; ++b)
+    for (int s = 0; s < 2; ++s) C.wt[b][s] = C.split ? reinterpret_cast<R*>(w + L.wt[b][s]) : nullptr;
   C.xs_e = reinterpret_cast<const R*>(w + L.xs_e);
   C.xs_sig = reinterpret_cast<const R*>(w + L.xs_sig);
   C.xs_thr = reinterpret_cast<const R*>(w + L.xs_thr);
@@ -565,6 +599,12 @@ int load_impl(slpic_t* h, int inst, int sp, int64_t n, const int32_t* cell, cons
     }
     const int64_t at = P.seg + (int64_t)p * P.cap_p;  // a multiple of CH
     if (m) HIPCHK(h, hipMemcpy(B.chunk(at), img.data(), img.size(), hipMemcpyHostToDevice));
+    if (m && splitting(&h->cfg)) {
+      // loaded markers carry the instance's flux weight (relative weight 1)
+      const std::vector<R> ones((size_t)m, R(1));
+      HIPCHK(h, hipMemcpy(h->ws + h->L.wt[bsel][sp] + (size_t)at * sizeof(R), ones.data(),
+                          (size_t)m * sizeof(R), hipMemcpyHostToDevice));
+    }
     const uint32_t cnt = (uint32_t)m;
     HIPCHK(h, hipMemcpy(h->ws + count_offset(h, slot3, inst, sp, p), &cnt, sizeof(uint32_t),
                         hipMemcpyHostToDevice));
@@ -583,6 +623,34 @@ int part_counts(slpic_t* h, uint32_t slot3, int inst, int sp, std::vector<uint32
   c.assign(P, 0u);
   HIPCHK(h, hipMemcpy2D(c.data(), sizeof(uint32_t), h->ws + count_offset(h, slot3, inst, sp, 0),
                         sizeof(uint32_t) * CSTRIDE, sizeof(uint32_t), P, hipMemcpyDeviceToHost));
+  return SLPIC_OK;
+}
+
+template <typename R>
+int read_weights_impl(slpic_t* h, int inst, int sp, int64_t max_n, int64_t* n_out, double* w) {
+  Global G;
+  uint32_t slot3, bsel;
+  int rc = current(h, G, slot3, bsel);
+  if (rc) return rc;
+  std::vector<uint32_t> cnt;
+  rc = part_counts(h, slot3, inst, sp, cnt);
+  if (rc) return rc;
+  int64_t n = 0;
+  for (uint32_t c : cnt) n += c;
+  *n_out = n;
+  if (n > max_n) return fail(h, SLPIC_INVALID_ARG, "output array too small");
+  const InstParams& P = h->ip[inst];
+  int64_t done = 0;
+  std::vector<R> buf;
+  for (int p = 0; p < P.parts; ++p) {
+    const int64_t m = cnt[p], at = P.seg + (int64_t)p * P.cap_p;
+    if (!m) continue;
+    buf.resize((size_t)m);
+    HIPCHK(h, hipMemcpy(buf.data(), h->ws + h->L.wt[bsel][sp] + (size_t)at * sizeof(R),
+                        (size_t)m * sizeof(R), hipMemcpyDeviceToHost));
+    for (int64_t q = 0; q < m; ++q) w[done + q] = (double)buf[(size_t)q];
+    done += m;
+  }
   return SLPIC_OK;
 }
 
@@ -665,8 +733,8 @@ int create_impl(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess)
-    e = cfg->precision == 64 ? occupancy_gen<double>(&per_cu, gen_lds_bytes(n_inst))
-                             : occupancy_gen<float>(&per_cu, gen_lds_bytes(n_inst));
+    e = cfg->precision == 64 ? occupancy_gen<double>(&per_cu, gen_lds_bytes(n_inst), splitting(cfg))
+                             : occupancy_gen<float>(&per_cu, gen_lds_bytes(n_inst), splitting(cfg));
   if (e != hipSuccess) {
     int rc = hip_fail(nullptr, e, "device query");
     delete h;
@@ -705,7 +773,8 @@ int create_impl(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
   std::vector<uint32_t> counts((size_t)CSTRIDE * 3 * 2 * MAX_PART * n_inst, 0u);
   std::vector<uint32_t> tiles((size_t)3 * 2 * n_inst, 0u);
   for (int i = 0; i < n_inst; ++i) {
-    st[i] = InstState{cfg->w_j0, 0u, POP_NONE};
+    const int base_shift = cfg->precision == 64 ? h->c64.dep_shift : h->c32.dep_shift;
+    st[i] = InstState{cfg->w_j0, 0u, POP_NONE, base_shift, 0};
     st[n_inst + i] = st[i];
     const int64_t ns = inst[i].seed_mode != SLPIC_SEED_NONE ? inst[i].n_seed : 0;
     const int P = L.parts[i];
@@ -729,6 +798,7 @@ int create_impl(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
   if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.cross, 0, sizeof(int32_t) * 2 * L.total_nodes, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.flux, 0, sizeof(double) * 2 * L.total_nodes, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.inst_err, 0, sizeof(uint32_t) * n_inst, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.maxw, 0, sizeof(uint32_t) * n_inst, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.ring, 0, sizeof(StatsRow) * RING * n_inst, h->stream);
   for (int i = 0; i < n_inst && e == hipSuccess; ++i) {
     if (inst[i].seed_mode == SLPIC_SEED_NONE) continue;
@@ -1045,6 +1115,15 @@ int slpic_read_markers(slpic_t* h, int inst, int species, int64_t max_n, int64_t
   return h->cfg.precision == 64
              ? read_impl<double>(h, inst, species, max_n, n, cell, off, vx, vy, vz, id)
              : read_impl<float>(h, inst, species, max_n, n, cell, off, vx, vy, vz, id);
+}
+
+int slpic_read_weights(slpic_t* h, int inst, int species, int64_t max_n, int64_t* n,
+                       double* w) {
+  if (!h || !n || !w || inst < 0 || inst >= h->n_inst || (species != 0 && species != 1))
+    return fail(h, SLPIC_INVALID_ARG, "bad read arguments");
+  if (!splitting(&h->cfg)) return fail(h, SLPIC_INVALID_ARG, "markers carry weights only with weight splitting");
+  return h->cfg.precision == 64 ? read_weights_impl<double>(h, inst, species, max_n, n, w)
+                                : read_weights_impl<float>(h, inst, species, max_n, n, w);
 }
 
 int slpic_read_fields(slpic_t* h, int inst, double* rho, double* phi, double* E) {

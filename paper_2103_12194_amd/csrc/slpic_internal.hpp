@@ -58,6 +58,13 @@ enum Mode { MODE_STEP = 0, MODE_REFRESH = 1 };
 // Per-instance constants.  Integer thresholds t_* turn a probability P into
 // the test (r >> 9) < t on a raw 32-bit Philox word, which equals
 // u < P for u = (2 (r >> 9) + 1) 2^-24.
+//
+// Collision strategy (Sec. III): with a split fraction s in (0, 1) a marker
+// is a collision candidate with probability q = min(1, P / s) (P the
+// null-collision or fixed-event candidate probability) and a colliding
+// candidate moves the fraction f = max(s, P) of its flux weight into the
+// collision; otherwise q = P and f = 1 (whole markers).  The candidate
+// thresholds below hold q, and f_e, f_cx hold f.
 struct InstParams {
   double d, dx, inv_dx, dt, V, n_g, v0, area, gamma_se;
   double nu_max_e, nu_max_cx, sigma_cx;
@@ -74,10 +81,16 @@ struct InstParams {
   int32_t cells, node;      // node: first node of the instance in node arrays
   int32_t limited;          // 0: plain PIC (beta == 1)
   int32_t parts;            // partitions P, a power of two (tile j reads j mod P)
-  uint32_t t_null_e, t_null_cx, t_see;
+  double f_e, f_cx;          // collided fraction of a colliding candidate
+  double g_e, g_cx;          // 1 - f_e, 1 - f_cx (in FP64: no cancellation in FP32)
+  uint32_t t_null_e, t_null_cx, t_see;  // candidate thresholds (q), emission
+  uint32_t t_cand_fixed_e;   // fixed-event electron candidate threshold (q)
   uint32_t key;             // Philox key word 1 of the instance's draws
-  uint32_t t_fixed[MAX_CHAN];
-  uint32_t t_fixed_cx;
+  uint32_t t_fixed[MAX_CHAN];  // fixed events, whole markers: channel k if
+                               // (r.x >> 9) < t_fixed[k]
+  uint32_t t_fsplit[MAX_CHAN]; // fixed events, split: channel k of a
+                               // candidate if (r.y >> 9) < t_fsplit[k]
+  uint32_t t_fixed_cx;         // fixed-event charge-exchange candidate (q)
 };
 
 // Markers of one (buffer, species) in chunks of CH slots.  Within a chunk
@@ -116,6 +129,11 @@ struct InstState {
   double w_j;
   uint32_t step;
   int32_t popmode;
+  int32_t dshift;   // fraction bits of this step's fixed-point deposit: the
+                    // handle's base, raised with weight splitting by
+                    // floor(-log2) of the largest marker flux weight, so
+                    // that deposits keep their resolution as weights shrink
+  int32_t pad;
 };
 
 // Handle-wide device words.  Per-step state is buffered by generation: a
@@ -157,7 +175,9 @@ struct Ctx {
   int n_inst, total_nodes, grid, max_tiles;
   int fixed;
   uint32_t flags, seed;
-  int dep_shift;             // fraction bits of the fixed-point deposit
+  int dep_shift;             // base fraction bits of the fixed-point deposit
+  uint32_t* maxw;            // [n_inst] largest flux weight (float bits) among a
+                             // step's outputs (weight splitting)
   int tail_lds;              // dynamic LDS bytes of the tail kernel
   int gen_lds;               // dynamic LDS bytes of the particle kernel
   uint32_t* sort_hist;       // [2][total_nodes] cell counts of the cell sort
@@ -166,6 +186,9 @@ struct Ctx {
   int32_t* cross;            // [2][total_nodes] net upward node crossings of a step
   double* flux;              // [2][total_nodes] time-integrated flux (w_j units)
   int max_cells;             // largest cell count of the batch
+  R* wt[2][2];               // [buffer][species] flux weight of each marker slot
+                             // in units of w_j (weight splitting only, else NULL)
+  int split;                 // weight splitting (split fraction in (0, 1))
   int sort_lds1, sort_lds2;  // dynamic LDS bytes of the sort's count and scatter
 };
 

@@ -442,6 +442,7 @@ struct Mk {  // one marker's state
   int32_t cell;
   R off, vx, vy, vz;
   uint64_t id;
+  R w;       // flux weight in units of the instance's w_j (weight splitting)
 };
 
 // ---------------------------------------------------------------- helpers
@@ -602,6 +603,7 @@ __device__ double inject(const Ctx<R>& C, IP& P, int inst, const InstState& cur,
         out.vy(sl) = R(0);
         out.vz(sl) = R(0);
         out.id(sl) = id[j];
+        if (C.split) C.wt[bout][0][sl] = R(1);
       }
     }
     base += (int64_t)tot[0];
@@ -627,7 +629,7 @@ __device__ double inject(const Ctx<R>& C, IP& P, int inst, const InstState& cur,
   }
   double vk[1] = {(double)kept}, exk[1], totk[1];
   block_scan<1, TBLOCK / WAVE>(vk, exk, totk, sh);
-  return totk[0] * (double)(1ull << C.dep_shift);
+  return __builtin_ldexp(totk[0], cur.dshift);
 }
 
 // One workgroup of TBLOCK threads per instance, launched after the particle
@@ -744,7 +746,21 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
                             ? (cur.popmode == POP_ROULETTE ? 2.0 : (cur.popmode == POP_SPLIT ? 0.5 : 1.0))
                             : 1.0;
   const double wj = cur.w_j * factor;
-  const double unit = 1.0 / (double)(1ull << C.dep_shift);
+  // the shift this step's deposits used, and the next step's: with weight
+  // splitting the base raised by floor(-log2) of the largest output flux
+  // weight (an active source injects weight 1)
+  const int dsh = MODE == MODE_STEP ? cur.dshift : C.dep_shift;
+  const double unit = __builtin_ldexp(1.0, -dsh);
+  int next_dsh = C.dep_shift;
+  if (MODE == MODE_STEP && C.split) {
+    float mw = __uint_as_float(C.maxw[inst]);
+    if (P.src > 0.0) mw = 1.0f;
+    if (mw > 0.0f && mw < 1.0f) {
+      int e;
+      (void)frexpf(mw, &e);  // mw in [2^(e-1), 2^e)
+      next_dsh += -e;        // floor(-log2 mw) >= -e
+    }
+  }
   const double qvol = QE * wj * unit / (P.area * P.dx);
   // charge density at the nodes this thread read (half cells at the
   // electrodes); with the flux diagnostic, the step's node crossings times
@@ -821,6 +837,9 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
     nx.w_j = wj;
     nx.step = cur.step + (MODE == MODE_STEP ? 1u : 0u);
     nx.popmode = pm;
+    nx.dshift = next_dsh;
+    nx.pad = 0;
+    if (C.split) C.maxw[inst] = 0u;
     C.st[sn * C.n_inst + inst] = nx;
     if (MODE == MODE_STEP) {
       // field by field, so that the row is never held in registers
@@ -982,14 +1001,18 @@ struct TileCursor {
 };
 
 // ---------------------------------------------------------------- main kernel
-template <typename R>
+template <typename R, bool WS>
 struct LaneOut {
-  Mk<R> e[2];        // electrons produced by this lane (before population
-                     // control): the marker or its emitted electron, and an
-                     // ionization's ejected electron
-  Mk<R> i;           // the ion produced by this lane: the marker or an
-                     // ionization's new ion
-  uint32_t me, mi;   // me: which slots of e[] are set (bit j: slot j); mi: i is set
+  // electrons produced by this lane (before population control): the marker
+  // or its emitted electron, an ionization's ejected electron and, with
+  // weight splitting, the scattered part of a split primary
+  static constexpr int NE = WS ? 3 : 2;
+  // ions: the marker or an ionization's new ion, and with weight splitting
+  // the scattered part of a split charge exchange
+  static constexpr int NI = WS ? 2 : 1;
+  Mk<R> e[NE];
+  Mk<R> i[NI];
+  uint32_t me, mi;   // which slots of e[] and i[] are set (bit j: slot j)
 };
 
 constexpr int NWAVE = BLOCK / WAVE;
@@ -1009,6 +1032,7 @@ struct Work {
   int inst, sp, part;
   uint32_t step;
   int pop;
+  int dshift;        // fraction bits of this step's fixed-point deposit
   int64_t pbase;
   uint32_t emits;
 };
@@ -1035,12 +1059,15 @@ __device__ __forceinline__ void next_output(Work& W, IP& P) {
 // the markers each lane of one wave produced.  Called by all lanes of the
 // wave, independently of the other waves.  QUEUE: outputs of collided
 // candidates (collision events) rather than of a tile (wall and emission
-// events).  Event counts go to the wave's row evw of LDS counters.
-template <typename R, int MODE, bool QUEUE>
+// events).  Event counts go to the wave's row evw of LDS counters.  WS: the
+// markers carry flux weights (weight splitting), which scale their deposit
+// and are stored with them.
+template <typename R, int MODE, bool QUEUE, bool WS>
 __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWin& win,
-                                     unsigned long long (*hist)[HWIN], const LaneOut<R>& o,
+                                     unsigned long long (*hist)[HWIN], const LaneOut<R, WS>& o,
                                      uint32_t ev, uint32_t err, uint32_t g, uint32_t bsel,
                                      uint32_t* evw) {
+  constexpr int NE = LaneOut<R, WS>::NE, NI = LaneOut<R, WS>::NI;
   const int lane = threadIdx.x & (WAVE - 1);
   IP& P = param(C.ip, W.inst);
   const int inst = W.inst, pop = W.pop;
@@ -1050,10 +1077,11 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
 
   // population control: each output is kept (roulette) or doubled (split)
   uint32_t keep_e = 0, keep_i = 0;
-  uint64_t clone_e[2] = {0, 0}, clone_i = 0;
+  uint64_t clone_e[NE], clone_i[NI];
   int cnt_e = 0, cnt_i = 0;
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < NE; ++j) {
+    clone_e[j] = 0;
     if (!(o.me >> j & 1u)) continue;
     if (pop == POP_ROULETTE) {
       const U4 r = draw_cold(o.e[j].id, step, CH_ROULETTE, C.seed, P.key);
@@ -1068,66 +1096,77 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
       }
     }
   }
-  if (o.mi) {
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    clone_i[j] = 0;
+    if (!(o.mi >> j & 1u)) continue;
     if (pop == POP_ROULETTE) {
-      const U4 r = draw_cold(o.i.id, step, CH_ROULETTE, C.seed, P.key);
-      if ((r.x >> 9) < (1u << 22)) { keep_i = 1u; ++cnt_i; }
+      const U4 r = draw_cold(o.i[j].id, step, CH_ROULETTE, C.seed, P.key);
+      if ((r.x >> 9) < (1u << 22)) { keep_i |= 1u << j; ++cnt_i; }
     } else {
-      keep_i = 1u;
+      keep_i |= 1u << j;
       ++cnt_i;
       if (pop == POP_SPLIT) {
-        const U4 r = draw_cold(o.i.id, step, CH_CHILD | (1u << 8), C.seed, P.key);
-        clone_i = child(r.x, r.y);
+        const U4 r = draw_cold(o.i[j].id, step, CH_CHILD | (1u << 8), C.seed, P.key);
+        clone_i[j] = child(r.x, r.y);
         ++cnt_i;
       }
     }
   }
-  // at most three outputs per lane (one from a tile, three from an
-  // ionization)
+  // at most NE + NI outputs per lane (one from a tile; three, or five with
+  // weight splitting, from a collision)
   const int n_out = __popc(o.me) + __popc(o.mi);
   const int removed = pop == POP_ROULETTE ? n_out - (cnt_e + cnt_i) : 0;
   const int split_added = pop == POP_SPLIT ? n_out : 0;
 
   // compaction: prefix within the wave by bit-sliced ballots (cnt_e in
-  // 0..4, 4 only for a split ionization; cnt_i in 0..2), one reservation per
-  // wave and species on the partition's counter.  The reservations go out
-  // before the deposit and the event counts, which run while they return.
+  // 0..2 NE, cnt_i in 0..2 NI), one reservation per wave and species on the
+  // partition's counter.  The reservations go out before the deposit and the
+  // event counts, which run while they return.
+  constexpr bool E3 = QUEUE || WS;   // cnt_e can reach 4
+  constexpr bool I3 = QUEUE && WS;   // cnt_i can reach 4
   const unsigned long long lt = (1ull << lane) - 1ull;
   const unsigned long long be0 = __ballot(cnt_e & 1), be1 = __ballot(cnt_e & 2),
-                           be2 = QUEUE ? __ballot(cnt_e & 4) : 0ull;
-  const unsigned long long bi0 = __ballot(cnt_i & 1), bi1 = __ballot(cnt_i & 2);
+                           be2 = E3 ? __ballot(cnt_e & 4) : 0ull;
+  const unsigned long long bi0 = __ballot(cnt_i & 1), bi1 = __ballot(cnt_i & 2),
+                           bi2 = I3 ? __ballot(cnt_i & 4) : 0ull;
   const uint32_t pre_e = __popcll(be0 & lt) + 2 * __popcll(be1 & lt) + 4 * __popcll(be2 & lt);
-  const uint32_t pre_i = __popcll(bi0 & lt) + 2 * __popcll(bi1 & lt);
+  const uint32_t pre_i = __popcll(bi0 & lt) + 2 * __popcll(bi1 & lt) + 4 * __popcll(bi2 & lt);
   const uint32_t te = __popcll(be0) + 2 * __popcll(be1) + 4 * __popcll(be2);
-  const uint32_t ti = __popcll(bi0) + 2 * __popcll(bi1);
+  const uint32_t ti = __popcll(bi0) + 2 * __popcll(bi1) + 4 * __popcll(bi2);
   uint32_t base_e = 0u, base_i = 0u;
   if (MODE == MODE_STEP && lane == 0) {
     if (te) base_e = atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 0, W.part), te);
     if (ti) base_i = atomicAdd(C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, 1, W.part), ti);
   }
   // deposit (fixed point, units of q w_j): every kept marker adds its two
-  // linear weights to the LDS window (clones count twice)
+  // linear weights, times its flux weight with weight splitting, to the LDS
+  // window (clones count twice)
   {
-    const int shift = C.dep_shift;
+    const int shift = W.dshift;
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < NE; ++q) {
       if (!(keep_e >> q & 1u)) continue;
       const Mk<R>& e = o.e[q];
-      const R b = beta_fast(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
+      R b = beta_fast(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
+      if (WS) b *= e.w;
       const unsigned long long mul = clone_e[q] ? 2ull : 1ull;
       dep_add(C.acc, C.acc, hist, win, 0, P.node, C.total_nodes, e.cell,
               fixed_pt<R>(b * (R(1) - e.off), shift) * mul, fixed_pt<R>(b * e.off, shift) * mul);
     }
-    if (keep_i) {
-      const Mk<R>& e = o.i;
-      const R b = beta_fast(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
-      const unsigned long long mul = clone_i ? 2ull : 1ull;
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+      if (!(keep_i >> q & 1u)) continue;
+      const Mk<R>& e = o.i[q];
+      R b = beta_fast(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
+      if (WS) b *= e.w;
+      const unsigned long long mul = clone_i[q] ? 2ull : 1ull;
       dep_add(C.acc, C.acc, hist, win, 1, P.node, C.total_nodes, e.cell,
               fixed_pt<R>(b * (R(1) - e.off), shift) * mul, fixed_pt<R>(b * e.off, shift) * mul);
     }
   }
 
-  // events: wave totals by ballot; removed and split_added are in 0..3
+  // events: wave totals by ballot; removed and split_added are in 0..NE+NI
   if (QUEUE) {
     if (__ballot(ev != 0u)) {
 #pragma unroll
@@ -1147,18 +1186,35 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
   }
   if (pop != POP_NONE) {
     const int x = pop == POP_ROULETTE ? removed : split_added;
-    const uint32_t n = (uint32_t)(__popcll(__ballot(x & 1)) + 2 * __popcll(__ballot(x & 2)));
+    const uint32_t n = (uint32_t)(__popcll(__ballot(x & 1)) + 2 * __popcll(__ballot(x & 2)) +
+                                  4 * __popcll(__ballot(x & 4)));
     if (lane == 0 && n) atomicAdd(&evw[pop == POP_ROULETTE ? EV_ROULETTE : EV_SPLIT], n);
   }
   if (err) atomicOr(C.inst_err + inst, err);
 
   if (MODE != MODE_STEP) return;
+  if (WS) {
+    // the largest flux weight among the wave's outputs, for the next
+    // step's deposit shift (positive floats order as their bit patterns)
+    float mw = 0.0f;
+#pragma unroll
+    for (int j = 0; j < NE; ++j)
+      if (keep_e >> j & 1u) mw = fmaxf(mw, (float)o.e[j].w);
+#pragma unroll
+    for (int j = 0; j < NI; ++j)
+      if (keep_i >> j & 1u) mw = fmaxf(mw, (float)o.i[j].w);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) mw = fmaxf(mw, __shfl_xor(mw, d));
+    if (lane == 0 && mw > 0.0f) atomicMax(C.maxw + inst, __float_as_uint(mw));
+  }
   const Soa<R> oe = gbuf(C, 1 - bsel, 0), oi = gbuf(C, 1 - bsel, 1);
+  R* const we = WS ? C.wt[1 - bsel][0] : nullptr;
+  R* const wi = WS ? C.wt[1 - bsel][1] : nullptr;
   uint32_t pe = __builtin_amdgcn_readfirstlane(base_e) + pre_e;
   uint32_t pi = __builtin_amdgcn_readfirstlane(base_i) + pre_i;
   uint32_t werr = 0;
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < NE; ++j) {
     if (!(keep_e >> j & 1u)) continue;
 #pragma unroll
     for (int rep = 0; rep < 2; ++rep) {
@@ -1171,24 +1227,28 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
         oe.vy(s) = o.e[j].vy;
         oe.vz(s) = o.e[j].vz;
         oe.id(s) = rep ? clone_e[j] : o.e[j].id;
+        if (WS) we[s] = o.e[j].w;
       } else {
         werr |= ERR_CAPACITY;
       }
       ++pe;
     }
   }
-  if (keep_i) {
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    if (!(keep_i >> j & 1u)) continue;
 #pragma unroll
     for (int rep = 0; rep < 2; ++rep) {
-      if (rep == 1 && !clone_i) continue;
+      if (rep == 1 && !clone_i[j]) continue;
       if (pi < (uint32_t)P.cap_p) {
         const int64_t s = W.pbase + pi;
-        oi.cell(s) = o.i.cell;
-        oi.off(s) = o.i.off;
-        oi.vx(s) = o.i.vx;
-        oi.vy(s) = o.i.vy;
-        oi.vz(s) = o.i.vz;
-        oi.id(s) = rep ? clone_i : o.i.id;
+        oi.cell(s) = o.i[j].cell;
+        oi.off(s) = o.i[j].off;
+        oi.vx(s) = o.i[j].vx;
+        oi.vy(s) = o.i[j].vy;
+        oi.vz(s) = o.i[j].vz;
+        oi.id(s) = rep ? clone_i[j] : o.i[j].id;
+        if (WS) wi[s] = o.i[j].w;
       } else {
         werr |= ERR_CAPACITY;
       }
@@ -1200,18 +1260,25 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
 
 // Electron-neutral collision of a candidate (Sec. III, Sec. IV): channel by
 // the SLPIC rate of Eq. (16) or the fixed-event thresholds, then the scatter
-// law of the channel; ionization spawns an electron and an ion.
-template <typename R>
+// law of the channel; ionization spawns an electron and an ion.  With weight
+// splitting (WS and f_e < 1) the primary stays as the uncollided part with
+// the fraction 1 - f_e of its flux weight and its velocity, and the
+// scattered part and the products carry f_e (Sec. III: w_j,p0 = w_j,p1 +
+// W_j,c); the scattered part's id comes from channel CHILD, sub 2.
+template <typename R, bool WS>
 __device__ void collide_electron(const Ctx<R>& C, IP& P, int inst, uint32_t step,
-                                 Mk<R>& m, LaneOut<R>& o, uint32_t& ev, uint32_t& err) {
+                                 Mk<R>& m, LaneOut<R, WS>& o, uint32_t& ev, uint32_t& err) {
   const U4 r = draw(m.id, step, CH_COLL, C.seed, P.key);
   const R v2 = m.vx * m.vx + m.vy * m.vy + m.vz * m.vz;
   const R eps = v2 * (R)(0.5 * ME / QE);
+  const bool split = WS && P.f_e < 1.0;
   int ch = -1;
   if (C.fixed) {
-    const uint32_t u = r.x >> 9;
+    // whole markers: channel from the candidate's own word; split: from
+    // the second word, with probability fixed_k / (their sum)
+    const uint32_t u = (split ? r.y : r.x) >> 9;
     for (int q = 0; q < C.n_chan; ++q)
-      if (ch < 0 && u < P.t_fixed[q]) ch = q;
+      if (ch < 0 && u < (split ? P.t_fsplit[q] : P.t_fixed[q])) ch = q;
   } else {
     const R sp0 = Fm<R>::sqrt(v2);
     const R v0 = (R)P.v0;
@@ -1221,6 +1288,8 @@ __device__ void collide_electron(const Ctx<R>& C, IP& P, int inst, uint32_t step
     ch = select_channel(C, eps, (R)P.n_g * slow, unif<R>(r.y) * numax, cum);
     if (cum > numax * R(1.000001)) err |= ERR_NU_BOUND;
   }
+  o.e[0] = m;
+  o.me = 1u;
   if (ch >= 0) {
     // kind and threshold of the lane's channel, picked from the uniform
     // per-channel entries (no dependent per-lane load)
@@ -1258,7 +1327,21 @@ __device__ void collide_electron(const Ctx<R>& C, IP& P, int inst, uint32_t step
     else e1 = esc;
     turn(hx, hy, hz, chi, unif<R>(r.w), ox, oy, oz);
     const R sp1 = Fm<R>::sqrt(e1 * (R)(2.0 * QE / ME));
-    m.vx = sp1 * ox; m.vy = sp1 * oy; m.vz = sp1 * oz;
+    // the collided part: the marker itself, or with weight splitting a new
+    // marker beside the uncollided remainder
+    Mk<R> sc = m;
+    sc.vx = sp1 * ox; sc.vy = sp1 * oy; sc.vz = sp1 * oz;
+    if (split) {
+      const R f = (R)P.f_e;
+      const U4 sid = draw_cold(m.id, step, CH_CHILD | (2u << 8), C.seed, P.key);
+      sc.id = child(sid.x, sid.y);
+      sc.w = m.w * f;
+      o.e[0].w = m.w * (R)P.g_e;
+      o.e[1] = sc;
+      o.me = 3u;
+    } else {
+      o.e[0] = sc;
+    }
     ev |= 1u << (kind == 0 ? EV_ELASTIC : (kind == 1 ? EV_EXCIT : EV_IONIZ));
     if (ioniz) {
       // the ejected electron and the ion at the primary's position
@@ -1270,23 +1353,30 @@ __device__ void collide_electron(const Ctx<R>& C, IP& P, int inst, uint32_t step
       Mk<R> e2 = m;
       e2.vx = spj * jx; e2.vy = spj * jy; e2.vz = spj * jz;
       e2.id = child(cid.x, cid.y);
+      e2.w = sc.w;
       Mk<R> i2 = m;
       normals3<R>(b, (R)P.vth_i, i2.vx, i2.vy, i2.vz);
       i2.id = child(cid.z, cid.w);
-      o.e[1] = e2;
-      o.i = i2;
+      i2.w = sc.w;
+      if (split) {
+        o.e[LaneOut<R, WS>::NE - 1] = e2;
+        o.me |= 4u;
+      } else {
+        o.e[1] = e2;
+        o.me |= 2u;
+      }
+      o.i[0] = i2;
       o.mi = 1u;
     }
   }
-  o.e[0] = m;
-  o.me = o.mi ? 3u : 1u;
 }
 
 // Ar+ charge exchange of a candidate: the ion takes a neutral's thermal
-// velocity.
-template <typename R>
+// velocity (with weight splitting, a new ion of the fraction f_cx of its
+// flux weight does, beside the uncollided remainder).
+template <typename R, bool WS>
 __device__ void collide_ion(const Ctx<R>& C, IP& P, int inst, uint32_t step,
-                            Mk<R>& m, LaneOut<R>& o, uint32_t& ev, uint32_t& err) {
+                            Mk<R>& m, LaneOut<R, WS>& o, uint32_t& ev, uint32_t& err) {
   bool hit = true;  // fixed-event candidates always exchange
   if (!C.fixed) {
     const U4 r = draw(m.id, step, CH_CX, C.seed, P.key);
@@ -1299,27 +1389,39 @@ __device__ void collide_ion(const Ctx<R>& C, IP& P, int inst, uint32_t step,
     if (nu > numax * R(1.000001)) err |= ERR_NU_BOUND;
     hit = unif<R>(r.y) * numax < nu;
   }
+  o.i[0] = m;
+  o.mi = 1u;
   if (hit) {
     const U4 b = draw_cold(m.id, step, CH_CX | (1u << 8), C.seed, P.key);
-    normals3<R>(b, (R)P.vth_i, m.vx, m.vy, m.vz);
+    Mk<R> sc = m;
+    normals3<R>(b, (R)P.vth_i, sc.vx, sc.vy, sc.vz);
+    if (WS && P.f_cx < 1.0) {
+      const R f = (R)P.f_cx;
+      const U4 sid = draw_cold(m.id, step, CH_CHILD | (2u << 8), C.seed, P.key);
+      sc.id = child(sid.x, sid.y);
+      sc.w = m.w * f;
+      o.i[0].w = m.w * (R)P.g_cx;
+      o.i[WS ? 1 : 0] = sc;
+      o.mi = 3u;
+    } else {
+      o.i[0] = sc;
+    }
     ev |= 1u << EV_CX;
   }
-  o.i = m;
-  o.mi = 1u;
 }
 
 // One marker of a tile: gather at x^n, null-collision draw, flight, walls
 // and emission.  A collision candidate sets cand and produces nothing yet;
 // otherwise the marker, or the electron its cathode impact emits, becomes
 // the lane's output.
-template <typename R, int MODE>
+template <typename R, int MODE, bool WS>
 __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp,
                                         uint32_t g, uint32_t step, bool valid, Mk<R>& m,
-                                        LaneOut<R>& o, uint32_t& ev, uint32_t& err, bool& cand) {
+                                        LaneOut<R, WS>& o, uint32_t& ev, uint32_t& err, bool& cand) {
   if (!valid) return;
   if (MODE == MODE_REFRESH) {
     if (sp == 0) { o.e[0] = m; o.me = 1u; }
-    else { o.i = m; o.mi = 1u; }
+    else { o.i[0] = m; o.mi = 1u; }
     return;
   }
   // the null-collision draw does not depend on the field and overlaps the
@@ -1381,6 +1483,7 @@ __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp
         e.off = R(0);
         e.vx = e.vy = e.vz = R(0);
         e.id = child(r.z, r.w);
+        e.w = m.w;  // the ion's flux weight (Sec. III: products carry it)
         o.e[0] = e;
         o.me = 1u;
       }
@@ -1394,12 +1497,12 @@ __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp
     // null-collision test: candidates go to the queue
     const uint32_t u = rnx >> 9;
     uint32_t tcand;
-    if (C.fixed) tcand = sp == 0 ? (C.n_chan > 0 ? P.t_fixed[C.n_chan - 1] : 0u) : P.t_fixed_cx;
+    if (C.fixed) tcand = sp == 0 ? P.t_cand_fixed_e : P.t_fixed_cx;
     else tcand = sp == 0 ? P.t_null_e : (P.sigma_cx > 0.0 ? P.t_null_cx : 0u);
     cand = u < tcand;
     if (!cand) {
       if (sp == 0) { o.e[0] = m; o.me = 1u; }
-      else { o.i = m; o.mi = 1u; }
+      else { o.i[0] = m; o.mi = 1u; }
     }
   }
 }
@@ -1415,7 +1518,7 @@ __device__ __forceinline__ const void* kernarg_base() {
 #endif
 }
 
-template <typename R, int MODE>
+template <typename R, int MODE, bool WS>
 __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 5 : 1) k_gen(Ctx<R> C_arg) {
   (void)C_arg;
   const Ctx<R>& C = *reinterpret_cast<const Ctx<R>*>(kernarg_base());
@@ -1429,6 +1532,7 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 5 : 1) k_gen(Ctx<R> C_
   __shared__ int32_t q_cell[NWAVE][QW];
   __shared__ R q_off[NWAVE][QW], q_vx[NWAVE][QW], q_vy[NWAVE][QW], q_vz[NWAVE][QW];
   __shared__ uint64_t q_id[NWAVE][QW];
+  __shared__ R q_w[WS ? NWAVE : 1][WS ? QW : 1];  // flux weights (weight splitting)
 
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   // the generation to advance from: set by the previous tail kernel, and
@@ -1458,14 +1562,14 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 5 : 1) k_gen(Ctx<R> C_
   const uint32_t per = (n_tiles + (uint32_t)C.grid - 1) / (uint32_t)C.grid;
   const uint32_t t_begin = blockIdx.x * per, t_end = min(n_tiles, t_begin + per);
   DepWin win{-1, 0};
-  Work W{-1, -1, 0, 0u, POP_NONE, 0, 0u};
+  Work W{-1, -1, 0, 0u, POP_NONE, 0, 0, 0u};
   uint32_t q_head = 0, q_count = 0;  // uniform over the wave
   uint32_t* evw = s_evw[wv];          // event counts of this wave since the last flush
   const unsigned long long lt = (1ull << lane) - 1ull;
 
   // collide up to WAVE queued candidates and emit the results
   auto run_queue = [&](uint32_t n) {
-    LaneOut<R> o;
+    LaneOut<R, WS> o;
     o.me = o.mi = 0u;
     uint32_t ev = 0, err = 0;
     // the appends of other lanes land before these reads (one wave: LDS
@@ -1480,6 +1584,7 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 5 : 1) k_gen(Ctx<R> C_
       m.vy = q_vy[wv][s];
       m.vz = q_vz[wv][s];
       m.id = q_id[wv][s];
+      m.w = WS ? q_w[WS ? wv : 0][WS ? s : 0] : R(1);
       IP& P = param(C.ip, W.inst);
       if (W.sp == 0) collide_electron(C, P, W.inst, W.step, m, o, ev, err);
       else collide_ion(C, P, W.inst, W.step, m, o, ev, err);
@@ -1488,7 +1593,7 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 5 : 1) k_gen(Ctx<R> C_
     q_head = ring(q_head, n);
     q_count -= n;
     next_output(W, param(C.ip, W.inst));
-    emit<R, MODE, true>(C, W, win, s_hist, o, ev, err, g, bsel, evw);
+    emit<R, MODE, true, WS>(C, W, win, s_hist, o, ev, err, g, bsel, evw);
   };
   // append marker m to the queue at offset off (< QW) past its head
   auto q_put = [&](const Mk<R>& m, uint32_t off) {
@@ -1499,6 +1604,7 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 5 : 1) k_gen(Ctx<R> C_
     q_vy[wv][s] = m.vy;
     q_vz[wv][s] = m.vz;
     q_id[wv][s] = m.id;
+    if (WS) q_w[WS ? wv : 0][WS ? s : 0] = m.w;
   };
 
   // One tile at a time, one marker per lane: a single marker's registers
@@ -1534,6 +1640,7 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 5 : 1) k_gen(Ctx<R> C_
       W.sp = sp;
       W.step = S0.step;
       W.pop = MODE == MODE_STEP ? S0.popmode : POP_NONE;
+      W.dshift = MODE == MODE_STEP ? S0.dshift : C.dep_shift;
     }
     const Soa<R> in = gbuf(C, bsel, sp);
 
@@ -1547,12 +1654,13 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 5 : 1) k_gen(Ctx<R> C_
       m.vy = in.vy(s);
       m.vz = in.vz(s);
       m.id = in.id(s);
+      m.w = WS ? C.wt[bsel][sp][s] : R(1);
     }
-    LaneOut<R> o;
+    LaneOut<R, WS> o;
     o.me = o.mi = 0u;
     uint32_t ev = 0, err = 0;
     bool cand = false;
-    advance<R, MODE>(C, P, inst, sp, g, W.step, idx < n, m, o, ev, err, cand);
+    advance<R, MODE, WS>(C, P, inst, sp, g, W.step, idx < n, m, o, ev, err, cand);
     if (MODE == MODE_STEP) {
       // append the wave's candidates to its queue (fewer than WAVE wait)
       const unsigned long long b = __ballot(cand);
@@ -1560,7 +1668,7 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 5 : 1) k_gen(Ctx<R> C_
       q_count += (uint32_t)__popcll(b);
     }
     next_output(W, P);
-    emit<R, MODE, false>(C, W, win, s_hist, o, ev, err, g, bsel, evw);
+    emit<R, MODE, false, WS>(C, W, win, s_hist, o, ev, err, g, bsel, evw);
     while (MODE == MODE_STEP && q_count >= (uint32_t)WAVE) run_queue((uint32_t)WAVE);
   }
   while (q_count > 0) run_queue(q_count < (uint32_t)WAVE ? q_count : (uint32_t)WAVE);
@@ -1729,6 +1837,7 @@ __global__ void __launch_bounds__(BLOCK) k_sort_scatter(Ctx<R> C) {
         out.vy(d) = in.vy(s);
         out.vz(d) = in.vz(s);
         out.id(d) = in.id(s);
+        if (C.split) C.wt[1u - bsel][sp][d] = C.wt[bsel][sp][s];
       }
     }
     __syncthreads();
@@ -1777,6 +1886,7 @@ __global__ void k_seed(Ctx<R> C, int inst, int mode, int64_t n, double sigma_v, 
   const int64_t s = P.seg + (k % P.parts) * P.cap_p + k / P.parts;
   o.id(s) = (uint64_t)k;
   o.cell(s) = 0;
+  if (C.split) C.wt[bsel][0][s] = R(1);
   if (mode == 2) {
     const U4 r0 = draw((uint64_t)k, 0u, CH_SEED, C.seed, P.key);
     const U4 r1 = draw((uint64_t)k, 0u, CH_SEED | (1u << 8), C.seed, P.key);
@@ -1808,10 +1918,17 @@ __global__ void k_philox_test(const uint32_t* ctr, uint32_t k0, uint32_t k1, int
 // ---------------------------------------------------------------- launchers
 template <typename R>
 hipError_t launch_particles(const Ctx<R>& C, int mode, hipStream_t s) {
-  if (mode == MODE_STEP)
-    hipLaunchKernelGGL((k_gen<R, MODE_STEP>), dim3(C.grid), dim3(BLOCK), C.gen_lds, s, C);
-  else
-    hipLaunchKernelGGL((k_gen<R, MODE_REFRESH>), dim3(C.grid), dim3(BLOCK), C.gen_lds, s, C);
+  if (C.split) {
+    if (mode == MODE_STEP)
+      hipLaunchKernelGGL((k_gen<R, MODE_STEP, true>), dim3(C.grid), dim3(BLOCK), C.gen_lds, s, C);
+    else
+      hipLaunchKernelGGL((k_gen<R, MODE_REFRESH, true>), dim3(C.grid), dim3(BLOCK), C.gen_lds, s, C);
+  } else {
+    if (mode == MODE_STEP)
+      hipLaunchKernelGGL((k_gen<R, MODE_STEP, false>), dim3(C.grid), dim3(BLOCK), C.gen_lds, s, C);
+    else
+      hipLaunchKernelGGL((k_gen<R, MODE_REFRESH, false>), dim3(C.grid), dim3(BLOCK), C.gen_lds, s, C);
+  }
   return hipGetLastError();
 }
 
@@ -1846,9 +1963,11 @@ hipError_t launch_seed(const Ctx<R>& C, int inst, int mode, int64_t n, double si
 }
 
 template <typename R>
-hipError_t occupancy_gen(int* blocks_per_cu, size_t dyn_lds) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_gen<R, MODE_STEP>, BLOCK,
-                                                      dyn_lds);
+hipError_t occupancy_gen(int* blocks_per_cu, size_t dyn_lds, bool split) {
+  return split ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_gen<R, MODE_STEP, true>,
+                                                              BLOCK, dyn_lds)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_gen<R, MODE_STEP, false>,
+                                                              BLOCK, dyn_lds);
 }
 
 template hipError_t launch_particles<float>(const Ctx<float>&, int, hipStream_t);
@@ -1861,8 +1980,8 @@ template hipError_t launch_seed<float>(const Ctx<float>&, int, int, int64_t, dou
                                        hipStream_t);
 template hipError_t launch_seed<double>(const Ctx<double>&, int, int, int64_t, double, uint32_t,
                                         hipStream_t);
-template hipError_t occupancy_gen<float>(int*, size_t);
-template hipError_t occupancy_gen<double>(int*, size_t);
+template hipError_t occupancy_gen<float>(int*, size_t, bool);
+template hipError_t occupancy_gen<double>(int*, size_t, bool);
 
 hipError_t launch_philox_test(const uint32_t* ctr, uint32_t k0, uint32_t k1, int64_t n,
                               uint32_t* out, hipStream_t s) {

@@ -13,7 +13,7 @@ def speed(p):
 
 
 def compare_populations(gpu, ref, tol_x_cells, tol_v, v_scale, tie_tol=None,
-                        label="", max_tied=None):
+                        label="", max_tied=None, tol_w=None):
     """Compare two populations keyed by id.
 
     Without tie_tol the id sets must be identical.  With tie_tol, oracle
@@ -75,6 +75,11 @@ def compare_populations(gpu, ref, tol_x_cells, tol_v, v_scale, tie_tol=None,
                       "n_bad": int(np.sum(ev > tol_v))}
             raise AssertionError(f"{label}: {k} error {ev.max():.3e} > {tol_v:.1e} {detail}")
     worst["v_errors"] = per_marker
+    if tol_w is not None:
+        # flux weights (weight splitting), relative
+        ew = np.abs(g["w"][gi] - r["w"][ri]) / r["w"][ri]
+        worst["w"] = float(ew.max()) if ew.size else 0.0
+        assert np.all(ew <= tol_w), f"{label}: weight error {ew.max():.3e} > {tol_w:.1e}"
     return worst
 
 

@@ -112,3 +112,23 @@ def test_create_without_a_device_fails_loudly():
         pytest.skip("a device is present")
     with pytest.raises(slpic.SlpicError):
         slpic.Sim(configs.c1().instances, configs.c1().run, synth.argon_like())
+
+
+def test_split_fraction_is_validated(built, xs_argon):
+    import dataclasses
+    w = configs.c1()
+    for s, flags, ok in ((0.0, 0, True), (0.5, 0, True), (1.0, 0, True),
+                         (1.5, 0, False), (-0.1, 0, False), (float("nan"), 0, False),
+                         (0.5, slpic.FLAG_FLUX, False), (1.0, slpic.FLAG_FLUX, True)):
+        run = dataclasses.replace(w.run, split_frac=s)
+        cfg = slpic.make_config(run, flags)
+        arr = slpic.make_instances(w.instances)
+        x = slpic._Xs(xs_argon)
+        n = built.slpic_workspace_bytes(C.byref(cfg), arr, 1, C.byref(x.c))
+        assert (n > 0) == ok, (s, flags)
+    # weights take one more value per marker slot
+    r0 = dataclasses.replace(w.run, split_frac=0.0)
+    r1 = dataclasses.replace(w.run, split_frac=0.5)
+    n0 = _ws(built, w.instances, r0, xs_argon)
+    n1 = _ws(built, w.instances, r1, xs_argon)
+    assert n1 > n0
