@@ -14,7 +14,8 @@ Prints one JSON line:
   value       particle-steps/s = sum over timed steps and instances of the
               markers entering the step, over the wall time of the steps,
               replayed from the captured HIP graph (16 steps per graph;
-              captured before the timed region)
+              captured before the timed region), in the launch shape the
+              autotuner picks on a separate copy of the workload
   roofline    particle kernel: 56 algorithmic bytes per marker-step (28-byte
               record read + 28-byte record written) over its average
               HIP-event duration, against 8 TB/s, from the same number of
@@ -247,6 +248,63 @@ def pic_leg(xs):
     return out
 
 
+def size_class(inst):
+    """Size class of an instance: marker target (<= 1e5, <= 1e6, above)
+    times cells (<= 1024, above)."""
+    m = 0 if inst.n_target <= 1e5 else (1 if inst.n_target <= 1e6 else 2)
+    return 2 * m + (0 if inst.cells <= 1024 else 1)
+
+
+def tuned_shape(w, xs, trial_steps=2):
+    """Launch shape the autotuner picks for a workload, on a handle of its
+    own (its trial steps advance that handle only)."""
+    import paper_2103_12194_amd as slpic
+    sim = slpic.Sim(w.instances, w.run, xs)
+    sim.autotune(trial_steps)
+    shape = sim.launch_shape()
+    sim.close()
+    return shape
+
+
+def per_class_leg(w, xs, warm, steps):
+    """The bisection round split into one handle per size class, each with
+    its autotuned launch shape, every instance on its batch index's Philox
+    stream (so each repeats its draws in the single handle): the classes'
+    steps are enqueued on their handles' own streams and run concurrently."""
+    import dataclasses
+    import torch
+    import paper_2103_12194_amd as slpic
+    from synth import configs
+    groups = {}
+    for k, inst in enumerate(w.instances):
+        groups.setdefault(size_class(inst), []).append(dataclasses.replace(inst, stream=k))
+    sims, shapes = [], {}
+    for c, insts in sorted(groups.items()):
+        sub = configs.Workload(f"class {c}", w.run, insts, w.steps)
+        shape = tuned_shape(sub, xs)
+        sim = slpic.Sim(insts, w.run, xs)
+        sim.set_launch_shape(*shape)
+        sim.step(warm)
+        sims.append(sim)
+        shapes[str(c)] = {"instances": len(insts), "grid": shape[0], "waves_per_simd": shape[1]}
+    for sim in sims:
+        sim.sync()
+    torch.cuda.synchronize()
+    s0 = [sim.steps_done() for sim in sims]
+    t0 = time.perf_counter()
+    for sim in sims:
+        sim.step(steps)
+    for sim in sims:
+        sim.sync()
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    ps = sum(history_total(sim, a, steps) for sim, a in zip(sims, s0))
+    for sim in sims:
+        sim.close()
+    return {"value": ps / secs, "unit": "particle-steps/s", "ms_per_step": secs * 1e3 / steps,
+            "classes": shapes}
+
+
 def configs_leg(xs):
     """Throughput of the other workloads, each from its seeded state after a
     warmup that lets its population settle: (name, workload, warmup,
@@ -277,6 +335,11 @@ def configs_leg(xs):
               f"{gen_ms / nk:.3f} ms, {ps / steps:.3e} markers/step", file=sys.stderr, flush=True)
         sim.close()
         del sim
+        if name.startswith("C5"):
+            pc = per_class_leg(w, xs, warm, steps)
+            out[name]["per_size_class_autotuned"] = pc
+            print(f"# {name}, one handle per size class, autotuned: {pc['value']:.3e} "
+                  f"particle-steps/s {pc['classes']}", file=sys.stderr, flush=True)
     return out
 
 
@@ -302,7 +365,14 @@ def main():
     print(f"# {w.name}: {len(w.instances)} instances, "
           f"{sum(i.n_target for i in w.instances):.3e} target markers", file=sys.stderr, flush=True)
 
+    # launch shape: autotuned on a copy of the workload, so that the timed
+    # handle takes exactly the warmup steps asked for
+    shape = tuned_shape(w, xs)
+    print(f"# autotuned launch shape: grid {shape[0]}, {shape[1]} waves per SIMD",
+          file=sys.stderr, flush=True)
     sim = slpic.Sim(w.instances, w.run, xs)
+    default_shape = sim.launch_shape()
+    sim.set_launch_shape(*shape)
     sim.step(args.warmup)
     sim.sync()
     print(f"# warmup {args.warmup} steps done", file=sys.stderr, flush=True)
@@ -371,6 +441,9 @@ def main():
                    "n_inst": len(w.instances), "marker_scale": args.scale,
                    "markers_per_step": n_markers, "parallelism": "none (1 GPU)"},
         "roofline": roofline, "plain": plain, "eager": eager,
+        "launch_shape": {"grid": shape[0], "waves_per_simd": shape[1], "autotuned": True,
+                         "default": {"grid": default_shape[0],
+                                     "waves_per_simd": default_shape[1]}},
         "cpu_baseline": cpu,
     }
     if pic is not None:

@@ -225,15 +225,31 @@ int slpic_sync(slpic_t* h);
 int slpic_use_graph(slpic_t* h, int enable);
 
 /* Launch shape.  The particle kernel runs on a grid of workgroups that each
- * take a contiguous run of 256-marker tiles; results do not depend on the
- * grid (random numbers are keyed by marker id and step, deposits are exact
+ * take a contiguous run of 256-marker tiles; the FP32 whole-marker kernel
+ * also comes in two register budgets, compiled for 4 or 5 (the default)
+ * waves per SIMD.  Results do not depend on the grid or the budget
+ * (random numbers are keyed by marker id and step, deposits are exact
  * fixed-point sums), only the time does.  slpic_autotune times trial_steps
- * steps (after one untimed step) on each candidate grid -- a quarter, half
- * and all of the compute units, and 1 .. the resident maximum workgroups per
- * compute unit -- keeps the fastest and writes it to *grid (host, may be
- * NULL).  The trial steps are ordinary steps of the simulation and count in
+ * steps (after one untimed step) for each candidate shape -- every budget
+ * with grids of a quarter, half and all of the compute units and 1 .. the
+ * resident maximum workgroups per compute unit -- in three interleaved
+ * rounds, keeps the candidate with the smallest median time and writes its
+ * grid to *grid (host, may be NULL).  Tuning a handle per size class of
+ * instances (marker count x cells) tunes each class's shape.  The trial
+ * steps are ordinary steps of the simulation and count in
  * slpic_steps_done.  Synchronizes; drops a captured graph. */
 int slpic_autotune(slpic_t* h, int trial_steps, int* grid);
+
+/* Current launch shape (host outputs): the particle-kernel grid and the
+ * waves per SIMD of its register budget (0 where the handle has one
+ * kernel only: FP64 or weight splitting). */
+int slpic_launch_shape(slpic_t* h, int* grid, int* waves_per_simd);
+
+/* Set the launch shape (as chosen by slpic_autotune, e.g. on another handle
+ * of the same size class): grid >= 1 (capped at the tile count), waves per
+ * SIMD 4 or 5 for FP32 whole markers, 0 otherwise; else SLPIC_INVALID_ARG.
+ * Synchronizes; drops a captured graph. */
+int slpic_set_launch_shape(slpic_t* h, int grid, int waves_per_simd);
 
 /* Current particle-kernel grid (host output). */
 int slpic_grid(slpic_t* h, int* grid);

@@ -80,7 +80,8 @@ EXPORTS = ["slpic_workspace_bytes", "slpic_create", "slpic_create_static", "slpi
            "slpic_scalars", "slpic_steps_done", "slpic_last_error",
            "slpic_destroy", "slpic_philox_device", "slpic_profile",
            "slpic_kernel_times", "slpic_partitions", "slpic_autotune",
-           "slpic_grid", "slpic_sort", "slpic_read_weights"]
+           "slpic_grid", "slpic_sort", "slpic_read_weights", "slpic_launch_shape",
+           "slpic_set_launch_shape"]
 
 
 def lib():
@@ -119,6 +120,8 @@ def lib():
         L.slpic_autotune.argtypes = [vp, i32, P(i32)]
         L.slpic_sort.argtypes = [vp]
         L.slpic_grid.argtypes = [vp, P(i32)]
+        L.slpic_launch_shape.argtypes = [vp, P(i32), P(i32)]
+        L.slpic_set_launch_shape.argtypes = [vp, i32, i32]
         L.slpic_partitions.argtypes = [vp, i32, i32, P(C.c_int32), P(i64), vp]
         L.slpic_kernel_times.argtypes = [vp, P(C.c_double), P(C.c_double), P(i64)]
         L.slpic_philox_device.argtypes = [vp, C.c_uint32, C.c_uint32, i64, vp, vp]
@@ -263,6 +266,15 @@ class Sim:
         g = C.c_int()
         _check(lib().slpic_grid(self.h, C.byref(g)), self.h)
         return int(g.value)
+
+    def launch_shape(self):
+        """(particle-kernel grid, waves per SIMD of its register budget)."""
+        g, w = C.c_int(), C.c_int()
+        _check(lib().slpic_launch_shape(self.h, C.byref(g), C.byref(w)), self.h)
+        return g.value, w.value
+
+    def set_launch_shape(self, grid, waves_per_simd):
+        _check(lib().slpic_set_launch_shape(self.h, int(grid), int(waves_per_simd)), self.h)
 
     def profile(self, enable=True):
         """Record per-kernel HIP events around the following steps."""

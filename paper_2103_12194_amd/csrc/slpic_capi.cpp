@@ -20,7 +20,7 @@ template <typename R> hipError_t launch_particles(const Ctx<R>&, int, hipStream_
 template <typename R> hipError_t launch_tail(const Ctx<R>&, int, hipStream_t);
 template <typename R>
 hipError_t launch_seed(const Ctx<R>&, int, int, int64_t, double, uint32_t, hipStream_t);
-template <typename R> hipError_t occupancy_gen(int*, size_t, bool);
+template <typename R> hipError_t occupancy_gen(int*, size_t, bool, int);
 // dynamic LDS of the particle kernel: tile offsets of the (instance,
 // species) pairs
 inline size_t gen_lds_bytes(int n_inst) { return ((size_t)(2 * n_inst + 1) * 4 + 15) & ~size_t(15); }
@@ -317,6 +317,8 @@ struct slpic_handle {
   Ctx<double> c64;
   int grid = 0;
   int cus = 0, occ_per_cu = 0;  // compute units; resident particle workgroups per CU
+  int occ = 5;                  // launch shape: waves per SIMD of the FP32 particle kernel
+  int blocks_at[7] = {0, 0, 0, 0, 0, 0, 0};  // resident workgroups per CU for each shape
   uint64_t gen = 0;      // generation launches issued
   int64_t steps = 0;
   bool use_graph = false;
@@ -380,6 +382,7 @@ void fill_ctx(slpic_t* h, Ctx<R>& C) {
   C.flux = reinterpret_cast<double*>(w + L.flux);
   C.g = reinterpret_cast<Global*>(w + L.glob);
   C.split = splitting(&h->cfg) ? 1 : 0;
+  C.occ = h->occ;
   for (int b = 0; b < 2; ++b)
     for (int s = 0; s < 2; ++s) C.wt[b][s] = C.split ? reinterpret_cast<R*>(w + L.wt[b][s]) : nullptr;
   C.xs_e = reinterpret_cast<const R*>(w + L.xs_e);
@@ -733,8 +736,14 @@ int create_impl(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess)
-    e = cfg->precision == 64 ? occupancy_gen<double>(&per_cu, gen_lds_bytes(n_inst), splitting(cfg))
-                             : occupancy_gen<float>(&per_cu, gen_lds_bytes(n_inst), splitting(cfg));
+    e = cfg->precision == 64 ? occupancy_gen<double>(&per_cu, gen_lds_bytes(n_inst), splitting(cfg), 5)
+                             : occupancy_gen<float>(&per_cu, gen_lds_bytes(n_inst), splitting(cfg), 5);
+  // the other launch shapes of the FP32 whole-marker kernel (autotuner)
+  for (int oc = 4; oc <= 5 && e == hipSuccess; ++oc) {
+    int b = 0;
+    if (cfg->precision == 32 && !splitting(cfg)) e = occupancy_gen<float>(&b, gen_lds_bytes(n_inst), false, oc);
+    h->blocks_at[oc] = oc == 5 ? per_cu : b;
+  }
   if (e != hipSuccess) {
     int rc = hip_fail(nullptr, e, "device query");
     delete h;
@@ -936,14 +945,18 @@ int slpic_step(slpic_t* h, int n_steps) {
   return SLPIC_OK;
 }
 
-// Changes the particle-kernel grid between steps.  Kernels read the
-// generation from device words, so only the launch shape changes; a
-// captured graph holds the old grid and is dropped.
-static int set_grid(slpic_t* h, int grid) {
+// Changes the particle kernel's launch shape (waves per SIMD of its
+// register budget) and grid between steps.  Kernels read the generation
+// from device words, so only the launch changes; a captured graph holds the
+// old shape and is dropped.
+static int set_shape(slpic_t* h, int occ, int grid) {
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->grid = grid;
+  h->occ = occ;
   h->c32.grid = grid;
   h->c64.grid = grid;
+  h->c32.occ = occ;
+  h->c64.occ = occ;
   if (h->graph) {
     (void)hipGraphExecDestroy(h->graph);
     h->graph = nullptr;
@@ -959,13 +972,26 @@ int slpic_grid(slpic_t* h, int* grid) {
 
 int slpic_autotune(slpic_t* h, int trial_steps, int* grid) {
   if (!h || trial_steps < 1 || h->profiling) return fail(h, SLPIC_INVALID_ARG, "bad autotune arguments");
-  std::vector<int> cand;
-  auto add = [&](int g) {
-    g = std::max(1, std::min(g, h->L.max_tiles));
-    if (std::find(cand.begin(), cand.end(), g) == cand.end()) cand.push_back(g);
+  // candidates: launch shapes (the FP32 whole-marker kernel comes in two
+  // register budgets) times grids (a quarter, half and all of the compute
+  // units, then 1 .. the resident maximum workgroups per compute unit)
+  struct Cand {
+    int occ, grid;
   };
-  for (int q = 4; q >= 1; q /= 2) add(h->cus / q);
-  for (int pc = 1; pc <= h->occ_per_cu; ++pc) add(h->cus * pc);
+  std::vector<Cand> cand;
+  auto add = [&](int oc, int g) {
+    g = std::max(1, std::min(g, h->L.max_tiles));
+    for (const Cand& c : cand)
+      if (c.occ == oc && c.grid == g) return;
+    cand.push_back(Cand{oc, g});
+  };
+  const bool shapes = h->cfg.precision == 32 && !splitting(&h->cfg);
+  for (int oc : {5, 4}) {
+    if (oc != 5 && !shapes) continue;
+    const int per_cu = std::max(1, h->blocks_at[oc]);
+    for (int q = 4; q >= 1; q /= 2) add(oc, h->cus / q);
+    for (int pc = 1; pc <= per_cu; ++pc) add(oc, h->cus * pc);
+  }
   hipEvent_t e0, e1;
   HIPCHK(h, hipEventCreate(&e0));
   hipError_t er = hipEventCreate(&e1);
@@ -973,32 +999,60 @@ int slpic_autotune(slpic_t* h, int trial_steps, int* grid) {
     (void)hipEventDestroy(e0);
     return hip_fail(h, er, "hipEventCreate");
   }
-  int best = h->grid, rc = SLPIC_OK;
-  float best_ms = 0.0f;
-  for (size_t c = 0; c < cand.size() && rc == SLPIC_OK; ++c) {
-    rc = set_grid(h, cand[c]);
-    // one untimed step on the new grid, then the timed ones
-    for (int k = 0; k <= trial_steps && rc == SLPIC_OK; ++k) {
-      if (k == 1 && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(h, SLPIC_HIP_ERROR, "event");
-      if (rc == SLPIC_OK) rc = launch_gen_any(h, MODE_STEP);
-      if (rc == SLPIC_OK) h->steps += 1;
-    }
-    float ms = 0.0f;
-    if (rc == SLPIC_OK && (hipEventRecord(e1, h->stream) != hipSuccess ||
-                           hipEventSynchronize(e1) != hipSuccess ||
-                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-      rc = fail(h, SLPIC_HIP_ERROR, "autotune timing");
-    if (rc == SLPIC_OK && (c == 0 || ms < best_ms)) {
-      best_ms = ms;
-      best = cand[c];
+  // three rounds over all candidates, so that the population's drift
+  // between trials spreads over every candidate; each keeps its median
+  constexpr int kRounds = 3;
+  std::vector<std::vector<float>> times(cand.size());
+  int rc = SLPIC_OK;
+  for (int round = 0; round < kRounds && rc == SLPIC_OK; ++round) {
+    for (size_t c = 0; c < cand.size() && rc == SLPIC_OK; ++c) {
+      rc = set_shape(h, cand[c].occ, cand[c].grid);
+      // one untimed step in the new shape, then the timed ones
+      for (int k = 0; k <= trial_steps && rc == SLPIC_OK; ++k) {
+        if (k == 1 && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(h, SLPIC_HIP_ERROR, "event");
+        if (rc == SLPIC_OK) rc = launch_gen_any(h, MODE_STEP);
+        if (rc == SLPIC_OK) h->steps += 1;
+      }
+      float ms = 0.0f;
+      if (rc == SLPIC_OK && (hipEventRecord(e1, h->stream) != hipSuccess ||
+                             hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = fail(h, SLPIC_HIP_ERROR, "autotune timing");
+      if (rc == SLPIC_OK) times[c].push_back(ms);
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  rc = set_grid(h, best);
-  if (rc == SLPIC_OK && grid) *grid = best;
+  size_t best = 0;
+  float best_ms = 0.0f;
+  for (size_t c = 0; c < cand.size(); ++c) {
+    std::vector<float> t = times[c];
+    std::sort(t.begin(), t.end());
+    const float med = t[t.size() / 2];
+    if (c == 0 || med < best_ms) {
+      best_ms = med;
+      best = c;
+    }
+  }
+  rc = set_shape(h, cand[best].occ, cand[best].grid);
+  if (rc == SLPIC_OK && grid) *grid = cand[best].grid;
   return rc;
+}
+
+int slpic_set_launch_shape(slpic_t* h, int grid, int waves_per_simd) {
+  if (!h || grid < 1 || h->profiling) return fail(h, SLPIC_INVALID_ARG, "bad launch shape");
+  const bool shapes = h->cfg.precision == 32 && !splitting(&h->cfg);
+  if (shapes ? (waves_per_simd != 4 && waves_per_simd != 5) : waves_per_simd != 0)
+    return fail(h, SLPIC_INVALID_ARG, "waves per SIMD must be 4 or 5 (FP32 whole markers), else 0");
+  return set_shape(h, shapes ? waves_per_simd : h->occ, std::min(grid, h->L.max_tiles));
+}
+
+int slpic_launch_shape(slpic_t* h, int* grid, int* waves_per_simd) {
+  if (!h || !grid || !waves_per_simd) return fail(h, SLPIC_INVALID_ARG, "null shape output");
+  *grid = h->grid;
+  *waves_per_simd = h->cfg.precision == 32 && !splitting(&h->cfg) ? h->occ : 0;
+  return SLPIC_OK;
 }
 
 int slpic_profile(slpic_t* h, int enable) {

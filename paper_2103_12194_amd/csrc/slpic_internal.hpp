@@ -189,6 +189,8 @@ struct Ctx {
   R* wt[2][2];               // [buffer][species] flux weight of each marker slot
                              // in units of w_j (weight splitting only, else NULL)
   int split;                 // weight splitting (split fraction in (0, 1))
+  int occ;                   // waves per SIMD of the FP32 particle kernel's
+                             // launch shape (4, 5 or 6)
   int sort_lds1, sort_lds2;  // dynamic LDS bytes of the sort's count and scatter
 };
 

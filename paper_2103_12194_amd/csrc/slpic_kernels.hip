@@ -1143,7 +1143,8 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
   // linear weights, times its flux weight with weight splitting, to the LDS
   // window (clones count twice)
   {
-    const int shift = W.dshift;
+    // whole markers always use the base shift
+    const int shift = WS ? W.dshift : C.dep_shift;
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
       if (!(keep_e >> q & 1u)) continue;
@@ -1518,8 +1519,12 @@ __device__ __forceinline__ const void* kernarg_base() {
 #endif
 }
 
-template <typename R, int MODE, bool WS>
-__global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 5 : 1) k_gen(Ctx<R> C_arg) {
+// OCC: waves per SIMD the FP32 kernel is compiled for (its register budget:
+// 4 or 5; the LDS of a workgroup allows at most 5 per compute unit), one of
+// the launch shapes an autotuner chooses between.  Results do not depend on
+// it, only the register allocation does.
+template <typename R, int MODE, bool WS, int OCC>
+__global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> C_arg) {
   (void)C_arg;
   const Ctx<R>& C = *reinterpret_cast<const Ctx<R>*>(kernarg_base());
   extern __shared__ uint32_t s_prefix[];  // 2 n_inst + 1 tile offsets (dynamic)
@@ -1640,7 +1645,7 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? 5 : 1) k_gen(Ctx<R> C_
       W.sp = sp;
       W.step = S0.step;
       W.pop = MODE == MODE_STEP ? S0.popmode : POP_NONE;
-      W.dshift = MODE == MODE_STEP ? S0.dshift : C.dep_shift;
+      if (WS) W.dshift = MODE == MODE_STEP ? S0.dshift : C.dep_shift;
     }
     const Soa<R> in = gbuf(C, bsel, sp);
 
@@ -1918,16 +1923,18 @@ __global__ void k_philox_test(const uint32_t* ctr, uint32_t k0, uint32_t k1, int
 // ---------------------------------------------------------------- launchers
 template <typename R>
 hipError_t launch_particles(const Ctx<R>& C, int mode, hipStream_t s) {
+  const dim3 g(C.grid), b(BLOCK);
   if (C.split) {
     if (mode == MODE_STEP)
-      hipLaunchKernelGGL((k_gen<R, MODE_STEP, true>), dim3(C.grid), dim3(BLOCK), C.gen_lds, s, C);
+      hipLaunchKernelGGL((k_gen<R, MODE_STEP, true, 5>), g, b, C.gen_lds, s, C);
     else
-      hipLaunchKernelGGL((k_gen<R, MODE_REFRESH, true>), dim3(C.grid), dim3(BLOCK), C.gen_lds, s, C);
+      hipLaunchKernelGGL((k_gen<R, MODE_REFRESH, true, 5>), g, b, C.gen_lds, s, C);
+  } else if (mode != MODE_STEP) {
+    hipLaunchKernelGGL((k_gen<R, MODE_REFRESH, false, 5>), g, b, C.gen_lds, s, C);
+  } else if (sizeof(R) == 4 && C.occ == 4) {
+    hipLaunchKernelGGL((k_gen<R, MODE_STEP, false, 4>), g, b, C.gen_lds, s, C);
   } else {
-    if (mode == MODE_STEP)
-      hipLaunchKernelGGL((k_gen<R, MODE_STEP, false>), dim3(C.grid), dim3(BLOCK), C.gen_lds, s, C);
-    else
-      hipLaunchKernelGGL((k_gen<R, MODE_REFRESH, false>), dim3(C.grid), dim3(BLOCK), C.gen_lds, s, C);
+    hipLaunchKernelGGL((k_gen<R, MODE_STEP, false, 5>), g, b, C.gen_lds, s, C);
   }
   return hipGetLastError();
 }
@@ -1962,12 +1969,18 @@ hipError_t launch_seed(const Ctx<R>& C, int inst, int mode, int64_t n, double si
   return hipGetLastError();
 }
 
+// resident particle-kernel workgroups per compute unit for the kernel that
+// launch_particles picks for (split, occ)
 template <typename R>
-hipError_t occupancy_gen(int* blocks_per_cu, size_t dyn_lds, bool split) {
-  return split ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_gen<R, MODE_STEP, true>,
-                                                              BLOCK, dyn_lds)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_gen<R, MODE_STEP, false>,
-                                                              BLOCK, dyn_lds);
+hipError_t occupancy_gen(int* blocks_per_cu, size_t dyn_lds, bool split, int occ) {
+  if (split)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_gen<R, MODE_STEP, true, 5>,
+                                                        BLOCK, dyn_lds);
+  if (sizeof(R) == 4 && occ == 4)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_gen<R, MODE_STEP, false, 4>,
+                                                        BLOCK, dyn_lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_gen<R, MODE_STEP, false, 5>,
+                                                      BLOCK, dyn_lds);
 }
 
 template hipError_t launch_particles<float>(const Ctx<float>&, int, hipStream_t);
@@ -1980,8 +1993,8 @@ template hipError_t launch_seed<float>(const Ctx<float>&, int, int, int64_t, dou
                                        hipStream_t);
 template hipError_t launch_seed<double>(const Ctx<double>&, int, int, int64_t, double, uint32_t,
                                         hipStream_t);
-template hipError_t occupancy_gen<float>(int*, size_t, bool);
-template hipError_t occupancy_gen<double>(int*, size_t, bool);
+template hipError_t occupancy_gen<float>(int*, size_t, bool, int);
+template hipError_t occupancy_gen<double>(int*, size_t, bool, int);
 
 hipError_t launch_philox_test(const uint32_t* ctr, uint32_t k0, uint32_t k1, int64_t n,
                               uint32_t* out, hipStream_t s) {

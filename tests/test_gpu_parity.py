@@ -350,6 +350,49 @@ def test_autotuned_grid_changes_timing_not_results(xs_argon):
     print("default grid", g0, "autotuned", g)
 
 
+def test_launch_shapes_change_timing_not_results(xs_argon):
+    """FP32: the autotuner searches both register budgets and the grids with
+    three interleaved rounds of trial steps; each shape gives bit-identical
+    statistics, markers and fields."""
+    insts = [_c1_small(n_seed=3000, n_target=2500),
+             configs.Instance(d=0.02, p_torr=3.0, V=450.0, cells=700, gamma_se=0.1,
+                              seed_mode=configs.SEED_MAXWELL_CELL0, n_seed=20000,
+                              n_target=20000, capacity=80000)]
+    run = configs.Run(precision=32)
+    tuned = slpic.Sim(insts, run, xs_argon)
+    grid, waves = tuned.launch_shape()
+    assert waves == 5 and grid >= 1
+    g = tuned.autotune(2)
+    g2, w2 = tuned.launch_shape()
+    assert g == g2 and w2 in (4, 5)
+    steps = tuned.steps_done() + 12
+    runs = []
+    for shape in ((grid, 5), (max(1, grid // 3), 4), (g2, w2)):
+        sim = slpic.Sim(insts, run, xs_argon)
+        sim.set_launch_shape(*shape)
+        assert sim.launch_shape()[1] == shape[1]
+        sim.step(steps)
+        assert sim.sync() == 0
+        runs.append(sim)
+    tuned.step(12)
+    assert tuned.sync() == 0
+    runs.append(tuned)
+    a = runs[0]
+    for b in runs[1:]:
+        for k in range(len(insts)):
+            ha = a.history(steps - 16, 16, inst=k)
+            hb = b.history(steps - 16, 16, inst=k)
+            for key in STAT_INT + ["w_e", "w_i", "w_j"]:
+                assert np.array_equal(ha[key], hb[key]), (k, key)
+            for sp in (0, 1):
+                compare_populations(a.read(sp, k), b.read(sp, k), 0.0, 0.0,
+                                    a.scalars(k)["v0"], label=f"inst {k} sp {sp}")
+            assert np.array_equal(a.fields(inst=k)[2], b.fields(inst=k)[2])
+    with pytest.raises(slpic.SlpicError):
+        a.set_launch_shape(grid, 6)
+    print("autotuned shape", (g2, w2), "default", (grid, 5))
+
+
 def test_cell_sort_orders_markers_and_keeps_results(xs_argon):
     """Sorting every 4 steps gives the same FP64 steps as never sorting, and
     an explicit sort leaves every (instance, species) in cell order across
