@@ -257,13 +257,19 @@ def size_class(inst):
 
 def tuned_shape(w, xs, trial_steps=2):
     """Launch shape the autotuner picks for a workload, on a handle of its
-    own (its trial steps advance that handle only)."""
+    own (its trial steps advance that handle only): (grid, waves per SIMD,
+    work distribution)."""
     import paper_2103_12194_amd as slpic
     sim = slpic.Sim(w.instances, w.run, xs)
     sim.autotune(trial_steps)
-    shape = sim.launch_shape()
+    shape = sim.launch_shape() + (sim.work_distribution(),)
     sim.close()
     return shape
+
+
+def apply_shape(sim, shape):
+    sim.set_launch_shape(shape[0], shape[1])
+    sim.set_work_distribution(shape[2])
 
 
 def per_class_leg(w, xs, warm, steps):
@@ -283,10 +289,11 @@ def per_class_leg(w, xs, warm, steps):
         sub = configs.Workload(f"class {c}", w.run, insts, w.steps)
         shape = tuned_shape(sub, xs)
         sim = slpic.Sim(insts, w.run, xs)
-        sim.set_launch_shape(*shape)
+        apply_shape(sim, shape)
         sim.step(warm)
         sims.append(sim)
-        shapes[str(c)] = {"instances": len(insts), "grid": shape[0], "waves_per_simd": shape[1]}
+        shapes[str(c)] = {"instances": len(insts), "grid": shape[0], "waves_per_simd": shape[1],
+                          "claimed_runs": shape[2]}
     for sim in sims:
         sim.sync()
     torch.cuda.synchronize()
@@ -368,11 +375,11 @@ def main():
     # launch shape: autotuned on a copy of the workload, so that the timed
     # handle takes exactly the warmup steps asked for
     shape = tuned_shape(w, xs)
-    print(f"# autotuned launch shape: grid {shape[0]}, {shape[1]} waves per SIMD",
-          file=sys.stderr, flush=True)
+    print(f"# autotuned launch shape: grid {shape[0]}, {shape[1]} waves per SIMD, "
+          f"{'claimed runs' if shape[2] else 'equal shares'}", file=sys.stderr, flush=True)
     sim = slpic.Sim(w.instances, w.run, xs)
-    default_shape = sim.launch_shape()
-    sim.set_launch_shape(*shape)
+    default_shape = sim.launch_shape() + (sim.work_distribution(),)
+    apply_shape(sim, shape)
     sim.step(args.warmup)
     sim.sync()
     print(f"# warmup {args.warmup} steps done", file=sys.stderr, flush=True)
@@ -441,9 +448,11 @@ def main():
                    "n_inst": len(w.instances), "marker_scale": args.scale,
                    "markers_per_step": n_markers, "parallelism": "none (1 GPU)"},
         "roofline": roofline, "plain": plain, "eager": eager,
-        "launch_shape": {"grid": shape[0], "waves_per_simd": shape[1], "autotuned": True,
+        "launch_shape": {"grid": shape[0], "waves_per_simd": shape[1],
+                         "claimed_runs": shape[2], "autotuned": True,
                          "default": {"grid": default_shape[0],
-                                     "waves_per_simd": default_shape[1]}},
+                                     "waves_per_simd": default_shape[1],
+                                     "claimed_runs": default_shape[2]}},
         "cpu_baseline": cpu,
     }
     if pic is not None:

@@ -232,7 +232,8 @@ int slpic_use_graph(slpic_t* h, int enable);
  * fixed-point sums), only the time does.  slpic_autotune times trial_steps
  * steps (after one untimed step) for each candidate shape -- every budget
  * with grids of a quarter, half and all of the compute units and 1 .. the
- * resident maximum workgroups per compute unit -- in three interleaved
+ * resident maximum workgroups per compute unit, each with both work
+ * distributions (slpic_set_work_distribution) -- in three interleaved
  * rounds, keeps the candidate with the smallest median time and writes its
  * grid to *grid (host, may be NULL).  Tuning a handle per size class of
  * instances (marker count x cells) tunes each class's shape.  The trial
@@ -250,6 +251,21 @@ int slpic_launch_shape(slpic_t* h, int* grid, int* waves_per_simd);
  * SIMD 4 or 5 for FP32 whole markers, 0 otherwise; else SLPIC_INVALID_ARG.
  * Synchronizes; drops a captured graph. */
 int slpic_set_launch_shape(slpic_t* h, int grid, int waves_per_simd);
+
+/* Work distribution of the particle kernel.  claimed == 1 (the default
+ * unless markers are cell-sorted, resort_period > 0): every workgroup
+ * claims runs of consecutive tiles from counters of the step, the runs
+ * shrinking as the step ends, so that workgroups that draw costly tiles
+ * (electrons against ions, high collision rates) do not hold the launch
+ * while others idle; claimed == 0: equal contiguous shares of the tiles
+ * (cell-sorted markers keep their deposits in a workgroup's LDS window
+ * best this way).  Both give the same results bit for bit; slpic_autotune
+ * times both.  Synchronizes; drops a captured graph.  Else
+ * SLPIC_INVALID_ARG. */
+int slpic_set_work_distribution(slpic_t* h, int claimed);
+
+/* Current work distribution (host output): 1 claimed runs, 0 equal shares. */
+int slpic_work_distribution(slpic_t* h, int* claimed);
 
 /* Current particle-kernel grid (host output). */
 int slpic_grid(slpic_t* h, int* grid);

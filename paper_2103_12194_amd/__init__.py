@@ -81,7 +81,8 @@ EXPORTS = ["slpic_workspace_bytes", "slpic_create", "slpic_create_static", "slpi
            "slpic_destroy", "slpic_philox_device", "slpic_profile",
            "slpic_kernel_times", "slpic_partitions", "slpic_autotune",
            "slpic_grid", "slpic_sort", "slpic_read_weights", "slpic_launch_shape",
-           "slpic_set_launch_shape"]
+           "slpic_set_launch_shape", "slpic_set_work_distribution",
+           "slpic_work_distribution"]
 
 
 def lib():
@@ -122,6 +123,8 @@ def lib():
         L.slpic_grid.argtypes = [vp, P(i32)]
         L.slpic_launch_shape.argtypes = [vp, P(i32), P(i32)]
         L.slpic_set_launch_shape.argtypes = [vp, i32, i32]
+        L.slpic_set_work_distribution.argtypes = [vp, i32]
+        L.slpic_work_distribution.argtypes = [vp, P(i32)]
         L.slpic_partitions.argtypes = [vp, i32, i32, P(C.c_int32), P(i64), vp]
         L.slpic_kernel_times.argtypes = [vp, P(C.c_double), P(C.c_double), P(i64)]
         L.slpic_philox_device.argtypes = [vp, C.c_uint32, C.c_uint32, i64, vp, vp]
@@ -275,6 +278,15 @@ class Sim:
 
     def set_launch_shape(self, grid, waves_per_simd):
         _check(lib().slpic_set_launch_shape(self.h, int(grid), int(waves_per_simd)), self.h)
+
+    def work_distribution(self):
+        """1: workgroups claim runs of tiles; 0: equal contiguous shares."""
+        d = C.c_int()
+        _check(lib().slpic_work_distribution(self.h, C.byref(d)), self.h)
+        return d.value
+
+    def set_work_distribution(self, claimed):
+        _check(lib().slpic_set_work_distribution(self.h, int(claimed)), self.h)
 
     def profile(self, enable=True):
         """Record per-kernel HIP events around the following steps."""

@@ -299,6 +299,22 @@ InstParams derive(const slpic_config* cfg, const slpic_instance& I, const slpic_
   }
   P.g_e = 1.0 - P.f_e;
   P.g_cx = 1.0 - P.f_cx;
+  P.dt_f = (float)P.dt;
+  P.v0_f = (float)P.v0;
+  P.inv_v0_f = (float)P.inv_v0;
+  P.dx_f = (float)P.dx;
+  P.inv_dx_f = (float)P.inv_dx;
+  P.qm_e_f = (float)P.qm_e;
+  P.qm_i_f = (float)P.qm_i;
+  P.n_g_f = (float)P.n_g;
+  P.nu_max_e_f = (float)P.nu_max_e;
+  P.nu_max_cx_f = (float)P.nu_max_cx;
+  P.sigma_cx_f = (float)P.sigma_cx;
+  P.vth_i_f = (float)P.vth_i;
+  P.f_e_f = (float)P.f_e;
+  P.g_e_f = (float)P.g_e;
+  P.f_cx_f = (float)P.f_cx;
+  P.g_cx_f = (float)P.g_cx;
   return P;
 }
 
@@ -319,6 +335,7 @@ struct slpic_handle {
   int cus = 0, occ_per_cu = 0;  // compute units; resident particle workgroups per CU
   int occ = 5;                  // launch shape: waves per SIMD of the FP32 particle kernel
   int blocks_at[7] = {0, 0, 0, 0, 0, 0, 0};  // resident workgroups per CU for each shape
+  int dist = 1;                 // work distribution: 1 claimed runs, 0 equal shares
   uint64_t gen = 0;      // generation launches issued
   int64_t steps = 0;
   bool use_graph = false;
@@ -382,6 +399,7 @@ void fill_ctx(slpic_t* h, Ctx<R>& C) {
   C.flux = reinterpret_cast<double*>(w + L.flux);
   C.g = reinterpret_cast<Global*>(w + L.glob);
   C.split = splitting(&h->cfg) ? 1 : 0;
+  C.dist = h->dist;
   C.occ = h->occ;
   for (int b = 0; b < 2; ++b)
     for (int s = 0; s < 2; ++s) C.wt[b][s] = C.split ? reinterpret_cast<R*>(w + L.wt[b][s]) : nullptr;
@@ -750,6 +768,9 @@ int create_impl(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
     return rc;
   }
   h->grid = std::max(1, std::min(cus * std::max(per_cu, 1), h->L.max_tiles));
+  // markers in cell order keep their deposits in the LDS window best with
+  // equal contiguous shares; otherwise runs are claimed (balance)
+  h->dist = cfg->resort_period > 0 ? 0 : 1;
   h->cus = cus;
   h->occ_per_cu = std::max(per_cu, 1);
   int lds_max = 0;
@@ -949,14 +970,17 @@ int slpic_step(slpic_t* h, int n_steps) {
 // register budget) and grid between steps.  Kernels read the generation
 // from device words, so only the launch changes; a captured graph holds the
 // old shape and is dropped.
-static int set_shape(slpic_t* h, int occ, int grid) {
+static int set_shape(slpic_t* h, int occ, int grid, int dist) {
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->grid = grid;
   h->occ = occ;
+  h->dist = dist;
   h->c32.grid = grid;
   h->c64.grid = grid;
   h->c32.occ = occ;
   h->c64.occ = occ;
+  h->c32.dist = dist;
+  h->c64.dist = dist;
   if (h->graph) {
     (void)hipGraphExecDestroy(h->graph);
     h->graph = nullptr;
@@ -974,24 +998,26 @@ int slpic_autotune(slpic_t* h, int trial_steps, int* grid) {
   if (!h || trial_steps < 1 || h->profiling) return fail(h, SLPIC_INVALID_ARG, "bad autotune arguments");
   // candidates: launch shapes (the FP32 whole-marker kernel comes in two
   // register budgets) times grids (a quarter, half and all of the compute
-  // units, then 1 .. the resident maximum workgroups per compute unit)
+  // units, then 1 .. the resident maximum workgroups per compute unit) times
+  // work distributions (claimed runs, equal contiguous shares)
   struct Cand {
-    int occ, grid;
+    int occ, grid, dist;
   };
   std::vector<Cand> cand;
-  auto add = [&](int oc, int g) {
+  auto add = [&](int oc, int g, int d) {
     g = std::max(1, std::min(g, h->L.max_tiles));
     for (const Cand& c : cand)
-      if (c.occ == oc && c.grid == g) return;
-    cand.push_back(Cand{oc, g});
+      if (c.occ == oc && c.grid == g && c.dist == d) return;
+    cand.push_back(Cand{oc, g, d});
   };
   const bool shapes = h->cfg.precision == 32 && !splitting(&h->cfg);
-  for (int oc : {5, 4}) {
-    if (oc != 5 && !shapes) continue;
-    const int per_cu = std::max(1, h->blocks_at[oc]);
-    for (int q = 4; q >= 1; q /= 2) add(oc, h->cus / q);
-    for (int pc = 1; pc <= per_cu; ++pc) add(oc, h->cus * pc);
-  }
+  for (int d : {1, 0})
+    for (int oc : {5, 4}) {
+      if (oc != 5 && !shapes) continue;
+      const int per_cu = std::max(1, h->blocks_at[oc]);
+      for (int q = 4; q >= 1; q /= 2) add(oc, h->cus / q, d);
+      for (int pc = 1; pc <= per_cu; ++pc) add(oc, h->cus * pc, d);
+    }
   hipEvent_t e0, e1;
   HIPCHK(h, hipEventCreate(&e0));
   hipError_t er = hipEventCreate(&e1);
@@ -1006,7 +1032,7 @@ int slpic_autotune(slpic_t* h, int trial_steps, int* grid) {
   int rc = SLPIC_OK;
   for (int round = 0; round < kRounds && rc == SLPIC_OK; ++round) {
     for (size_t c = 0; c < cand.size() && rc == SLPIC_OK; ++c) {
-      rc = set_shape(h, cand[c].occ, cand[c].grid);
+      rc = set_shape(h, cand[c].occ, cand[c].grid, cand[c].dist);
       // one untimed step in the new shape, then the timed ones
       for (int k = 0; k <= trial_steps && rc == SLPIC_OK; ++k) {
         if (k == 1 && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(h, SLPIC_HIP_ERROR, "event");
@@ -1035,7 +1061,7 @@ int slpic_autotune(slpic_t* h, int trial_steps, int* grid) {
       best = c;
     }
   }
-  rc = set_shape(h, cand[best].occ, cand[best].grid);
+  rc = set_shape(h, cand[best].occ, cand[best].grid, cand[best].dist);
   if (rc == SLPIC_OK && grid) *grid = cand[best].grid;
   return rc;
 }
@@ -1045,7 +1071,19 @@ int slpic_set_launch_shape(slpic_t* h, int grid, int waves_per_simd) {
   const bool shapes = h->cfg.precision == 32 && !splitting(&h->cfg);
   if (shapes ? (waves_per_simd != 4 && waves_per_simd != 5) : waves_per_simd != 0)
     return fail(h, SLPIC_INVALID_ARG, "waves per SIMD must be 4 or 5 (FP32 whole markers), else 0");
-  return set_shape(h, shapes ? waves_per_simd : h->occ, std::min(grid, h->L.max_tiles));
+  return set_shape(h, shapes ? waves_per_simd : h->occ, std::min(grid, h->L.max_tiles), h->dist);
+}
+
+int slpic_set_work_distribution(slpic_t* h, int claimed) {
+  if (!h || (claimed != 0 && claimed != 1) || h->profiling)
+    return fail(h, SLPIC_INVALID_ARG, "work distribution must be 0 (equal shares) or 1 (claimed runs)");
+  return set_shape(h, h->occ, h->grid, claimed);
+}
+
+int slpic_work_distribution(slpic_t* h, int* claimed) {
+  if (!h || !claimed) return fail(h, SLPIC_INVALID_ARG, "null distribution output");
+  *claimed = h->dist;
+  return SLPIC_OK;
 }
 
 int slpic_launch_shape(slpic_t* h, int* grid, int* waves_per_simd) {

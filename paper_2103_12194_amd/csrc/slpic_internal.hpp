@@ -20,10 +20,13 @@ constexpr int CSTRIDE = 64;       // uint32 slots between compaction counters:
                                   // reservations of one (instance, species)
                                   // spread over memory channels
 constexpr int NSLOT = 1;          // copies of each global deposit node
+constexpr int NPOOL = 8;          // claim counters of the particle kernel's
+                                  // work distribution
 constexpr int MAX_DEVICES = 64;   // devices a process can hold a static workspace on
-constexpr int HWIN = 960;         // nodes in a workgroup's LDS deposit window
-                                  // (30 KB of LDS per workgroup in all: five
-                                  // workgroups per CU)
+constexpr int HWIN = 928;         // nodes in a workgroup's LDS deposit window
+                                  // (under 30 KB of LDS per workgroup in all,
+                                  // with room for the tile offsets of 256
+                                  // instances: five workgroups per CU)
 
 // bytes of the static workspace on each device (slpic_create_static)
 constexpr size_t STATIC_WS_BYTES = (size_t)64 << 20;
@@ -91,6 +94,11 @@ struct InstParams {
   uint32_t t_fsplit[MAX_CHAN]; // fixed events, split: channel k of a
                                // candidate if (r.y >> 9) < t_fsplit[k]
   uint32_t t_fixed_cx;         // fixed-event charge-exchange candidate (q)
+  // FP32 copies of the constants that the FP32 kernels use per marker,
+  // rounded once on the host (the same rounding as a conversion on the
+  // device) instead of converted at every use
+  float dt_f, v0_f, inv_v0_f, dx_f, inv_dx_f, qm_e_f, qm_i_f, n_g_f, nu_max_e_f, nu_max_cx_f,
+      sigma_cx_f, vth_i_f, f_e_f, g_e_f, f_cx_f, g_cx_f;
 };
 
 // Markers of one (buffer, species) in chunks of CH slots.  Within a chunk
@@ -147,6 +155,10 @@ struct Global {
   uint32_t cur_gen;     // generation of the current state (set by tails)
   uint32_t bufsel[2];   // particle buffer holding generation g's markers
   uint32_t err;
+  // tiles claimed so far from each pool of the particle kernel's work
+  // distribution, by the particle kernel of generation g in claim[g % 2]
+  // (reset for g + 1 by the tail kernel of g); one 256-byte line each
+  uint32_t claim[2][NPOOL][CSTRIDE];
 };
 
 template <typename R>
@@ -189,6 +201,8 @@ struct Ctx {
   R* wt[2][2];               // [buffer][species] flux weight of each marker slot
                              // in units of w_j (weight splitting only, else NULL)
   int split;                 // weight splitting (split fraction in (0, 1))
+  int dist;                  // work distribution of the particle kernel:
+                             // 0 equal contiguous shares, 1 claimed runs
   int occ;                   // waves per SIMD of the FP32 particle kernel's
                              // launch shape (4, 5 or 6)
   int sort_lds1, sort_lds2;  // dynamic LDS bytes of the sort's count and scatter

@@ -107,6 +107,13 @@ template <> struct Fm<float> {
 using IP = const __attribute__((address_space(4))) InstParams;
 __device__ __forceinline__ IP& param(const InstParams* ip, int i) { return ((IP*)ip)[i]; }
 
+// A per-instance constant in kernel precision: the FP64 field, or its FP32
+// copy rounded on the host.
+template <typename R> __device__ __forceinline__ R pr(double d, float f);
+template <> __device__ __forceinline__ double pr<double>(double d, float) { return d; }
+template <> __device__ __forceinline__ float pr<float>(double, float f) { return f; }
+#define PR(P, name) pr<R>((P).name, (P).name##_f)
+
 // ---------------------------------------------------------------- Philox
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
 // multiplies on words 0 and 2, with the Weyl-sequence key schedule.
@@ -857,6 +864,8 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
     for (int sp = 0; sp < 2; ++sp)
       C.tiles[(size_t)((g + 1) % 3u) * 2 * C.n_inst + 2 * inst + sp] = pair_tiles(s_mx[sp], P.parts);
     C.g->bufsel[(g + 1) % 2u] = MODE == MODE_STEP ? 1u - s_bs : s_bs;
+    if (inst == 0)  // the next particle kernel's claims
+      for (int p = 0; p < NPOOL; ++p) C.g->claim[(g + 1) % 2u][p][0] = 0u;
     C.g->cur_gen = g + 1;
   }
 }
@@ -1072,7 +1081,7 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
   IP& P = param(C.ip, W.inst);
   const int inst = W.inst, pop = W.pop;
   const uint32_t step = W.step;
-  const R v0 = (R)P.v0;
+  const R v0 = PR(P, v0);
   const int limited = P.limited;
 
   // population control: each output is kept (roulette) or doubled (split)
@@ -1282,11 +1291,11 @@ __device__ void collide_electron(const Ctx<R>& C, IP& P, int inst, uint32_t step
       if (ch < 0 && u < (split ? P.t_fsplit[q] : P.t_fixed[q])) ch = q;
   } else {
     const R sp0 = Fm<R>::sqrt(v2);
-    const R v0 = (R)P.v0;
+    const R v0 = PR(P, v0);
     const R slow = P.limited ? (sp0 < v0 ? sp0 : v0) : sp0;
-    const R numax = (R)P.nu_max_e;
+    const R numax = PR(P, nu_max_e);
     R cum;
-    ch = select_channel(C, eps, (R)P.n_g * slow, unif<R>(r.y) * numax, cum);
+    ch = select_channel(C, eps, PR(P, n_g) * slow, unif<R>(r.y) * numax, cum);
     if (cum > numax * R(1.000001)) err |= ERR_NU_BOUND;
   }
   o.e[0] = m;
@@ -1333,11 +1342,11 @@ __device__ void collide_electron(const Ctx<R>& C, IP& P, int inst, uint32_t step
     Mk<R> sc = m;
     sc.vx = sp1 * ox; sc.vy = sp1 * oy; sc.vz = sp1 * oz;
     if (split) {
-      const R f = (R)P.f_e;
+      const R f = PR(P, f_e);
       const U4 sid = draw_cold(m.id, step, CH_CHILD | (2u << 8), C.seed, P.key);
       sc.id = child(sid.x, sid.y);
       sc.w = m.w * f;
-      o.e[0].w = m.w * (R)P.g_e;
+      o.e[0].w = m.w * PR(P, g_e);
       o.e[1] = sc;
       o.me = 3u;
     } else {
@@ -1356,7 +1365,7 @@ __device__ void collide_electron(const Ctx<R>& C, IP& P, int inst, uint32_t step
       e2.id = child(cid.x, cid.y);
       e2.w = sc.w;
       Mk<R> i2 = m;
-      normals3<R>(b, (R)P.vth_i, i2.vx, i2.vy, i2.vz);
+      normals3<R>(b, PR(P, vth_i), i2.vx, i2.vy, i2.vz);
       i2.id = child(cid.z, cid.w);
       i2.w = sc.w;
       if (split) {
@@ -1383,10 +1392,10 @@ __device__ void collide_ion(const Ctx<R>& C, IP& P, int inst, uint32_t step,
     const U4 r = draw(m.id, step, CH_CX, C.seed, P.key);
     const R v2 = m.vx * m.vx + m.vy * m.vy + m.vz * m.vz;
     const R sp1 = Fm<R>::sqrt(v2);
-    const R v0 = (R)P.v0;
+    const R v0 = PR(P, v0);
     const R slow = P.limited ? (sp1 < v0 ? sp1 : v0) : sp1;
-    const R nu = (R)P.n_g * (R)P.sigma_cx * slow;
-    const R numax = (R)P.nu_max_cx;
+    const R nu = PR(P, n_g) * PR(P, sigma_cx) * slow;
+    const R numax = PR(P, nu_max_cx);
     if (nu > numax * R(1.000001)) err |= ERR_NU_BOUND;
     hit = unif<R>(r.y) * numax < nu;
   }
@@ -1395,13 +1404,13 @@ __device__ void collide_ion(const Ctx<R>& C, IP& P, int inst, uint32_t step,
   if (hit) {
     const U4 b = draw_cold(m.id, step, CH_CX | (1u << 8), C.seed, P.key);
     Mk<R> sc = m;
-    normals3<R>(b, (R)P.vth_i, sc.vx, sc.vy, sc.vz);
+    normals3<R>(b, PR(P, vth_i), sc.vx, sc.vy, sc.vz);
     if (WS && P.f_cx < 1.0) {
-      const R f = (R)P.f_cx;
+      const R f = PR(P, f_cx);
       const U4 sid = draw_cold(m.id, step, CH_CHILD | (2u << 8), C.seed, P.key);
       sc.id = child(sid.x, sid.y);
       sc.w = m.w * f;
-      o.i[0].w = m.w * (R)P.g_cx;
+      o.i[0].w = m.w * PR(P, g_cx);
       o.i[WS ? 1 : 0] = sc;
       o.mi = 3u;
     } else {
@@ -1436,12 +1445,12 @@ __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp
   uint32_t rnx = rn.x;
   asm volatile("" : "+v"(rnx));
   const R Ep = e0 + m.off * (e1 - e0);
-  const R a = (R)(sp == 0 ? P.qm_e : P.qm_i) * Ep;
+  const R a = (sp == 0 ? PR(P, qm_e) : PR(P, qm_i)) * Ep;
   const R c = Fm<R>::sqrt(m.vy * m.vy + m.vz * m.vz);
   R disp, vx1, tdisp;
   bool turns;
-  flight<R>(m.vx, c, a, (R)P.dt, (R)P.v0, (R)P.inv_v0, P.limited, disp, vx1, turns, tdisp);
-  const R inv_dx = (R)P.inv_dx;
+  flight<R>(m.vx, c, a, PR(P, dt), PR(P, v0), PR(P, inv_v0), P.limited, disp, vx1, turns, tdisp);
+  const R inv_dx = PR(P, inv_dx);
   R f = m.off + disp * inv_dx;
   const R fl = m_floor(f);
   int cell = m.cell + (int)fl;
@@ -1475,7 +1484,7 @@ __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp
       // the flight, so the ion reaches x = 0 with v_x^2 = vx^2 - 2 a x
       const U4 r = draw_cold(m.id, step, CH_SEE, C.seed, P.key);
       const bool see = (C.flags & 2u)
-                           ? unif<R>(r.x) < impact_yield<R>(E, (R)P.qm_i, (R)P.dx, m)
+                           ? unif<R>(r.x) < impact_yield<R>(E, PR(P, qm_i), PR(P, dx), m)
                            : (r.x >> 9) < P.t_see;
       if (see) {
         ev |= 1u << EV_SEE;
@@ -1530,6 +1539,9 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
   extern __shared__ uint32_t s_prefix[];  // 2 n_inst + 1 tile offsets (dynamic)
   __shared__ unsigned long long s_hist[2][HWIN];
   __shared__ uint32_t s_gen;
+  __shared__ uint32_t s_run[2];
+  __shared__ uint32_t s_claim[5];  // pool, its counter as seen, the claim's offset and size
+  __shared__ uint32_t s_dist[3];   // first tile of the pools, first-run size, workgroups per pool
   __shared__ uint32_t s_evw[NWAVE][NEV];
   __shared__ double s_scan[NWAVE + 1];
   // collision queues (rings), one per wave: candidates of the wave's
@@ -1558,14 +1570,109 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
   const uint32_t n_tiles = s_prefix[nk];
   const uint32_t bsel = C.g->bufsel[g % 2u];
 
-  // each workgroup takes a contiguous run of tiles, so that (for markers in
-  // cell order) its deposits stay inside one LDS window.  Wave w of the
-  // workgroup takes markers [64 w, 64 w + 64) of every tile and runs on its
-  // own: compaction, collision queue and output reservations are per wave,
-  // and the waves meet only to flush the deposit window when the instance
-  // changes (all four change at the same tile).
-  const uint32_t per = (n_tiles + (uint32_t)C.grid - 1) / (uint32_t)C.grid;
-  const uint32_t t_begin = blockIdx.x * per, t_end = min(n_tiles, t_begin + per);
+  // Work distribution.  Tile costs differ widely (electron tiles against ion
+  // tiles, collision rates from instance to instance), so equal shares of
+  // tiles leave much of the grid idle while the costliest shares finish.
+  // The tiles form NPOOL pools of consecutive tiles, each with a claim
+  // counter of the step on a line of its own.  Workgroup b claims runs of
+  // consecutive tiles from pool b mod NPOOL, each as large as the pool's
+  // unclaimed tiles over twice its share of the grid (at most
+  // n_tiles / (2 grid), at least one) as of its previous claim, so that runs
+  // shrink as the step ends, and moves on to the pool with the most tiles
+  // left when its pool is exhausted.  Claiming from the start, rather than
+  // taking a fixed first share, keeps a workgroup that starts late (when
+  // the grid exceeds what stays resident) from ending late.  Runs are
+  // contiguous, so that (for markers in cell order) deposits stay inside
+  // one LDS window.  A claim goes out at the start of a run's last tile and
+  // is read at its end; the first lane of the workgroup keeps the claims in
+  // LDS.  With fewer than four tiles per workgroup the claims would cost
+  // more than they balance: equal contiguous shares, no claims, as with
+  // the static distribution (C.dist == 0), which suits markers in cell
+  // order, whose contiguous shares keep their deposits in the window.  The claim
+  // logic reads its constants from LDS (s_dist), so that they hold no scalar
+  // registers in the tile loop.
+  uint32_t run_b, run_e;
+  {
+    const uint32_t grid = gridDim.x;
+    const bool pooled = C.dist && n_tiles >= 4u * grid;
+    const uint32_t per = (n_tiles + grid - 1u) / grid;
+    run_b = pooled ? 0u : (uint32_t)min((uint64_t)n_tiles, (uint64_t)blockIdx.x * per);
+    run_e = pooled ? 0u : min(n_tiles, run_b + per);
+    if (tid == 0) {
+      const uint32_t home = blockIdx.x % (uint32_t)NPOOL;
+      s_dist[0] = pooled ? 0u : n_tiles;              // first tile of the pools
+      s_dist[1] = max(1u, n_tiles / (2u * grid));     // largest run
+      s_dist[2] = max(1u, grid / (uint32_t)NPOOL);    // workgroups per pool
+      s_claim[0] = home;                              // pool
+      s_claim[1] = pooled ? __hip_atomic_load(&C.g->claim[g % 2u][home][0], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT)
+                          : 0u;                       // its counter as last seen
+    }
+  }
+  // tiles [pool_lo(p), pool_lo(p + 1)) form pool p
+  auto pool_lo = [&](uint32_t p) {
+    const uint32_t base = s_dist[0];
+    return base + (uint32_t)(((uint64_t)(n_tiles - base) * p) / (uint32_t)NPOOL);
+  };
+  // thread 0: claim a run from the current pool (its offset in the pool in
+  // s_claim[3], its size in s_claim[4]) when there are pools
+  auto claim = [&]() {
+    if (s_dist[0] >= n_tiles) {
+      s_claim[3] = 0u;
+      s_claim[4] = 0u;
+      return;
+    }
+    const uint32_t p = s_claim[0];
+    const uint32_t size = pool_lo(p + 1) - pool_lo(p), seen = s_claim[1];
+    const uint32_t rem = size > seen ? size - seen : 0u;
+    const uint32_t kk = min(s_dist[1], max(1u, rem / (2u * s_dist[2])));
+    s_claim[3] = atomicAdd(&C.g->claim[g % 2u][p][0], kk);
+    s_claim[4] = kk;
+  };
+  // wave 0, at the end of a run: the claimed run into s_run, or, when the
+  // claim found its pool exhausted, a claim from the pool with the most
+  // tiles left (the lanes read every pool's counter at once), until every
+  // pool is exhausted (s_run empty)
+  auto resolve = [&]() {
+    for (;;) {
+      const uint32_t p = s_claim[0], at = s_claim[3], kk = s_claim[4];
+      if (kk == 0u) {
+        if (lane == 0) s_run[0] = s_run[1] = n_tiles;
+        return;
+      }
+      const uint32_t lo = pool_lo(p), size = pool_lo(p + 1) - lo;
+      if (at < size) {
+        if (lane == 0) {
+          s_claim[1] = at + kk;
+          s_run[0] = lo + at;
+          s_run[1] = lo + min(at + kk, size);
+        }
+        return;
+      }
+      unsigned long long key = 0ull;  // tiles left << 8 | pool
+      if (lane < NPOOL) {
+        const uint32_t c = __hip_atomic_load(&C.g->claim[g % 2u][lane][0], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t sz = pool_lo((uint32_t)lane + 1u) - pool_lo((uint32_t)lane);
+        key = (unsigned long long)(sz > c ? sz - c : 0u) << 8 | (unsigned long long)lane;
+      }
+#pragma unroll
+      for (int d = 1; d < NPOOL; d <<= 1) {
+        const unsigned long long o = __shfl_xor(key, d);
+        key = o > key ? o : key;
+      }
+      if ((key >> 8) == 0ull) {
+        if (lane == 0) s_run[0] = s_run[1] = n_tiles;
+        return;
+      }
+      if (lane == 0) {
+        const uint32_t q = (uint32_t)(key & 0xffu);
+        s_claim[0] = q;
+        s_claim[1] = pool_lo(q + 1) - pool_lo(q) - (uint32_t)(key >> 8);
+        claim();
+      }
+    }
+  };
   DepWin win{-1, 0};
   Work W{-1, -1, 0, 0u, POP_NONE, 0, 0, 0u};
   uint32_t q_head = 0, q_count = 0;  // uniform over the wave
@@ -1616,7 +1723,11 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
   // leave room for five waves per SIMD, which hide more of the load and
   // atomic latency than two markers per lane at four waves did.
   TileCursor cur;
-  for (uint32_t t = t_begin; t < t_end; ++t) {
+  for (;;) {
+  if (tid == 0 && run_b == run_e) claim();  // nothing in this run: claim at once
+  cur.kc = -1;  // a run can start anywhere: find its pair by bisection
+  for (uint32_t t = run_b; t < run_e; ++t) {
+    if (tid == 0 && t + 1u == run_e) claim();
     cur.locate(s_prefix, nk, t);
     const int k = cur.kc, inst = k >> 1, sp = k & 1;
     IP& P = param(C.ip, inst);
@@ -1675,6 +1786,14 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
     next_output(W, P);
     emit<R, MODE, false, WS>(C, W, win, s_hist, o, ev, err, g, bsel, evw);
     while (MODE == MODE_STEP && q_count >= (uint32_t)WAVE) run_queue((uint32_t)WAVE);
+  }
+  if (wv == 0) resolve();
+  __syncthreads();
+  // the same for every lane: kept in scalar registers
+  run_b = __builtin_amdgcn_readfirstlane(s_run[0]);
+  run_e = __builtin_amdgcn_readfirstlane(s_run[1]);
+  __syncthreads();  // read before thread 0 writes the next run
+  if (run_b >= run_e) break;
   }
   while (q_count > 0) run_queue(q_count < (uint32_t)WAVE ? q_count : (uint32_t)WAVE);
   if (win.inst >= 0) dep_flush(C, s_hist, win, s_evw);

@@ -351,9 +351,9 @@ def test_autotuned_grid_changes_timing_not_results(xs_argon):
 
 
 def test_launch_shapes_change_timing_not_results(xs_argon):
-    """FP32: the autotuner searches both register budgets and the grids with
-    three interleaved rounds of trial steps; each shape gives bit-identical
-    statistics, markers and fields."""
+    """FP32: the autotuner searches both register budgets, the grids and the
+    two work distributions with three interleaved rounds of trial steps;
+    each shape gives bit-identical statistics, markers and fields."""
     insts = [_c1_small(n_seed=3000, n_target=2500),
              configs.Instance(d=0.02, p_torr=3.0, V=450.0, cells=700, gamma_se=0.1,
                               seed_mode=configs.SEED_MAXWELL_CELL0, n_seed=20000,
@@ -367,10 +367,13 @@ def test_launch_shapes_change_timing_not_results(xs_argon):
     assert g == g2 and w2 in (4, 5)
     steps = tuned.steps_done() + 12
     runs = []
-    for shape in ((grid, 5), (max(1, grid // 3), 4), (g2, w2)):
+    d2 = tuned.work_distribution()
+    assert d2 in (0, 1) and slpic.Sim(insts, run, xs_argon).work_distribution() == 1
+    for shape in ((grid, 5, 1), (max(1, grid // 3), 4, 1), (grid, 5, 0), (g2, w2, d2)):
         sim = slpic.Sim(insts, run, xs_argon)
-        sim.set_launch_shape(*shape)
-        assert sim.launch_shape()[1] == shape[1]
+        sim.set_launch_shape(*shape[:2])
+        sim.set_work_distribution(shape[2])
+        assert sim.launch_shape()[1] == shape[1] and sim.work_distribution() == shape[2]
         sim.step(steps)
         assert sim.sync() == 0
         runs.append(sim)
@@ -390,7 +393,9 @@ def test_launch_shapes_change_timing_not_results(xs_argon):
             assert np.array_equal(a.fields(inst=k)[2], b.fields(inst=k)[2])
     with pytest.raises(slpic.SlpicError):
         a.set_launch_shape(grid, 6)
-    print("autotuned shape", (g2, w2), "default", (grid, 5))
+    with pytest.raises(slpic.SlpicError):
+        a.set_work_distribution(2)
+    print("autotuned shape", (g2, w2, d2), "default", (grid, 5, 1))
 
 
 def test_cell_sort_orders_markers_and_keeps_results(xs_argon):
