@@ -1540,7 +1540,8 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
   __shared__ unsigned long long s_hist[2][HWIN];
   __shared__ uint32_t s_gen;
   __shared__ uint32_t s_run[2];
-  __shared__ uint32_t s_claim[5];  // pool, its counter as seen, the claim's offset and size
+  __shared__ uint32_t s_claim[7];  // pool, its tiles left and when, the claim's offset and
+                                   // size, the workgroup's start and tiles taken
   __shared__ uint32_t s_dist[3];   // first tile of the pools, first-run size, workgroups per pool
   __shared__ uint32_t s_evw[NWAVE][NEV];
   __shared__ double s_scan[NWAVE + 1];
@@ -1577,8 +1578,8 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
   // counter of the step on a line of its own.  Workgroup b claims runs of
   // consecutive tiles from pool b mod NPOOL, each as large as the pool's
   // unclaimed tiles over twice its share of the grid (at most
-  // n_tiles / (2 grid), at least one) as of its previous claim, so that runs
-  // shrink as the step ends, and moves on to the pool with the most tiles
+  // n_tiles / (2 grid), at least one), so that runs shrink as the step
+  // ends, and moves on to the pool with the most tiles
   // left when its pool is exhausted.  Claiming from the start, rather than
   // taking a fixed first share, keeps a workgroup that starts late (when
   // the grid exceeds what stays resident) from ending late.  Runs are
@@ -1600,13 +1601,16 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
     run_e = pooled ? 0u : min(n_tiles, run_b + per);
     if (tid == 0) {
       const uint32_t home = blockIdx.x % (uint32_t)NPOOL;
+      const uint32_t now = (uint32_t)__builtin_amdgcn_s_memrealtime();
       s_dist[0] = pooled ? 0u : n_tiles;              // first tile of the pools
       s_dist[1] = max(1u, n_tiles / (2u * grid));     // largest run
       s_dist[2] = max(1u, grid / (uint32_t)NPOOL);    // workgroups per pool
       s_claim[0] = home;                              // pool
-      s_claim[1] = pooled ? __hip_atomic_load(&C.g->claim[g % 2u][home][0], __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT)
-                          : 0u;                       // its counter as last seen
+      s_claim[1] = (uint32_t)(((uint64_t)n_tiles * (home + 1u)) / (uint32_t)NPOOL -
+                              ((uint64_t)n_tiles * home) / (uint32_t)NPOOL);  // its tiles left
+      s_claim[2] = now;                               // as of this time
+      s_claim[5] = now;                               // start of the workgroup
+      s_claim[6] = 0u;                                // tiles it has taken
     }
   }
   // tiles [pool_lo(p), pool_lo(p + 1)) form pool p
@@ -1615,19 +1619,25 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
     return base + (uint32_t)(((uint64_t)(n_tiles - base) * p) / (uint32_t)NPOOL);
   };
   // thread 0: claim a run from the current pool (its offset in the pool in
-  // s_claim[3], its size in s_claim[4]) when there are pools
+  // s_claim[3], its size in s_claim[4]) when there are pools.  The pool's
+  // tiles left are estimated from the count at the last claim, less what
+  // the pool's workgroups have taken since at this workgroup's own rate
+  // (the real-time counter, no memory access).
   auto claim = [&]() {
     if (s_dist[0] >= n_tiles) {
       s_claim[3] = 0u;
       s_claim[4] = 0u;
       return;
     }
-    const uint32_t p = s_claim[0];
-    const uint32_t size = pool_lo(p + 1) - pool_lo(p), seen = s_claim[1];
-    const uint32_t rem = size > seen ? size - seen : 0u;
+    const uint32_t p = s_claim[0], now = (uint32_t)__builtin_amdgcn_s_memrealtime();
+    const float rate = (float)s_claim[6] / (float)max(1u, now - s_claim[5]);  // tiles per tick
+    const float left =
+        (float)s_claim[1] - rate * (float)(now - s_claim[2]) * (float)s_dist[2];
+    const uint32_t rem = left > 0.0f ? (uint32_t)left : 0u;
     const uint32_t kk = min(s_dist[1], max(1u, rem / (2u * s_dist[2])));
     s_claim[3] = atomicAdd(&C.g->claim[g % 2u][p][0], kk);
     s_claim[4] = kk;
+    s_claim[2] = now;
   };
   // wave 0, at the end of a run: the claimed run into s_run, or, when the
   // claim found its pool exhausted, a claim from the pool with the most
@@ -1643,9 +1653,11 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
       const uint32_t lo = pool_lo(p), size = pool_lo(p + 1) - lo;
       if (at < size) {
         if (lane == 0) {
-          s_claim[1] = at + kk;
+          const uint32_t end = min(at + kk, size);
+          s_claim[1] = size - end;   // tiles left at the claim
+          s_claim[6] += end - at;
           s_run[0] = lo + at;
-          s_run[1] = lo + min(at + kk, size);
+          s_run[1] = lo + end;
         }
         return;
       }
@@ -1666,9 +1678,9 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
         return;
       }
       if (lane == 0) {
-        const uint32_t q = (uint32_t)(key & 0xffu);
-        s_claim[0] = q;
-        s_claim[1] = pool_lo(q + 1) - pool_lo(q) - (uint32_t)(key >> 8);
+        s_claim[0] = (uint32_t)(key & 0xffu);
+        s_claim[1] = (uint32_t)(key >> 8);
+        s_claim[2] = (uint32_t)__builtin_amdgcn_s_memrealtime();
         claim();
       }
     }
