@@ -450,6 +450,9 @@ int upload_tables(slpic_t* h, Ctx<R>& C, const slpic_xs* xs) {
   C.e_lo = (R)xs->energies[0];
   C.e_hi = (R)xs->energies[ng - 1];
   C.inv_dlog = (R)((ng - 1) / std::log(xs->energies[ng - 1] / xs->energies[0]));
+  const double dlog = std::log(xs->energies[ng - 1] / xs->energies[0]) / (ng - 1);
+  C.log2_ratio = (R)(dlog / std::log(2.0));
+  C.ratio_m1 = (R)std::expm1(dlog);
   HIPCHK(h, hipMemcpyAsync((void*)C.xs_e, e.data(), sizeof(R) * ng, hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, hipMemcpyAsync((void*)C.xs_sig, sig.data(), sizeof(R) * sig.size(), hipMemcpyHostToDevice,
                            h->stream));

@@ -181,6 +181,7 @@ struct Ctx {
   const R* xs_thr;           // [n_chan]
   const int32_t* xs_kind;    // [n_chan]
   R log_emin, inv_dlog;      // log-uniform grid index
+  R log2_ratio, ratio_m1;    // log2 of the node ratio g, and g - 1
   R e_lo, e_hi;              // first and last node energies
   double ion_B;
   int n_chan, n_grid;

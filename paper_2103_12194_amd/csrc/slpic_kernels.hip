@@ -413,14 +413,28 @@ __device__ __forceinline__ T chan_entry(const T* table, int k) {
 template <typename R>
 __device__ __forceinline__ int select_channel(const Ctx<R>& C, R eps, R scale, R target, R& cum) {
   const int n = C.n_grid, nc = C.n_chan;
-  // segment [i, i+1] holding eps: the log-uniform estimate ic is off by at
-  // most one node, so the energies of nodes ic-1 .. ic+2 are loaded together
-  // and the segment is picked from them
+  // segment [i, i+1] holding eps, and the position t in it
   int i;
   R t;
   if (!(eps > C.e_lo)) { i = 0; t = R(0); }
   else if (!(eps < C.e_hi)) { i = n - 2; t = R(1); }
-  else {
+  else if (sizeof(R) == 4) {
+    // FP32: the node energies of the log-uniform grid are e_lo g^i, g the
+    // node ratio, computed rather than loaded, so that the cross sections
+    // are the only dependent loads.  Within a few 1e-5 of a node the FP32
+    // estimate of i may be the neighbouring segment; t, clamped to [0, 1],
+    // then gives the node's value, a few 1e-5 of a segment's change away
+    // from the interpolant (which is continuous at nodes).
+    int ic = (int)((Fm<R>::log(eps) - C.log_emin) * C.inv_dlog);
+    ic = ic < 0 ? 0 : (ic > n - 2 ? n - 2 : ic);
+    const R e0 = C.e_lo * __builtin_amdgcn_exp2f((float)ic * (float)C.log2_ratio);
+    i = ic;
+    t = Fm<R>::div(eps - e0, e0 * C.ratio_m1);
+    t = t < R(0) ? R(0) : (t > R(1) ? R(1) : t);
+  } else {
+    // FP64: the log-uniform estimate ic is off by at most one node, so the
+    // energies of nodes ic-1 .. ic+2 are loaded together and the segment
+    // holding eps is picked from them (as the table lookup of the oracle)
     int ic = (int)((Fm<R>::log(eps) - C.log_emin) * C.inv_dlog);
     ic = ic < 0 ? 0 : (ic > n - 2 ? n - 2 : ic);
     const int im = ic > 0 ? ic - 1 : 0, ip = ic + 2 < n ? ic + 2 : n - 1;
