@@ -1164,7 +1164,7 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
   }
   // deposit (fixed point, units of q w_j): every kept marker adds its two
   // linear weights, times its flux weight with weight splitting, to the LDS
-  // window (clones count twice)
+  // window (clones count twice: one bit more)
   {
     // whole markers always use the base shift
     const int shift = WS ? W.dshift : C.dep_shift;
@@ -1174,9 +1174,9 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
       const Mk<R>& e = o.e[q];
       R b = beta_fast(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
       if (WS) b *= e.w;
-      const unsigned long long mul = clone_e[q] ? 2ull : 1ull;
+      const uint32_t dbl = clone_e[q] ? 1u : 0u;
       dep_add(C.acc, C.acc, hist, win, 0, P.node, C.total_nodes, e.cell,
-              fixed_pt<R>(b * (R(1) - e.off), shift) * mul, fixed_pt<R>(b * e.off, shift) * mul);
+              fixed_pt<R>(b * (R(1) - e.off), shift) << dbl, fixed_pt<R>(b * e.off, shift) << dbl);
     }
 #pragma unroll
     for (int q = 0; q < NI; ++q) {
@@ -1184,9 +1184,9 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
       const Mk<R>& e = o.i[q];
       R b = beta_fast(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
       if (WS) b *= e.w;
-      const unsigned long long mul = clone_i[q] ? 2ull : 1ull;
+      const uint32_t dbl = clone_i[q] ? 1u : 0u;
       dep_add(C.acc, C.acc, hist, win, 1, P.node, C.total_nodes, e.cell,
-              fixed_pt<R>(b * (R(1) - e.off), shift) * mul, fixed_pt<R>(b * e.off, shift) * mul);
+              fixed_pt<R>(b * (R(1) - e.off), shift) << dbl, fixed_pt<R>(b * e.off, shift) << dbl);
     }
   }
 
@@ -1777,7 +1777,10 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
         win.anchor = anchor < 0 ? 0 : anchor;
         win.inst = inst;
       }
-      const InstState S0 = C.st[(g % 2u) * C.n_inst + inst];
+      // the state of generation g: written by the last tail kernel, read
+      // only while this kernel runs (scalar loads)
+      using CS = const __attribute__((address_space(4))) InstState;
+      CS& S0 = ((CS*)C.st)[(g % 2u) * C.n_inst + inst];
       W.inst = inst;
       W.sp = sp;
       W.step = S0.step;
