@@ -994,6 +994,9 @@ struct TileCursor {
       kc = lo;
       kbeg = s_prefix[kc];
       kend = s_prefix[kc + 1];
+      // a new run can begin on the tile after the last run's end, in
+      // another pair: the place then has to be computed afresh
+      next = 0xffffffffu;
     }
     while (t >= kend) {
       ++kc;

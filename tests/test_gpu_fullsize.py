@@ -50,12 +50,30 @@ def _setup():
 
 @pytest.mark.parametrize("resort_period", [0, 4])
 def test_large_gaps_match_independent_oracles_step_by_step(resort_period, xs_argon):
+    _large_gaps(resort_period, xs_argon)
+
+
+@pytest.mark.parametrize("resort_period", [0, 4])
+def test_large_gaps_with_claimed_runs_match_independent_oracles(resort_period, xs_argon):
+    """The same on a grid of 32 workgroups, so that the particle kernel's
+    workgroups claim runs of tiles from the step's pool counters (at least
+    four tiles per workgroup), with and without the cell sort."""
+    _large_gaps(resort_period, xs_argon, grid=32, claimed=1)
+
+
+def _large_gaps(resort_period, xs_argon, grid=None, claimed=None):
     insts, pops = _setup()
     # a flux weight at which the markers' space charge moves the field by
     # 0.1-3 % of V/d: about 1e8 times the field tolerance below
     run = configs.Run(precision=64, w_j0=2e7, resort_period=resort_period)
-    print(f"full-size parity, resort_period={resort_period}", flush=True)
+    print(f"full-size parity, resort_period={resort_period}, grid={grid}, claimed={claimed}",
+          flush=True)
     gpu = slpic.Sim(insts, run, xs_argon)
+    if grid is not None:
+        gpu.set_launch_shape(grid, 0)
+    if claimed is not None:
+        gpu.set_work_distribution(claimed)
+        assert gpu.work_distribution() == claimed
     refs = [oracle.Sim(x, run, xs_argon, instance_index=k) for k, x in enumerate(insts)]
     for k, (e, i) in enumerate(pops):
         for sim, kw in ((gpu, {"inst": k}), (refs[k], {})):
