@@ -49,6 +49,9 @@ thread_local std::string g_create_error;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// channels per row of the particle kernel's cross-section table
+int row_channels(int n_chan) { return n_chan <= 4 ? 4 : MAX_CHAN; }
+
 // Integer form of a per-step probability: with u = (2m + 1) 2^-24 for the
 // 23-bit integer m = r >> 9, u < P holds exactly for m < ceil((P 2^24 - 1)/2).
 uint32_t prob_threshold(double P) {
@@ -142,11 +145,11 @@ bool make_layout(const slpic_config* cfg, const slpic_instance* inst, int n_inst
   L.cross = take(sizeof(int32_t) * 2 * (size_t)nodes);
   L.flux = take(sizeof(double) * 2 * (size_t)nodes);
   L.glob = take(sizeof(Global));
-  const int ng = xs->n_grid, nc = std::max(xs->n_chan, 1);
+  const int ng = xs->n_grid;
   L.xs_e = take(rs * ng);
-  L.xs_sig = take(rs * (size_t)ng * nc);
-  L.xs_thr = take(rs * nc);
-  L.xs_kind = take(sizeof(int32_t) * nc);
+  L.xs_sig = take(rs * (size_t)ng * 2 * row_channels(xs->n_chan));
+  L.xs_thr = take(rs * MAX_CHAN);
+  L.xs_kind = take(sizeof(int32_t) * MAX_CHAN);
   // cap is a whole number of chunks (every partition is)
   const size_t chunk_bytes = (size_t)CH * (4 + 4 * rs + 8);
   for (int b = 0; b < 2; ++b)
@@ -431,19 +434,29 @@ void fill_ctx(slpic_t* h, Ctx<R>& C) {
   C.sort_lds2 = (int)sort_lds_bytes(h->n_inst, maxc, 2);
 }
 
+// Cross-section table rows for the particle kernel: per node the channels'
+// values and their changes to the next node, padded to 4 or MAX_CHAN
+// channels, so that a collision reads its node's row in one aligned access.
+// The change is b - a in the kernel's precision, the same number the
+// interpolation a + t (b - a) would form.
 template <typename R>
 int upload_tables(slpic_t* h, Ctx<R>& C, const slpic_xs* xs) {
-  const int ng = xs->n_grid, nc = xs->n_chan;
-  std::vector<R> e(ng), sig((size_t)ng * std::max(nc, 1)), thr(std::max(nc, 1));
-  std::vector<int32_t> kind(std::max(nc, 1), 0);
+  const int ng = xs->n_grid, nc = xs->n_chan, ncp = row_channels(nc);
+  std::vector<R> e(ng), sig((size_t)ng * 2 * ncp, R(0)), thr(MAX_CHAN, (R)INFINITY);
+  std::vector<int32_t> kind(MAX_CHAN, 0);
   for (int j = 0; j < ng; ++j) e[j] = (R)xs->energies[j];
   for (int j = 0; j < ng; ++j)
-    for (int k = 0; k < nc; ++k) sig[(size_t)j * nc + k] = (R)xs->sigma[(size_t)k * ng + j];
+    for (int k = 0; k < nc; ++k) {
+      const R a = (R)xs->sigma[(size_t)k * ng + j];
+      sig[(size_t)j * 2 * ncp + k] = a;
+      if (j + 1 < ng) sig[(size_t)j * 2 * ncp + ncp + k] = (R)xs->sigma[(size_t)k * ng + j + 1] - a;
+    }
   for (int k = 0; k < nc; ++k) {
     thr[k] = (R)xs->threshold_eV[k];
     kind[k] = xs->kind[k];
   }
   C.n_chan = nc;
+  C.ncp = ncp;
   C.n_grid = ng;
   C.fixed = xs->fixed_prob ? 1 : 0;
   C.log_emin = (R)std::log(xs->energies[0]);

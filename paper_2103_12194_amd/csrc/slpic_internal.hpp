@@ -177,14 +177,17 @@ struct Ctx {
   uint32_t* inst_err;        // [n_inst], sticky
   Global* g;
   const R* xs_e;             // [n_grid] node energies
-  const R* xs_sig;           // [n_grid][n_chan]
-  const R* xs_thr;           // [n_chan]
-  const int32_t* xs_kind;    // [n_chan]
+  const R* xs_sig;           // [n_grid][2][ncp]: each node's cross sections,
+                             // then their changes to the next node (zero
+                             // past n_chan and at the last node)
+  const R* xs_thr;           // [MAX_CHAN] thresholds (+inf past n_chan)
+  const int32_t* xs_kind;    // [MAX_CHAN]
   R log_emin, inv_dlog;      // log-uniform grid index
   R log2_ratio, ratio_m1;    // log2 of the node ratio g, and g - 1
   R e_lo, e_hi;              // first and last node energies
   double ion_B;
   int n_chan, n_grid;
+  int ncp;                   // channels per table row: 4 or MAX_CHAN
   int n_inst, total_nodes, grid, max_tiles;
   int fixed;
   uint32_t flags, seed;

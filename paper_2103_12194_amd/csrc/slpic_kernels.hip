@@ -121,14 +121,20 @@ struct U4 {
   uint32_t x, y, z, w;
 };
 
+// a ^ b ^ c in one instruction: gfx950's three-input bitwise operation
+// with the truth table of XOR (0x96 for the operand bytes 0xf0, 0xcc, 0xaa)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                      uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-    c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+    c2 = xor3((uint32_t)(p0 >> 32), c3, k1);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     k0 += 0x9E3779B9u;
@@ -406,13 +412,49 @@ __device__ __forceinline__ T chan_entry(const T* table, int k) {
   return ((CT*)table)[k];
 }
 
+// Running sum over the NB channels of a table row (loaded at once, so
+// that the collision waits for one memory access rather than one per
+// channel); also picks the kind and threshold of the chosen channel from
+// the uniform per-channel entries.
+template <typename R, int NB, typename F>
+__device__ __forceinline__ int sum_channels(const Ctx<R>& C, const R* row, R eps, R t, R scale,
+                                            F target_of, R& cum, int& kind, R& thr) {
+  R a[NB], d[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    a[k] = row[k];
+    d[k] = row[NB + k];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  const R target = target_of();
+  int ch = -1;
+  R sum = R(0);
+  kind = 0;
+  thr = R(0);
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const R tk = chan_entry(C.xs_thr, k);
+    const R v = eps < tk ? R(0) : a[k] + t * d[k];
+    sum += scale * v;
+    if (ch < 0 && target < sum) {
+      ch = k;
+      kind = chan_entry(C.xs_kind, k);
+      thr = tk;
+    }
+  }
+  cum = sum;
+  return ch;
+}
+
 // Channel choice of a collision candidate: the first channel k with
 // target < sum_{q<=k} n_g sigma_q(eps) slow, where sigma_q is interpolated
 // linearly between log-uniform nodes and is zero below the channel's
-// threshold.  Returns -1 for a null collision; cum receives the full sum.
-template <typename R>
-__device__ __forceinline__ int select_channel(const Ctx<R>& C, R eps, R scale, R target, R& cum) {
-  const int n = C.n_grid, nc = C.n_chan;
+// threshold.  Returns -1 for a null collision; cum receives the full sum,
+// kind and thr the chosen channel's kind and threshold.
+template <typename R, typename F>
+__device__ __forceinline__ int select_channel(const Ctx<R>& C, R eps, R scale, F target, R& cum,
+                                              int& kind, R& thr) {
+  const int n = C.n_grid;
   // segment [i, i+1] holding eps, and the position t in it
   int i;
   R t;
@@ -445,17 +487,11 @@ __device__ __forceinline__ int select_channel(const Ctx<R>& C, R eps, R scale, R
     else if (!(eps < e1) && ic < n - 2) { i = ic + 1; el = e1; eh = ep; }
     t = Fm<R>::div(eps - el, eh - el);
   }
-  const R* a = C.xs_sig + (size_t)i * nc;
-  const R* b = a + nc;
-  int ch = -1;
-  R sum = R(0);
-  for (int k = 0; k < nc; ++k) {
-    const R v = eps < chan_entry(C.xs_thr, k) ? R(0) : a[k] + t * (b[k] - a[k]);
-    sum += scale * v;
-    if (ch < 0 && target < sum) ch = k;
-  }
-  cum = sum;
-  return ch;
+  // the node's row: values, then changes to the next node (padding
+  // channels have zero cross sections and an infinite threshold)
+  if (C.ncp == 4) return sum_channels<R, 4>(C, C.xs_sig + (size_t)i * 8, eps, t, scale, target, cum, kind, thr);
+  return sum_channels<R, MAX_CHAN>(C, C.xs_sig + (size_t)i * (2 * MAX_CHAN), eps, t, scale, target,
+                                   cum, kind, thr);
 }
 
 template <typename R>
@@ -1295,39 +1331,44 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
 template <typename R, bool WS>
 __device__ void collide_electron(const Ctx<R>& C, IP& P, int inst, uint32_t step,
                                  Mk<R>& m, LaneOut<R, WS>& o, uint32_t& ev, uint32_t& err) {
-  const U4 r = draw(m.id, step, CH_COLL, C.seed, P.key);
+  U4 r;
   const R v2 = m.vx * m.vx + m.vy * m.vy + m.vz * m.vz;
   const R eps = v2 * (R)(0.5 * ME / QE);
   const bool split = WS && P.f_e < 1.0;
-  int ch = -1;
+  int ch = -1, kind = 0;
+  R thr = R(0);
   if (C.fixed) {
+    r = draw(m.id, step, CH_COLL, C.seed, P.key);
     // whole markers: channel from the candidate's own word; split: from
     // the second word, with probability fixed_k / (their sum)
     const uint32_t u = (split ? r.y : r.x) >> 9;
     for (int q = 0; q < C.n_chan; ++q)
       if (ch < 0 && u < (split ? P.t_fsplit[q] : P.t_fixed[q])) ch = q;
-  } else {
-    const R sp0 = Fm<R>::sqrt(v2);
-    const R v0 = PR(P, v0);
-    const R slow = P.limited ? (sp0 < v0 ? sp0 : v0) : sp0;
-    const R numax = PR(P, nu_max_e);
-    R cum;
-    ch = select_channel(C, eps, PR(P, n_g) * slow, unif<R>(r.y) * numax, cum);
-    if (cum > numax * R(1.000001)) err |= ERR_NU_BOUND;
-  }
-  o.e[0] = m;
-  o.me = 1u;
-  if (ch >= 0) {
-    // kind and threshold of the lane's channel, picked from the uniform
-    // per-channel entries (no dependent per-lane load)
-    int kind = 0;
-    R thr = R(0);
+    // its kind and threshold, picked from the uniform per-channel entries
+    // (no dependent per-lane load)
     for (int q = 0; q < C.n_chan; ++q) {
       const int kq = chan_entry(C.xs_kind, q);
       const R tq = chan_entry(C.xs_thr, q);
       kind = q == ch ? kq : kind;
       thr = q == ch ? tq : thr;
     }
+  } else {
+    const R sp0 = Fm<R>::sqrt(v2);
+    const R v0 = PR(P, v0);
+    const R slow = P.limited ? (sp0 < v0 ? sp0 : v0) : sp0;
+    const R numax = PR(P, nu_max_e);
+    R cum;
+    // the draw runs while the cross-section row is loaded
+    auto target = [&]() {
+      r = draw(m.id, step, CH_COLL, C.seed, P.key);
+      return unif<R>(r.y) * numax;
+    };
+    ch = select_channel(C, eps, PR(P, n_g) * slow, target, cum, kind, thr);
+    if (cum > numax * R(1.000001)) err |= ERR_NU_BOUND;
+  }
+  o.e[0] = m;
+  o.me = 1u;
+  if (ch >= 0) {
     R hx, hy, hz, ox, oy, oz;
     unit3(m.vx, m.vy, m.vz, hx, hy, hz);
     // ionization: share eps - I between the scattered and the ejected
