@@ -185,11 +185,12 @@ __device__ __forceinline__ void normals3(U4 r, R sigma, R& a, R& b, R& c) {
 // cancellation for short intervals (q = p + len, W(u) = sqrt(u^2 + c^2)):
 //   q W(q) - p W(p) = len (q + p)(q^2 + p^2 + c^2) / (q W(q) + p W(p)),
 //   asinh(q/c) - asinh(p/c) = asinh(len (q + p) / (q W(p) + p W(q))).
+// Wp = W(p) and Wq = W(q) come from the caller: the span ends are the
+// flight's ends, 0 or the speed-limit point, whose W are known there.
 template <typename R>
-__device__ __forceinline__ R sqrt_span(R p, R len, R c) {
+__device__ __forceinline__ R sqrt_span(R p, R len, R c, R Wp, R Wq) {
   const R q = p + len, sq = p + q;
   const R c2 = c * c;
-  const R Wp = Fm<R>::sqrt(p * p + c2), Wq = Fm<R>::sqrt(q * q + c2);
   const R den1 = q * Wq + p * Wp, den2 = q * Wp + p * Wq;
   const bool empty = !(len > R(0)) || !(den1 > R(0));
   const R t1 = empty ? R(0) : Fm<R>::div(len * sq * (q * q + p * p + c2), den1);
@@ -198,30 +199,32 @@ __device__ __forceinline__ R sqrt_span(R p, R len, R c) {
 }
 
 // Integral of max(1, W(u)/v0) over [p, p + len] for p >= 0, where |v| < v0
-// (beta = 1) below u = ss: a linear part and one square-root part.
+// (beta = 1) below u = ss: a linear part and one square-root part.  Wp and
+// Wq are W(p) and W(p + len); W(ss) = v0.
 template <typename R>
-__device__ __forceinline__ R half_span(R p, R len, R c, R inv_v0, R ss) {
+__device__ __forceinline__ R half_span(R p, R len, R c, R inv_v0, R ss, R v0, R Wp, R Wq) {
   const R q = p + len;
   const bool split = p < ss;
   const R e = q < ss ? q : ss;                 // end of the linear part
   const R lin = split ? e - p : R(0);
   const R start = split ? e : p;
   R rest = split ? q - e : len;                // keeps len exact when unsplit
-  rest = rest > R(0) ? rest : R(0);
-  return lin + sqrt_span(start, rest, c) * inv_v0;
+  rest = rest > R(0) ? rest : R(0);            // (zero when q < ss)
+  return lin + sqrt_span(start, rest, c, split ? v0 : Wp, Wq) * inv_v0;
 }
 
 // Wall-clock time (times |a|) for s to move from s0 to s0 + len: the
 // integral of max(1, |v|/v0) ds, split at s = 0 by symmetry.  The second
-// half span is taken only when s crosses 0 (rare; it would add +0).
+// half span is taken only when s crosses 0 (rare; it would add +0).  w0 and
+// w1 are |v| at the two ends, W(s0) and W(s0 + len); W(0) = c.
 template <typename R>
-__device__ __forceinline__ R time_span(R s0, R len, R c, R inv_v0, R ss) {
+__device__ __forceinline__ R time_span(R s0, R len, R c, R inv_v0, R ss, R v0, R w0, R w1) {
   const R s1 = s0 + len;
   const bool pos = s0 >= R(0), neg = !(s1 > R(0));
   const R p1 = pos ? s0 : (neg ? -s1 : R(0));
   const R l1 = (pos || neg) ? len : -s0;
-  R t = half_span(p1, l1, c, inv_v0, ss);
-  if (!(pos || neg)) t += half_span(R(0), s1, c, inv_v0, ss);
+  R t = half_span(p1, l1, c, inv_v0, ss, v0, pos ? w0 : (neg ? w1 : c), pos ? w1 : w0);
+  if (!(pos || neg)) t += half_span(R(0), s1, c, inv_v0, ss, v0, c, w1);
   return t;
 }
 
@@ -276,16 +279,17 @@ __device__ void flight(R vx, R c, R a, R dt, R v0, R inv_v0, int limited, R& dis
     // a Halley step of relative size e leaves an error of order e^3
     const R quick = sizeof(R) == 4 ? R(2e-3) : R(1e-8);
     for (int it = 0; it < 40; ++it) {
-      const R f = time_span(s0, delta, c, inv_v0, ss) - rhs;
+      const R s = s0 + delta;
+      const R W = Fm<R>::sqrt(s * s + c * c);  // |v| at the end of the flight
+      const R f = time_span(s0, delta, c, inv_v0, ss, v0, w0, W) - rhs;
       if (f > R(0)) hi = delta;
       else if (f < R(0)) lo = delta;
       else break;
-      const R s = s0 + delta;
-      const R W = Fm<R>::sqrt(s * s + c * c);
       R step;
       if (W > v0) {
-        const R hp = W * inv_v0, hpp = Fm<R>::div(s * inv_v0, W);
-        step = Fm<R>::div(R(-2) * f * hp, R(2) * hp * hp - f * hpp);
+        // -2 f f' / (2 f'^2 - f f'') with f'' = s / (v0 W), over W
+        const R hp = W * inv_v0;
+        step = Fm<R>::div(R(-2) * f * hp * W, R(2) * hp * hp * W - f * s * inv_v0);
       } else {
         step = -f;
       }
