@@ -9,6 +9,10 @@ MCC (elastic, excitation, ionization with spawn; ion charge exchange),
 ion-induced secondary emission, population control, deposit and the Poisson
 solve over every instance.  Markers start from the seeded state (uniform in
 the first cell, kT_e = 1 eV) and are resident in HBM before timing starts.
+The seeds take about EVOLVE = 200 steps to spread over their gaps, so when
+the warmup is shorter the sweep first takes EVOLVE - W untimed steps (the
+line's config names them): the timed steps always see the evolved sweep,
+whatever W is.  The plain leg takes the same steps before its timing.
 
 Prints one JSON line:
   value       particle-steps/s = sum over timed steps and instances of the
@@ -48,6 +52,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 BYTES_PER_MARKER_STEP = 56.0      # 28-byte FP32 record in + out
+EVOLVE = 200                      # steps for the seeded sweep to spread over its gaps
 HBM_PEAK_GBS = 8000.0             # MI355X HBM3E
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_gen_c4_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2103_12194_amd", "csrc", f)
@@ -380,9 +385,13 @@ def main():
     sim = slpic.Sim(w.instances, w.run, xs)
     default_shape = sim.launch_shape() + (sim.work_distribution(),)
     apply_shape(sim, shape)
+    # untimed steps that let the seeds spread over their gaps, then the warmup
+    evolve = max(0, EVOLVE - args.warmup)
+    sim.step(evolve)
     sim.step(args.warmup)
     sim.sync()
-    print(f"# warmup {args.warmup} steps done", file=sys.stderr, flush=True)
+    print(f"# {evolve} evolution steps and {args.warmup} warmup steps done", file=sys.stderr,
+          flush=True)
     # the timed steps: graph replay (captured here, outside the timed region)
     sim.use_graph(True)
     s0, secs, _ = time_steps(sim, args.steps, profile=False)
@@ -418,7 +427,7 @@ def main():
 
     plain = None
     if not args.no_plain:
-        pps, psecs = plain_leg(w, xs, args.steps, args.warmup)
+        pps, psecs = plain_leg(w, xs, args.steps, evolve + args.warmup)
         plain = {"value": pps / psecs, "unit": "particle-steps/s",
                  "ms_per_step_all_instances": psecs * 1e3 / args.steps,
                  "batched_over_plain": value / (pps / psecs)}
@@ -446,7 +455,9 @@ def main():
                                "1e4-2e6 target markers each; FP32 particles, "
                                "FP64 Poisson and totals; one launch pair per step",
                    "n_inst": len(w.instances), "marker_scale": args.scale,
-                   "markers_per_step": n_markers, "parallelism": "none (1 GPU)"},
+                   "markers_per_step": n_markers, "parallelism": "none (1 GPU)",
+                   "initial_state": "seeded in each gap's first cell (1 eV Maxwellian)",
+                   "untimed_steps_before_warmup": evolve},
         "roofline": roofline, "plain": plain, "eager": eager,
         "launch_shape": {"grid": shape[0], "waves_per_simd": shape[1],
                          "claimed_runs": shape[2], "autotuned": True,
