@@ -85,6 +85,7 @@ def lib():
         L.or_flux.argtypes = [vp, C.c_int, vp]
         L.or_flux_reset.argtypes = [vp]
         L.or_set_source.argtypes = [vp, C.c_double]
+        L.or_set_clock.argtypes = [vp, C.c_uint32, C.c_double]
         L.or_scalars.argtypes = [vp, vp]
         L.or_min_margin.restype = C.c_double
         L.or_min_margin.argtypes = [vp]
@@ -271,6 +272,12 @@ class Sim:
         initial flux weight (electrons at rest at x = 0); 0 switches it off."""
         if lib().or_set_source(self.h, float(per_step)) != 0:
             raise ValueError(f"source rate {per_step} outside [0, 2^24]")
+
+    def set_clock(self, step, w_j):
+        """Continue a run from its step counter (which keys the draws) and
+        flux weight w_j; the field is re-solved from the markers present."""
+        if lib().or_set_clock(self.h, int(step), float(w_j)) != 0:
+            raise ValueError(f"flux weight {w_j} must be finite and positive")
 
     def stats(self):
         row = np.zeros(NSTAT)

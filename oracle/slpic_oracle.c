@@ -1005,6 +1005,14 @@ int or_set_source(or_sim* s, double per_step) {
   return 0;
 }
 
+int or_set_clock(or_sim* s, uint32_t step, double w_j) {
+  if (!(w_j > 0.0 && w_j < INFINITY)) return -1;
+  s->step = step;
+  s->w_j = w_j;
+  deposit_and_solve(s);
+  return 0;
+}
+
 void or_flux_reset(or_sim* s) {
   for (int sp = 0; sp < 2; ++sp)
     memset(s->flux[sp], 0, ((size_t)s->p.cells + 1) * sizeof(double));

@@ -128,6 +128,11 @@ void or_flux_reset(or_sim* s);
  * population control.  Returns -1 (and changes nothing) unless per_step is
  * finite and in [0, 2^24]; 0 switches the source off. */
 int or_set_source(or_sim* s, double per_step);
+/* Takes over an instance mid-run: the step counter (which keys every draw)
+ * and the flux weight w_j that a run reached, then the charge density and
+ * field of the markers present (as or_load leaves them).  Returns -1 (and
+ * changes nothing) unless w_j is finite and positive. */
+int or_set_clock(or_sim* s, uint32_t step, double w_j);
 /* statistics of the last step, OR_NSTAT doubles */
 void or_last_stats(const or_sim* s, double* row);
 /* derived scalars: dx, dt, v0, n_g, nu_max_e, nu_max_cx, w_j, step */
