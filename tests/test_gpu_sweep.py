@@ -1,18 +1,20 @@
-"""The batched Paschen sweep at its full size (64 argon gaps, 128-4096 cells,
-2.5e7 target markers), in the launch shape bench.py times (the library's
-default: claimed runs, five waves per SIMD), on the evolved state after 200
-steps.
+"""The workloads at their full sizes, in the launch shape bench.py times
+(the library's default: claimed runs where a launch has four tiles per
+workgroup or more, five waves per SIMD), each on its evolved state after the
+bench's warmup: the 64-instance Paschen sweep (2.5e7 target markers), the
+256-instance bisection round (1.8e8), the 4096-cell gap with its cell sort
+every 16 steps (1e7) and the 512-cell gap (1e6).
 
 - Every instance keeps the marker balance of the events it reports, step by
   step (entering - absorbed + 2 ionizations + emissions - roulette + splits
   = leaving), with no error flags.
-- Sampled instances (the smallest, two middle and the largest by markers)
-  are taken over by the FP64 oracle at the GPU's step counter and flux
-  weight (Philox draws are keyed by marker id, step and channel) and both
-  take one step: states within 1e-5 (positions relative to the gap),
-  decisions with a margin below 1e-6 excused (at most 1 in 1000 markers),
-  counts equal up to the excused markers, charge density and field within
-  1e-6 of their largest magnitude.
+- Sampled instances (from the smallest to the largest by markers) are taken
+  over by the FP64 oracle at the GPU's step counter and flux weight (Philox
+  draws are keyed by marker id, step and channel) and both take one step:
+  states within 1e-5 (positions relative to the gap), decisions with a
+  margin below 1e-6 excused (at most 1 in 1000 markers), counts equal up to
+  the excused markers, charge density and field within 1e-6 of their
+  largest magnitude.
 """
 
 import dataclasses
@@ -33,20 +35,28 @@ if not torch.cuda.is_available():
 
 import paper_2103_12194_amd as slpic  # noqa: E402
 
-EVOLVE = 200
 BOOK_STEPS = 8
 
+# workload, the bench's warmup, sampled instances
+CASES = {
+    "sweep64": (lambda xs: configs.c4(xs.sigma_total_max(), precision=32), 200, 4),
+    "bisection256": (lambda xs: configs.c5(xs.sigma_total_max(), precision=32), 100, 3),
+    "gap4096_sorted": (lambda xs: configs.c3(), 2048, 1),
+    "gap512": (lambda xs: configs.c2(300.0), 200, 1),
+}
 
-def test_sweep_at_full_size_sampled_against_the_oracle():
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_full_size_workload_sampled_against_the_oracle(case):
+    make, warm, n_pick = CASES[case]
     xs = synth.argon_like()
-    w = configs.c4(xs.sigma_total_max(), precision=32)
+    w = make(xs)
     n_inst = len(w.instances)
-    print(f"full C4 sweep: {n_inst} instances, "
-          f"{sum(i.n_target for i in w.instances):.3e} target markers", flush=True)
+    targets = sum(i.n_target for i in w.instances)
+    print(f"{case}: {n_inst} instances, {targets:.3e} target markers", flush=True)
     gpu = slpic.Sim(w.instances, w.run, xs)
-    assert gpu.work_distribution() == 1
-    print("launch shape", gpu.launch_shape(), flush=True)
-    gpu.step(EVOLVE)
+    print("launch shape", gpu.launch_shape(), "claimed runs", gpu.work_distribution(), flush=True)
+    gpu.step(warm)
     assert gpu.sync() == 0
     s0 = gpu.steps_done()
     gpu.step(BOOK_STEPS)
@@ -61,12 +71,12 @@ def test_sweep_at_full_size_sampled_against_the_oracle():
         assert np.all(h["err"] == 0), k
         total += int(h["n_in"][-1])
     print(f"markers entering the last step: {total:.3e}", flush=True)
-    assert total > 1.5e7
+    assert total > 0.3 * targets
 
     # the sampled instances, taken over by the oracle
     counts = [gpu.count(0, k) + gpu.count(1, k) for k in range(n_inst)]
     order = np.argsort(counts)
-    picks = [int(order[0]), int(order[n_inst // 3]), int(order[2 * n_inst // 3]), int(order[-1])]
+    picks = sorted({int(order[round(j * (n_inst - 1) / max(1, n_pick - 1))]) for j in range(n_pick)})
     run64 = dataclasses.replace(w.run, precision=64)
     refs = {}
     for k in picks:
@@ -92,7 +102,7 @@ def test_sweep_at_full_size_sampled_against_the_oracle():
                                     v0, tie_tol=1e-6, max_tied=max(1, n // 1000),
                                     label=f"inst {k} sp {sp}")
             tied += r["tied"]
-            print("full C4", k, sp, {q: r[q] for q in ("n", "tied", "x_cells", "vx", "vy", "vz")},
+            print(case, k, sp, {q: r[q] for q in ("n", "tied", "x_cells", "vx", "vy", "vz")},
                   flush=True)
         sg, so = gpu.stats(inst=k), refs[k].stats()
         for key in STAT_INT:
