@@ -419,7 +419,9 @@ __device__ __forceinline__ T chan_entry(const T* table, int k) {
 // Running sum over the NB channels of a table row (loaded at once, so
 // that the collision waits for one memory access rather than one per
 // channel); also picks the kind and threshold of the chosen channel from
-// the uniform per-channel entries.
+// the uniform per-channel entries.  target_of() gives the target: it runs
+// after the row's loads are issued, so that work it does (the candidate's
+// draw) overlaps them.
 template <typename R, int NB, typename F>
 __device__ __forceinline__ int sum_channels(const Ctx<R>& C, const R* row, R eps, R t, R scale,
                                             F target_of, R& cum, int& kind, R& thr) {
@@ -454,7 +456,8 @@ __device__ __forceinline__ int sum_channels(const Ctx<R>& C, const R* row, R eps
 // target < sum_{q<=k} n_g sigma_q(eps) slow, where sigma_q is interpolated
 // linearly between log-uniform nodes and is zero below the channel's
 // threshold.  Returns -1 for a null collision; cum receives the full sum,
-// kind and thr the chosen channel's kind and threshold.
+// kind and thr the chosen channel's kind and threshold.  target() returns
+// the target (called once, after the table row is requested).
 template <typename R, typename F>
 __device__ __forceinline__ int select_channel(const Ctx<R>& C, R eps, R scale, F target, R& cum,
                                               int& kind, R& thr) {
