@@ -272,13 +272,60 @@ __device__ void flight(R vx, R c, R a, R dt, R v0, R inv_v0, int limited, R& dis
       const R sy = ay <= v0 ? ay : Fm<R>::sqrt(R(2) * v0 * ay - v0 * v0);
       delta = (y < R(0) ? -sy : sy) - s0;
     }
-    if (!(delta > lo && delta < hi)) delta = rhs * (w0 > v0 ? v0 / w0 : R(1));
+    const bool guessed = delta > lo && delta < hi;
+    if (!guessed) delta = rhs * (w0 > v0 ? v0 / w0 : R(1));
+    bool solved = false;
+    if (sizeof(R) == 4) {
+      // Fully speed-limited flight (|v| > v0 all along, as for nearly every
+      // limited electron): the path length in s is w0^2 F(delta / w0) with
+      // F(r) = int_0^r sqrt(1 + 2 p u + u^2) du, p = s0 / w0.  The Taylor
+      // coefficients of the integrand are the Gegenbauer polynomials
+      // C_n^(-1/2)(-p): g_0 = 1, g_1 = p, g_2 = (1 - p^2) / 2 and
+      // n g_n = -(2n - 3) p g_(n-1) - (n - 3) g_(n-2), each at most
+      // 2 / (2n - 1) in magnitude, so for r <= 0.2 eight terms of F leave
+      // under 1e-7 of it.  F' = sqrt(1 + 2 p r + r^2) and F'' = (p + r) / F'
+      // in closed form; one Halley step from the guess (within 2e-3) then
+      // reaches FP32 rounding, without the spans' square roots and
+      // logarithm (a 1 % margin on the guess covers its error).  Only the
+      // series guess qualifies (not the fallback above), and a step larger
+      // than the guess's error (0.4 %) sends the marker to the iteration
+      // below.  The choice is the marker's own, never its wave's: a result
+      // must not depend on which markers share a wave.  A wave whose lanes
+      // all qualify skips the iteration.
+      const R sN = s0 + R(1.01) * delta;
+      const bool ok = guessed && w0 > v0 && sN * sN + c * c > v0 * v0 &&
+                      !(s0 < R(0) && sN > R(0) && !(c > v0)) && delta < R(0.2) * w0;
+      if (ok) {
+        const R iw = Fm<R>::div(R(1), w0);
+        const R p = s0 * iw, cq = c * iw, r0 = delta * iw;
+        constexpr int NT = 8;
+        R gn[NT];
+        gn[0] = R(1);
+        gn[1] = p;
+        gn[2] = R(0.5) * cq * cq;
+#pragma unroll
+        for (int n = 3; n < NT; ++n)
+          gn[n] = R(-(2.0 * n - 3.0) / n) * p * gn[n - 1] - R((n - 3.0) / n) * gn[n - 2];
+        R F = gn[NT - 1] * R(1.0 / NT);
+#pragma unroll
+        for (int n = NT - 2; n >= 0; --n) F = F * r0 + gn[n] * R(1.0 / (n + 1));
+        F *= r0;
+        const R S = Fm<R>::sqrt(R(1) + r0 * (R(2) * p + r0));  // F'(r0)
+        const R f = F - v0 * rhs * iw * iw;
+        // Halley: -2 f F' / (2 F'^2 - f F''), over F'
+        const R step = Fm<R>::div(R(2) * f * S * S, R(2) * S * S * S - f * (p + r0));
+        if ((step < R(0) ? -step : step) <= R(4e-3) * r0) {
+          delta = (r0 - step) * w0;
+          solved = true;
+        }
+      }
+    }
     // Halley iteration on f(delta) = time_span - rhs, f' = max(1, W/v0),
     // f'' = s / (v0 W) where W > v0, kept inside the bracket [lo, hi]
     const R tol = sizeof(R) == 4 ? R(1e-7) : R(1e-16);
     // a Halley step of relative size e leaves an error of order e^3
     const R quick = sizeof(R) == 4 ? R(2e-3) : R(1e-8);
-    for (int it = 0; it < 40; ++it) {
+    for (int it = 0; it < 40 && !solved; ++it) {
       const R s = s0 + delta;
       const R W = Fm<R>::sqrt(s * s + c * c);  // |v| at the end of the flight
       const R f = time_span(s0, delta, c, inv_v0, ss, v0, w0, W) - rhs;
