@@ -251,58 +251,43 @@ __device__ void flight(R vx, R c, R a, R dt, R v0, R inv_v0, int limited, R& dis
     const R sg = a > R(0) ? R(1) : R(-1);
     const R at = a * sg, s0 = sg * vx;
     const R rhs = at * dt;
-    const R ss = c < v0 ? Fm<R>::sqrt(v0 * v0 - c * c) : R(0);
     const R w0 = Fm<R>::sqrt(w0sq);
-    R lo = R(0), hi = rhs, delta;
-    if (w0 > v0) {
-      // speed-limited start: the path length in s, integral of W = |v| over
-      // [s0, s0 + d], is w0 d + s0 d^2 / (2 w0) + c^2 d^3 / (6 w0^3) + ...;
-      // solve the quadratic, then one Newton step adds the cubic term
-      const R disc = w0 * w0 + R(2) * s0 * v0 * Fm<R>::div(rhs, w0);
-      delta = disc > R(0) ? Fm<R>::div(R(2) * v0 * rhs, w0 + Fm<R>::sqrt(disc)) : R(-1);
-      const R iw = Fm<R>::div(R(1), w0);
-      const R cub = c * c * iw * iw * iw * (R(1) / R(6)) * delta * delta * delta;
-      delta -= Fm<R>::div(cub, w0 + s0 * iw * delta);
-    } else {
-      // slow start: the c = 0 motion (beta = 1 up to v0, then v0 ds = s ds)
-      const R as = s0 < R(0) ? -s0 : s0;
-      R y = as <= v0 ? as : (as * as + v0 * v0) * R(0.5) * inv_v0;
-      y = (s0 < R(0) ? -y : y) + rhs;
-      const R ay = y < R(0) ? -y : y;
-      const R sy = ay <= v0 ? ay : Fm<R>::sqrt(R(2) * v0 * ay - v0 * v0);
-      delta = (y < R(0) ? -sy : sy) - s0;
-    }
-    const bool guessed = delta > lo && delta < hi;
-    if (!guessed) delta = rhs * (w0 > v0 ? v0 / w0 : R(1));
+    R delta = R(0);
     bool solved = false;
     if (sizeof(R) == 4) {
       // Fully speed-limited flight (|v| > v0 all along, as for nearly every
       // limited electron): the path length in s is w0^2 F(delta / w0) with
-      // F(r) = int_0^r sqrt(1 + 2 p u + u^2) du, p = s0 / w0.  The Taylor
-      // coefficients of the integrand are the Gegenbauer polynomials
-      // C_n^(-1/2)(-p): g_0 = 1, g_1 = p, g_2 = (1 - p^2) / 2 and
-      // n g_n = -(2n - 3) p g_(n-1) - (n - 3) g_(n-2), each at most
-      // 2 / (2n - 1) in magnitude, so for r <= 0.2 eight terms of F leave
-      // under 1e-7 of it.  F' = sqrt(1 + 2 p r + r^2) and F'' = (p + r) / F'
-      // in closed form; one Halley step from the guess (within 2e-3) then
-      // reaches FP32 rounding, without the spans' square roots and
-      // logarithm (a 1 % margin on the guess covers its error).  Only the
-      // series guess qualifies (not the fallback above), and a step larger
-      // than the guess's error (0.4 %) sends the marker to the iteration
-      // below.  The choice is the marker's own, never its wave's: a result
+      // F(r) = int_0^r sqrt(1 + 2 p u + u^2) du, p = s0 / w0, q = c / w0,
+      // and F(r) = R = v0 |a| dt / w0^2.  The Taylor coefficients of the
+      // integrand are the Gegenbauer polynomials C_n^(-1/2)(-p): g_0 = 1,
+      // g_1 = p, g_2 = q^2 / 2 and n g_n = -(2n - 3) p g_(n-1) - (n - 3)
+      // g_(n-2), each at most 2 / (2n - 1) in magnitude, so for r <= 0.2
+      // eight terms of F leave under 1e-7 of it.  The guess is the series
+      // reversion to fourth order, r = R - (p/2) R^2 + (p^2/2 - q^2/6) R^3 +
+      // (13 p q^2 / 24 - 5 p^3 / 8) R^4 (within 2e-3 for R < 0.25); with
+      // F' = sqrt(1 + 2 p r + r^2) and F'' = (p + r) / F' in closed form,
+      // one Halley step then reaches FP32 rounding, without square roots or
+      // logarithms of the spans.  A step larger than the guess's error
+      // (0.4 %) sends the marker to the iteration below, as does a flight
+      // that would reach |v| <= v0 (a 1 % margin on the guess covers its
+      // error).  The choice is the marker's own, never its wave's: a result
       // must not depend on which markers share a wave.  A wave whose lanes
       // all qualify skips the iteration.
-      const R sN = s0 + R(1.01) * delta;
-      const bool ok = guessed && w0 > v0 && sN * sN + c * c > v0 * v0 &&
-                      !(s0 < R(0) && sN > R(0) && !(c > v0)) && delta < R(0.2) * w0;
+      const R iw = Fm<R>::div(R(1), w0);
+      const R p = s0 * iw, cq = c * iw, q2 = cq * cq;
+      const R Rt = v0 * rhs * iw * iw;
+      const R b2 = R(-0.5) * p, b3 = R(0.5) * p * p - q2 * R(1.0 / 6.0);
+      const R b4 = p * (q2 * R(13.0 / 24.0) - p * p * R(5.0 / 8.0));
+      const R r0 = Rt * (R(1) + Rt * (b2 + Rt * (b3 + Rt * b4)));
+      const R sN = s0 + R(1.01) * r0 * w0;
+      const bool ok = w0 > v0 && Rt < R(0.25) && r0 > R(0) && r0 < R(0.2) &&
+                      sN * sN + c * c > v0 * v0 && !(s0 < R(0) && sN > R(0) && !(c > v0));
       if (ok) {
-        const R iw = Fm<R>::div(R(1), w0);
-        const R p = s0 * iw, cq = c * iw, r0 = delta * iw;
         constexpr int NT = 8;
         R gn[NT];
         gn[0] = R(1);
         gn[1] = p;
-        gn[2] = R(0.5) * cq * cq;
+        gn[2] = R(0.5) * q2;
 #pragma unroll
         for (int n = 3; n < NT; ++n)
           gn[n] = R(-(2.0 * n - 3.0) / n) * p * gn[n - 1] - R((n - 3.0) / n) * gn[n - 2];
@@ -311,7 +296,7 @@ __device__ void flight(R vx, R c, R a, R dt, R v0, R inv_v0, int limited, R& dis
         for (int n = NT - 2; n >= 0; --n) F = F * r0 + gn[n] * R(1.0 / (n + 1));
         F *= r0;
         const R S = Fm<R>::sqrt(R(1) + r0 * (R(2) * p + r0));  // F'(r0)
-        const R f = F - v0 * rhs * iw * iw;
+        const R f = F - Rt;
         // Halley: -2 f F' / (2 F'^2 - f F''), over F'
         const R step = Fm<R>::div(R(2) * f * S * S, R(2) * S * S * S - f * (p + r0));
         if ((step < R(0) ? -step : step) <= R(4e-3) * r0) {
@@ -320,37 +305,61 @@ __device__ void flight(R vx, R c, R a, R dt, R v0, R inv_v0, int limited, R& dis
         }
       }
     }
-    // Halley iteration on f(delta) = time_span - rhs, f' = max(1, W/v0),
-    // f'' = s / (v0 W) where W > v0, kept inside the bracket [lo, hi]
-    const R tol = sizeof(R) == 4 ? R(1e-7) : R(1e-16);
-    // a Halley step of relative size e leaves an error of order e^3
-    const R quick = sizeof(R) == 4 ? R(2e-3) : R(1e-8);
-    for (int it = 0; it < 40 && !solved; ++it) {
-      const R s = s0 + delta;
-      const R W = Fm<R>::sqrt(s * s + c * c);  // |v| at the end of the flight
-      const R f = time_span(s0, delta, c, inv_v0, ss, v0, w0, W) - rhs;
-      if (f > R(0)) hi = delta;
-      else if (f < R(0)) lo = delta;
-      else break;
-      R step;
-      if (W > v0) {
-        // -2 f f' / (2 f'^2 - f f'') with f'' = s / (v0 W), over W
-        const R hp = W * inv_v0;
-        step = Fm<R>::div(R(-2) * f * hp * W, R(2) * hp * hp * W - f * s * inv_v0);
+    if (!solved) {
+      const R ss = c < v0 ? Fm<R>::sqrt(v0 * v0 - c * c) : R(0);
+      R lo = R(0), hi = rhs;
+      if (w0 > v0) {
+        // speed-limited start: the path length in s, integral of W = |v|
+        // over [s0, s0 + d], is w0 d + s0 d^2 / (2 w0) + c^2 d^3 / (6 w0^3)
+        // + ...; solve the quadratic, then one Newton step adds the cubic
+        // term
+        const R disc = w0 * w0 + R(2) * s0 * v0 * Fm<R>::div(rhs, w0);
+        delta = disc > R(0) ? Fm<R>::div(R(2) * v0 * rhs, w0 + Fm<R>::sqrt(disc)) : R(-1);
+        const R iw = Fm<R>::div(R(1), w0);
+        const R cub = c * c * iw * iw * iw * (R(1) / R(6)) * delta * delta * delta;
+        delta -= Fm<R>::div(cub, w0 + s0 * iw * delta);
       } else {
-        step = -f;
+        // slow start: the c = 0 motion (beta = 1 up to v0, then v0 ds = s ds)
+        const R as = s0 < R(0) ? -s0 : s0;
+        R y = as <= v0 ? as : (as * as + v0 * v0) * R(0.5) * inv_v0;
+        y = (s0 < R(0) ? -y : y) + rhs;
+        const R ay = y < R(0) ? -y : y;
+        const R sy = ay <= v0 ? ay : Fm<R>::sqrt(R(2) * v0 * ay - v0 * v0);
+        delta = (y < R(0) ? -sy : sy) - s0;
       }
-      R dn = delta + step;
-      const R astep = step < R(0) ? -step : step;
-      if (astep <= quick * delta) {
-        // converged to within step^2: take the step unless it leaves the
-        // bracket (possible when it is below the resolution of delta)
-        if (dn > lo && dn < hi) delta = dn;
-        break;
+      if (!(delta > lo && delta < hi)) delta = rhs * (w0 > v0 ? v0 / w0 : R(1));
+      // Halley iteration on f(delta) = time_span - rhs, f' = max(1, W/v0),
+      // f'' = s / (v0 W) where W > v0, kept inside the bracket [lo, hi]
+      const R tol = sizeof(R) == 4 ? R(1e-7) : R(1e-16);
+      // a Halley step of relative size e leaves an error of order e^3
+      const R quick = sizeof(R) == 4 ? R(2e-3) : R(1e-8);
+      for (int it = 0; it < 40; ++it) {
+        const R s = s0 + delta;
+        const R W = Fm<R>::sqrt(s * s + c * c);  // |v| at the end of the flight
+        const R f = time_span(s0, delta, c, inv_v0, ss, v0, w0, W) - rhs;
+        if (f > R(0)) hi = delta;
+        else if (f < R(0)) lo = delta;
+        else break;
+        R step;
+        if (W > v0) {
+          // -2 f f' / (2 f'^2 - f f'') with f'' = s / (v0 W), over W
+          const R hp = W * inv_v0;
+          step = Fm<R>::div(R(-2) * f * hp * W, R(2) * hp * hp * W - f * s * inv_v0);
+        } else {
+          step = -f;
+        }
+        R dn = delta + step;
+        const R astep = step < R(0) ? -step : step;
+        if (astep <= quick * delta) {
+          // converged to within step^2: take the step unless it leaves the
+          // bracket (possible when it is below the resolution of delta)
+          if (dn > lo && dn < hi) delta = dn;
+          break;
+        }
+        if (!(dn > lo && dn < hi)) dn = R(0.5) * (lo + hi);
+        delta = dn;
+        if (hi - lo <= tol * hi) break;
       }
-      if (!(dn > lo && dn < hi)) dn = R(0.5) * (lo + hi);
-      delta = dn;
-      if (hi - lo <= tol * hi) break;
     }
     tau = Fm<R>::div(delta, at);
     dv = sg * delta;
