@@ -360,7 +360,7 @@ def main():
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
               f"(instances of a sweep are independent and would be spread "
-              f"over GPUs by a launcher, which this build does not include)",
+              f"over GPUs by a launcher, which this package does not include)",
               file=sys.stderr)
         return 2
     import torch

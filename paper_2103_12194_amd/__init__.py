@@ -90,7 +90,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB):
-            raise SlpicError(-7, f"{LIB} is not built (run __graft_entry__.build())")
+            raise SlpicError(-7, f"{LIB} is not built (run paper_2103_12194_amd._build.build())")
         L = C.CDLL(LIB)
         vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int
         P = C.POINTER
