@@ -233,13 +233,17 @@ __device__ __forceinline__ R time_span(R s0, R len, R c, R inv_v0, R ss, R v0, R
 // new v_x and, when v_x changes sign inside the flight, the displacement of
 // the turning point.
 template <typename R>
-__device__ void flight(R vx, R c, R a, R dt, R v0, R inv_v0, int limited, R& disp, R& vx1,
+__device__ void flight(R vx, R c2, R a, R dt, R v0, R inv_v0, int limited, R& disp, R& vx1,
                        bool& turns, R& turn_disp) {
   R dv;  // change of v_x (= a tau)
   R tau;
-  const R w0sq = vx * vx + c * c;
+  // c = |v_perp| from c2 = v_y^2 + v_z^2: FP64 takes it at once (and c^2
+  // as c c); FP32 only where the iteration needs it, c^2 being c2
+  const R c64 = sizeof(R) == 8 ? Fm<R>::sqrt(c2) : R(0);
+  const R cc = sizeof(R) == 8 ? c64 * c64 : c2;
+  const R w0sq = vx * vx + cc;
   const R ve = vx + a * dt;
-  if (!limited || (w0sq <= v0 * v0 && ve * ve + c * c <= v0 * v0)) {
+  if (!limited || (w0sq <= v0 * v0 && ve * ve + cc <= v0 * v0)) {
     tau = dt;  // beta == 1 along the whole flight
     dv = a * dt;
   } else if (a == R(0)) {
@@ -251,7 +255,10 @@ __device__ void flight(R vx, R c, R a, R dt, R v0, R inv_v0, int limited, R& dis
     const R sg = a > R(0) ? R(1) : R(-1);
     const R at = a * sg, s0 = sg * vx;
     const R rhs = at * dt;
-    const R w0 = Fm<R>::sqrt(w0sq);
+    // |v| at the start and, in FP32, its reciprocal by one reciprocal
+    // square root
+    const R iw32 = sizeof(R) == 4 ? (R)__builtin_amdgcn_rsqf((float)w0sq) : R(0);
+    const R w0 = sizeof(R) == 4 ? w0sq * iw32 : Fm<R>::sqrt(w0sq);
     R delta = R(0);
     bool solved = false;
     if (sizeof(R) == 4) {
@@ -273,15 +280,15 @@ __device__ void flight(R vx, R c, R a, R dt, R v0, R inv_v0, int limited, R& dis
       // error).  The choice is the marker's own, never its wave's: a result
       // must not depend on which markers share a wave.  A wave whose lanes
       // all qualify skips the iteration.
-      const R iw = Fm<R>::div(R(1), w0);
-      const R p = s0 * iw, cq = c * iw, q2 = cq * cq;
+      const R iw = iw32;
+      const R p = s0 * iw, q2 = cc * iw * iw;
       const R Rt = v0 * rhs * iw * iw;
       const R b2 = R(-0.5) * p, b3 = R(0.5) * p * p - q2 * R(1.0 / 6.0);
       const R b4 = p * (q2 * R(13.0 / 24.0) - p * p * R(5.0 / 8.0));
       const R r0 = Rt * (R(1) + Rt * (b2 + Rt * (b3 + Rt * b4)));
       const R sN = s0 + R(1.01) * r0 * w0;
       const bool ok = w0 > v0 && Rt < R(0.25) && r0 > R(0) && r0 < R(0.2) &&
-                      sN * sN + c * c > v0 * v0 && !(s0 < R(0) && sN > R(0) && !(c > v0));
+                      sN * sN + cc > v0 * v0 && !(s0 < R(0) && sN > R(0) && !(cc > v0 * v0));
       if (ok) {
         constexpr int NT = 8;
         R gn[NT];
@@ -306,6 +313,7 @@ __device__ void flight(R vx, R c, R a, R dt, R v0, R inv_v0, int limited, R& dis
       }
     }
     if (!solved) {
+      const R c = sizeof(R) == 8 ? c64 : Fm<R>::sqrt(c2);
       const R ss = c < v0 ? Fm<R>::sqrt(v0 * v0 - c * c) : R(0);
       R lo = R(0), hi = rhs;
       if (w0 > v0) {
@@ -1567,10 +1575,10 @@ __device__ __forceinline__ void advance(const Ctx<R>& C, IP& P, int inst, int sp
   asm volatile("" : "+v"(rnx));
   const R Ep = e0 + m.off * (e1 - e0);
   const R a = (sp == 0 ? PR(P, qm_e) : PR(P, qm_i)) * Ep;
-  const R c = Fm<R>::sqrt(m.vy * m.vy + m.vz * m.vz);
+  const R c2 = m.vy * m.vy + m.vz * m.vz;
   R disp, vx1, tdisp;
   bool turns;
-  flight<R>(m.vx, c, a, PR(P, dt), PR(P, v0), PR(P, inv_v0), P.limited, disp, vx1, turns, tdisp);
+  flight<R>(m.vx, c2, a, PR(P, dt), PR(P, v0), PR(P, inv_v0), P.limited, disp, vx1, turns, tdisp);
   const R inv_dx = PR(P, inv_dx);
   R f = m.off + disp * inv_dx;
   const R fl = m_floor(f);
