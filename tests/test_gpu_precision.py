@@ -106,3 +106,50 @@ def test_fp32_error_of_each_stage_against_the_fp64_oracle(xs_argon):
     assert errs["field E (deposit + Poisson)"] < 1e-5
     assert errs["total w_e"] < 1e-6 and errs["total w_i"] < 1e-6
     assert errs["collision outcomes differing / collisions"] < 1e-3
+
+
+def test_fp32_flight_across_speed_ratios():
+    """One collisionless FP32 step against the FP64 oracle for electrons from
+    just above to 1000 times the speed limit, in every direction, in the
+    vacuum field of a 256-cell gap: the FP32 flight's series path (markers
+    above v0 all along whose relative change of v is small) and its
+    iteration (the rest: slow markers, large changes, turning points) both
+    run, in the same waves, and every state agrees within 1e-5."""
+    cells = 256
+    gap = configs.Instance(d=0.01, p_torr=1.0, V=300.0, cells=cells, gamma_se=0.0,
+                           seed_mode=configs.SEED_NONE, capacity=60000)
+    xs = xsec.fixed_event([0.0, 0.0, 0.0], probs_cx=0.0)
+    gpu = slpic.Sim([gap], configs.Run(precision=32), xs)
+    ref = oracle.Sim(gap, configs.Run(precision=64), xs)
+    sc = gpu.scalars()
+    v0, dt, dx = sc["v0"], sc["dt"], sc["dx"]
+    rng = np.random.default_rng(11)
+    n = 20000
+    speed = v0 * 10.0 ** rng.uniform(-0.5, 3.0, n)
+    mu = rng.uniform(-1.0, 1.0, n)
+    phi = rng.uniform(0.0, 2.0 * np.pi, n)
+    st = np.sqrt(1.0 - mu * mu)
+    pop = {"cell": rng.integers(64, 192, n).astype(np.int32), "off": rng.uniform(0.0, 1.0, n),
+           "vx": speed * mu, "vy": speed * st * np.cos(phi), "vz": speed * st * np.sin(phi),
+           "id": np.arange(1, n + 1, dtype=np.uint64)}
+    # FP32 values on both sides
+    for k in ("off", "vx", "vy", "vz"):
+        pop[k] = pop[k].astype(np.float32).astype(np.float64)
+    e_none = {k: v[:0] for k, v in pop.items()}
+    for sim in (gpu, ref):
+        sim.load(0, pop)
+        sim.load(1, e_none)
+    # how the markers split between the two paths (vacuum field, a = qE/m)
+    a = 1.602176634e-19 / 9.1093837015e-31 * gap.V / gap.d
+    rt = v0 * a * dt / speed ** 2
+    series = (speed > v0) & (rt < 0.2)
+    print(f"v0 {v0:.3e} m/s, |a| dt {a * dt:.3e} m/s: {series.mean():.2f} of the markers "
+          f"within the series' reach", flush=True)
+    assert 0.2 < series.mean() < 0.9
+    gpu.step(1)
+    ref.step(1)
+    assert gpu.sync() == 0
+    w = compare_populations(gpu.read(0), ref.read(0), 1e-5 * cells, 1e-5, v0, label="electrons")
+    print("flight across speed ratios:", {q: w[q] for q in ("n", "x_cells", "vx", "vy", "vz")})
+    assert w["n"] == n
+    gpu.close()
