@@ -403,6 +403,7 @@ void fill_ctx(slpic_t* h, Ctx<R>& C) {
   C.g = reinterpret_cast<Global*>(w + L.glob);
   C.split = splitting(&h->cfg) ? 1 : 0;
   C.dist = h->dist;
+  C.sorted = h->cfg.resort_period > 0 ? 1 : 0;
   C.occ = h->occ;
   for (int b = 0; b < 2; ++b)
     for (int s = 0; s < 2; ++s) C.wt[b][s] = C.split ? reinterpret_cast<R*>(w + L.wt[b][s]) : nullptr;

@@ -141,7 +141,9 @@ struct InstState {
                     // handle's base, raised with weight splitting by
                     // floor(-log2) of the largest marker flux weight, so
                     // that deposits keep their resolution as weights shrink
-  int32_t pad;
+  int32_t anchor;   // first node of the deposit window for markers not in
+                    // cell order: the window centred on the node that took
+                    // the largest deposit in the step before
 };
 
 // Handle-wide device words.  Per-step state is buffered by generation: a
@@ -207,6 +209,7 @@ struct Ctx {
   int split;                 // weight splitting (split fraction in (0, 1))
   int dist;                  // work distribution of the particle kernel:
                              // 0 equal contiguous shares, 1 claimed runs
+  int sorted;                // markers are cell-sorted now and then (resort_period > 0)
   int occ;                   // waves per SIMD of the FP32 particle kernel's
                              // launch shape (4, 5 or 6)
   int sort_lds1, sort_lds2;  // dynamic LDS bytes of the sort's count and scatter

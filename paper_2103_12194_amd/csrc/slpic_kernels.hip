@@ -776,13 +776,17 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
   __shared__ uint32_t s_pc[MAX_PART];      // electron output partition counts
   __shared__ InstState s_cur;
   __shared__ uint32_t s_bs;
+  __shared__ unsigned long long s_best;    // largest deposit (float bits) << 32 | node
   const int inst = blockIdx.x, t = threadIdx.x;
   IP& P = param(C.ip, inst);
   const int N = P.cells, node = P.node;
   if (t < NEV) s_ev[t] = 0ull;
   if (t < 4) s_cnt[t / 2][t % 2] = 0u;
   if (t < 2) s_mx[t] = 0u;
-  if (t == 0) s_err = 0u;
+  if (t == 0) {
+    s_err = 0u;
+    s_best = 0ull;
+  }
   __syncthreads();
 
   // The loads that do not need the generation go first, so that they
@@ -791,6 +795,7 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
   // in flight together, then cleared) as raw fixed-point differences in
   // LDS with the species totals, and the step's event slots.
   double se = 0.0, si = 0.0;
+  unsigned long long best = 0ull;  // this thread's densest node, as in s_best
   const size_t tn = (size_t)C.total_nodes;
   {
     unsigned long long* acc_e = C.acc + node;
@@ -822,8 +827,19 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
         se += (double)ae[u];
         si += (double)ai[u];
         s_S[i] = (double)ai[u] - (double)ae[u];
+        // nonnegative floats order as their bit patterns
+        const float dep = (float)((double)ae[u] + (double)ai[u]);
+        const unsigned long long key =
+            (unsigned long long)__float_as_uint(dep) << 32 | (unsigned long long)(uint32_t)i;
+        best = key > best ? key : best;
       }
     }
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+      const unsigned long long o = __shfl_xor(best, d);
+      best = o > best ? o : best;
+    }
+    if ((t & (WAVE - 1)) == 0) atomicMax(&s_best, best);
     if (t < NEV * NSLOT) {
       unsigned long long* e = C.ev + (size_t)inst * NEV * NSLOT + t;
       const unsigned long long v = *e;
@@ -966,7 +982,15 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
     nx.step = cur.step + (MODE == MODE_STEP ? 1u : 0u);
     nx.popmode = pm;
     nx.dshift = next_dsh;
-    nx.pad = 0;
+    {
+      // the deposit window of the next step, centred on this step's densest
+      // node (the largest deposit of both species together)
+      const int densest = (int)(uint32_t)s_best;
+      const int top = N + 1 - HWIN;
+      int anc = densest - HWIN / 2;
+      anc = anc > top ? top : anc;
+      nx.anchor = anc < 0 ? 0 : anc;
+    }
     if (C.split) C.maxw[inst] = 0u;
     C.st[sn * C.n_inst + inst] = nx;
     if (MODE == MODE_STEP) {
@@ -1881,21 +1905,27 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
     if (inst != W.inst || sp != W.sp) {
       // new (instance, species): collide what is queued for the old one
       while (q_count > 0) run_queue(q_count < (uint32_t)WAVE ? q_count : (uint32_t)WAVE);
+      // the state of generation g: written by the last tail kernel, read
+      // only while this kernel runs (scalar loads)
+      using CS = const __attribute__((address_space(4))) InstState;
+      CS& S0 = ((CS*)C.st)[(g % 2u) * C.n_inst + inst];
       if (inst != win.inst) {
-        // flush the old deposit window, anchor the new one a quarter window
-        // below the tile's first marker
+        // flush the old deposit window and anchor the new one: for
+        // cell-sorted markers a quarter window below the tile's first
+        // marker (a run's markers follow the cells); otherwise where the
+        // instance deposited most in the step before (the tail kernel's
+        // choice), which a marker of any tile is likely to hit
         if (win.inst >= 0) dep_flush(C, s_hist, win, s_evw);
-        int c0 = first < n ? gbuf(C, bsel, sp).cell(pb + first) : 0;
-        int anchor = c0 - HWIN / 4;
+        int anchor = S0.anchor;
+        if (C.sorted) {
+          const int c0 = first < n ? gbuf(C, bsel, sp).cell(pb + first) : 0;
+          anchor = c0 - HWIN / 4;
+        }
         const int top = P.cells + 1 - HWIN;
         anchor = anchor > top ? top : anchor;
         win.anchor = anchor < 0 ? 0 : anchor;
         win.inst = inst;
       }
-      // the state of generation g: written by the last tail kernel, read
-      // only while this kernel runs (scalar loads)
-      using CS = const __attribute__((address_space(4))) InstState;
-      CS& S0 = ((CS*)C.st)[(g % 2u) * C.n_inst + inst];
       W.inst = inst;
       W.sp = sp;
       W.step = S0.step;
