@@ -25,6 +25,11 @@ template <typename R> hipError_t occupancy_gen(int*, size_t, bool, int);
 // species) pairs
 inline size_t gen_lds_bytes(int n_inst) { return ((size_t)(2 * n_inst + 1) * 4 + 15) & ~size_t(15); }
 // dynamic LDS of the cell sort's count (arrays = 1) and scatter (2) kernels:
+// the tail kernel's dynamic LDS: a double per node (charge, then its sums),
+// then a float per node and one more (deposit, then its prefix sums)
+inline int tail_lds_bytes(int max_cells) {
+  return (max_cells + 1) * (int)sizeof(double) + (max_cells + 2) * (int)sizeof(float);
+}
 // the tile offsets, then arrays of max_cells words
 inline size_t sort_lds_bytes(int n_inst, int max_cells, int arrays) {
   return ((size_t)(2 * n_inst + 1 + 3) & ~size_t(3)) * 4 + (size_t)arrays * max_cells * 4;
@@ -428,7 +433,7 @@ void fill_ctx(slpic_t* h, Ctx<R>& C) {
   C.dep_shift = std::min(want, 60 - bits);
   int maxc = 0;
   for (auto& I : h->inst) maxc = std::max(maxc, I.cells);
-  C.tail_lds = (maxc + 1) * (int)sizeof(double);
+  C.tail_lds = tail_lds_bytes(maxc);
   C.gen_lds = (int)gen_lds_bytes(h->n_inst);
   C.max_cells = maxc;
   C.sort_lds1 = (int)sort_lds_bytes(h->n_inst, maxc, 1);
@@ -795,7 +800,7 @@ int create_impl(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
     lds_max = 65536;
   int maxc = 0;
   for (int i = 0; i < n_inst; ++i) maxc = std::max(maxc, inst[i].cells);
-  if ((size_t)(maxc + 1) * sizeof(double) + 1024 > (size_t)lds_max) {
+  if ((size_t)tail_lds_bytes(maxc) + 1024 > (size_t)lds_max) {
     delete h;
     return fail(nullptr, SLPIC_INVALID_ARG, "too many cells for the device's shared memory per block");
   }

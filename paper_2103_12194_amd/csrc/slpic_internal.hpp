@@ -142,8 +142,8 @@ struct InstState {
                     // floor(-log2) of the largest marker flux weight, so
                     // that deposits keep their resolution as weights shrink
   int32_t anchor;   // first node of the deposit window for markers not in
-                    // cell order: the window centred on the node that took
-                    // the largest deposit in the step before
+                    // cell order: of the windows inside the gap, the one
+                    // that took the largest deposit in the step before
 };
 
 // Handle-wide device words.  Per-step state is buffered by generation: a

@@ -764,11 +764,13 @@ __device__ double inject(const Ctx<R>& C, IP& P, int inst, const InstState& cur,
 // kernel: charge density from the fixed-point deposit, Poisson solve,
 // statistics row, population-control decision for the next step and the
 // generation switch.  Every global load is issued up front; the prefix sums
-// run in LDS (dynamic shared memory of cells + 1 doubles).
+// run in LDS (dynamic shared memory: max_cells + 1 doubles, then
+// max_cells + 2 floats).
 template <typename R, int MODE>
 __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
   extern __shared__ double s_S[];          // rho, then S
-  __shared__ double sh[(TBLOCK / WAVE + 1) * 3];
+  float* s_D = (float*)(s_S + C.max_cells + 1);  // deposit per node, then its prefix sums
+  __shared__ double sh[(TBLOCK / WAVE + 1) * 4];
   __shared__ unsigned long long s_ev[NEV];
   __shared__ uint32_t s_cnt[2][2];         // [in, out][species]
   __shared__ uint32_t s_mx[2];             // fullest output partition per species
@@ -776,7 +778,7 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
   __shared__ uint32_t s_pc[MAX_PART];      // electron output partition counts
   __shared__ InstState s_cur;
   __shared__ uint32_t s_bs;
-  __shared__ unsigned long long s_best;    // largest deposit (float bits) << 32 | node
+  __shared__ unsigned long long s_best;    // next deposit window: (float bits of its deposit) << 32 | first node
   const int inst = blockIdx.x, t = threadIdx.x;
   IP& P = param(C.ip, inst);
   const int N = P.cells, node = P.node;
@@ -795,7 +797,6 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
   // in flight together, then cleared) as raw fixed-point differences in
   // LDS with the species totals, and the step's event slots.
   double se = 0.0, si = 0.0;
-  unsigned long long best = 0ull;  // this thread's densest node, as in s_best
   const size_t tn = (size_t)C.total_nodes;
   {
     unsigned long long* acc_e = C.acc + node;
@@ -827,19 +828,9 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
         se += (double)ae[u];
         si += (double)ai[u];
         s_S[i] = (double)ai[u] - (double)ae[u];
-        // nonnegative floats order as their bit patterns
-        const float dep = (float)((double)ae[u] + (double)ai[u]);
-        const unsigned long long key =
-            (unsigned long long)__float_as_uint(dep) << 32 | (unsigned long long)(uint32_t)i;
-        best = key > best ? key : best;
+        s_D[i] = (float)((double)ae[u] + (double)ai[u]);
       }
     }
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-      const unsigned long long o = __shfl_xor(best, d);
-      best = o > best ? o : best;
-    }
-    if ((t & (WAVE - 1)) == 0) atomicMax(&s_best, best);
     if (t < NEV * NSLOT) {
       unsigned long long* e = C.ev + (size_t)inst * NEV * NSLOT + t;
       const unsigned long long v = *e;
@@ -936,20 +927,27 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
   const int chunk = (N + 1 + TBLOCK - 1) / TBLOCK;
   const int i0 = t * chunk, i1 = min(i0 + chunk, N + 1);
   const double rho0 = s_S[0], rhoN = s_S[N];
-  double loc = 0.0;
-  for (int i = i0; i < i1; ++i)
+  double loc = 0.0, dloc = 0.0;
+  for (int i = i0; i < i1; ++i) {
     if (i >= 1 && i <= N - 1) loc += s_S[i];
-  double v3[3] = {loc, se, si}, ex3[3], tot3[3];
-  block_scan<3, TBLOCK / WAVE>(v3, ex3, tot3, sh);
-  double run = ex3[0], usum = 0.0;
+    dloc += (double)s_D[i];
+  }
+  double v4[4] = {loc, se, si, dloc}, ex4[4], tot4[4];
+  block_scan<4, TBLOCK / WAVE>(v4, ex4, tot4, sh);
+  double run = ex4[0], usum = 0.0, drun = ex4[3];
   for (int i = i0; i < i1; ++i) {
     if (i >= 1 && i <= N - 1) run += s_S[i];
     const double sv = (i == 0) ? 0.0 : (i <= N - 1 ? run : 0.0);
     s_S[i] = sv;
     if (i <= N - 1) usum += sv;
+    // deposit of the nodes before i (rounding keeps the sums ordered)
+    const double d = (double)s_D[i];
+    s_D[i] = (float)drun;
+    drun += d;
   }
+  if (t == 0) s_D[N + 1] = (float)tot4[3];
   double v1[1] = {usum}, ex1[1], tot1[1];
-  block_scan<1, TBLOCK / WAVE>(v1, ex1, tot1, sh);  // its barriers also publish s_S
+  block_scan<1, TBLOCK / WAVE>(v1, ex1, tot1, sh);  // its barriers also publish s_S and s_D
   const double T = tot1[0];
   const double dx = P.dx, k = dx / EPS0;
   const double Ehalf = (-P.V / dx - k * T) / (double)N;
@@ -967,6 +965,26 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
     ER[i] = (R)e;
     if (i <= N - 1) U += s_S[i];
   }
+  {
+    // the next step's deposit window: of the HWIN-node windows inside the
+    // gap, the one that took the largest deposit of both species in this
+    // step (nonnegative floats order as their bit patterns)
+    unsigned long long best = 0ull;
+    const int top = min(i1 - 1, N + 1 - HWIN);
+    for (int a = i0; a <= top; ++a) {
+      const float w = s_D[a + HWIN] - s_D[a];
+      const unsigned long long key =
+          (unsigned long long)__float_as_uint(w) << 32 | (unsigned long long)(uint32_t)a;
+      best = key > best ? key : best;
+    }
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+      const unsigned long long o = __shfl_xor(best, d);
+      best = o > best ? o : best;
+    }
+    if ((t & (WAVE - 1)) == 0 && best) atomicMax(&s_best, best);
+  }
+  __syncthreads();
 
   if (t == 0) {
     const int64_t n[2] = {(int64_t)s_cnt[1][0], (int64_t)s_cnt[1][1]};
@@ -982,15 +1000,7 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
     nx.step = cur.step + (MODE == MODE_STEP ? 1u : 0u);
     nx.popmode = pm;
     nx.dshift = next_dsh;
-    {
-      // the deposit window of the next step, centred on this step's densest
-      // node (the largest deposit of both species together)
-      const int densest = (int)(uint32_t)s_best;
-      const int top = N + 1 - HWIN;
-      int anc = densest - HWIN / 2;
-      anc = anc > top ? top : anc;
-      nx.anchor = anc < 0 ? 0 : anc;
-    }
+    nx.anchor = (int)(uint32_t)s_best;  // 0 where the gap fits one window
     if (C.split) C.maxw[inst] = 0u;
     C.st[sn * C.n_inst + inst] = nx;
     if (MODE == MODE_STEP) {
@@ -1000,8 +1010,8 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
       row.n_e = n[0];
       row.n_i = n[1];
       row.n_in = nin;
-      row.w_e = tot3[1] * unit * wj;
-      row.w_i = tot3[2] * unit * wj;
+      row.w_e = tot4[1] * unit * wj;
+      row.w_i = tot4[2] * unit * wj;
       row.w_j = wj;
       for (int q = 0; q < NEV; ++q) row.ev[q] = (int64_t)s_ev[q];
       row.err = err0 | s_err;
