@@ -26,9 +26,10 @@ template <typename R> hipError_t occupancy_gen(int*, size_t, bool, int);
 inline size_t gen_lds_bytes(int n_inst) { return ((size_t)(2 * n_inst + 1) * 4 + 15) & ~size_t(15); }
 // dynamic LDS of the cell sort's count (arrays = 1) and scatter (2) kernels:
 // the tail kernel's dynamic LDS: a double per node (charge, then its sums),
-// then a float per node and one more (deposit, then its prefix sums)
+// then for each species a float per node and one more (deposit, then its
+// prefix sums)
 inline int tail_lds_bytes(int max_cells) {
-  return (max_cells + 1) * (int)sizeof(double) + (max_cells + 2) * (int)sizeof(float);
+  return (max_cells + 1) * (int)sizeof(double) + 2 * (max_cells + 2) * (int)sizeof(float);
 }
 // the tile offsets, then arrays of max_cells words
 inline size_t sort_lds_bytes(int n_inst, int max_cells, int arrays) {
@@ -826,7 +827,7 @@ int create_impl(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
   std::vector<uint32_t> tiles((size_t)3 * 2 * n_inst, 0u);
   for (int i = 0; i < n_inst; ++i) {
     const int base_shift = cfg->precision == 64 ? h->c64.dep_shift : h->c32.dep_shift;
-    st[i] = InstState{cfg->w_j0, 0u, POP_NONE, base_shift, 0};
+    st[i] = InstState{cfg->w_j0, 0u, POP_NONE, base_shift, {0, 0}};
     st[n_inst + i] = st[i];
     const int64_t ns = inst[i].seed_mode != SLPIC_SEED_NONE ? inst[i].n_seed : 0;
     const int P = L.parts[i];

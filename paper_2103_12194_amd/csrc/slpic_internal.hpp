@@ -23,7 +23,8 @@ constexpr int NSLOT = 1;          // copies of each global deposit node
 constexpr int NPOOL = 8;          // claim counters of the particle kernel's
                                   // work distribution
 constexpr int MAX_DEVICES = 64;   // devices a process can hold a static workspace on
-constexpr int HWIN = 928;         // nodes in a workgroup's LDS deposit window
+constexpr int HWIN = 1856;        // nodes in a workgroup's LDS deposit window
+                                  // (of the species its tile holds)
                                   // (under 30 KB of LDS per workgroup in all,
                                   // with room for the tile offsets of 256
                                   // instances: five workgroups per CU)
@@ -141,9 +142,10 @@ struct InstState {
                     // handle's base, raised with weight splitting by
                     // floor(-log2) of the largest marker flux weight, so
                     // that deposits keep their resolution as weights shrink
-  int32_t anchor;   // first node of the deposit window for markers not in
-                    // cell order: of the windows inside the gap, the one
-                    // that took the largest deposit in the step before
+  int32_t anchor[2];  // first node of each species' deposit window for
+                      // markers not in cell order: of the windows inside
+                      // the gap, the one that took the species' largest
+                      // deposit in the step before
 };
 
 // Handle-wide device words.  Per-step state is buffered by generation: a

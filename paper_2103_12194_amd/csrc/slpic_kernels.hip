@@ -764,13 +764,15 @@ __device__ double inject(const Ctx<R>& C, IP& P, int inst, const InstState& cur,
 // kernel: charge density from the fixed-point deposit, Poisson solve,
 // statistics row, population-control decision for the next step and the
 // generation switch.  Every global load is issued up front; the prefix sums
-// run in LDS (dynamic shared memory: max_cells + 1 doubles, then
-// max_cells + 2 floats).
+// run in LDS (dynamic shared memory: max_cells + 1 doubles, then two rows
+// of max_cells + 2 floats).
 template <typename R, int MODE>
 __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
   extern __shared__ double s_S[];          // rho, then S
-  float* s_D = (float*)(s_S + C.max_cells + 1);  // deposit per node, then its prefix sums
-  __shared__ double sh[(TBLOCK / WAVE + 1) * 4];
+  // [species][max_cells + 2]: deposit per node, then its prefix sums
+  float* s_D = (float*)(s_S + C.max_cells + 1);
+  const int DS = C.max_cells + 2;
+  __shared__ double sh[(TBLOCK / WAVE + 1) * 5];
   __shared__ unsigned long long s_ev[NEV];
   __shared__ uint32_t s_cnt[2][2];         // [in, out][species]
   __shared__ uint32_t s_mx[2];             // fullest output partition per species
@@ -778,7 +780,7 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
   __shared__ uint32_t s_pc[MAX_PART];      // electron output partition counts
   __shared__ InstState s_cur;
   __shared__ uint32_t s_bs;
-  __shared__ unsigned long long s_best;    // next deposit window: (float bits of its deposit) << 32 | first node
+  __shared__ unsigned long long s_best[2];  // next deposit windows: (float bits of the deposit) << 32 | first node
   const int inst = blockIdx.x, t = threadIdx.x;
   IP& P = param(C.ip, inst);
   const int N = P.cells, node = P.node;
@@ -787,7 +789,7 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
   if (t < 2) s_mx[t] = 0u;
   if (t == 0) {
     s_err = 0u;
-    s_best = 0ull;
+    s_best[0] = s_best[1] = 0ull;
   }
   __syncthreads();
 
@@ -828,7 +830,8 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
         se += (double)ae[u];
         si += (double)ai[u];
         s_S[i] = (double)ai[u] - (double)ae[u];
-        s_D[i] = (float)((double)ae[u] + (double)ai[u]);
+        s_D[i] = (float)(double)ae[u];
+        s_D[DS + i] = (float)(double)ai[u];
       }
     }
     if (t < NEV * NSLOT) {
@@ -927,25 +930,31 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
   const int chunk = (N + 1 + TBLOCK - 1) / TBLOCK;
   const int i0 = t * chunk, i1 = min(i0 + chunk, N + 1);
   const double rho0 = s_S[0], rhoN = s_S[N];
-  double loc = 0.0, dloc = 0.0;
+  double loc = 0.0, dle = 0.0, dli = 0.0;
   for (int i = i0; i < i1; ++i) {
     if (i >= 1 && i <= N - 1) loc += s_S[i];
-    dloc += (double)s_D[i];
+    dle += (double)s_D[i];
+    dli += (double)s_D[DS + i];
   }
-  double v4[4] = {loc, se, si, dloc}, ex4[4], tot4[4];
-  block_scan<4, TBLOCK / WAVE>(v4, ex4, tot4, sh);
-  double run = ex4[0], usum = 0.0, drun = ex4[3];
+  double v5[5] = {loc, se, si, dle, dli}, ex5[5], tot5[5];
+  block_scan<5, TBLOCK / WAVE>(v5, ex5, tot5, sh);
+  double run = ex5[0], usum = 0.0, drun_e = ex5[3], drun_i = ex5[4];
   for (int i = i0; i < i1; ++i) {
     if (i >= 1 && i <= N - 1) run += s_S[i];
     const double sv = (i == 0) ? 0.0 : (i <= N - 1 ? run : 0.0);
     s_S[i] = sv;
     if (i <= N - 1) usum += sv;
     // deposit of the nodes before i (rounding keeps the sums ordered)
-    const double d = (double)s_D[i];
-    s_D[i] = (float)drun;
-    drun += d;
+    const double de = (double)s_D[i], di = (double)s_D[DS + i];
+    s_D[i] = (float)drun_e;
+    s_D[DS + i] = (float)drun_i;
+    drun_e += de;
+    drun_i += di;
   }
-  if (t == 0) s_D[N + 1] = (float)tot4[3];
+  if (t == 0) {
+    s_D[N + 1] = (float)tot5[3];
+    s_D[DS + N + 1] = (float)tot5[4];
+  }
   double v1[1] = {usum}, ex1[1], tot1[1];
   block_scan<1, TBLOCK / WAVE>(v1, ex1, tot1, sh);  // its barriers also publish s_S and s_D
   const double T = tot1[0];
@@ -965,14 +974,16 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
     ER[i] = (R)e;
     if (i <= N - 1) U += s_S[i];
   }
-  {
-    // the next step's deposit window: of the HWIN-node windows inside the
-    // gap, the one that took the largest deposit of both species in this
-    // step (nonnegative floats order as their bit patterns)
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp) {
+    // the next step's deposit window of each species: of the HWIN-node
+    // windows inside the gap, the one that took the species' largest
+    // deposit in this step (nonnegative floats order as their bit patterns)
+    const float* D = s_D + sp * DS;
     unsigned long long best = 0ull;
     const int top = min(i1 - 1, N + 1 - HWIN);
     for (int a = i0; a <= top; ++a) {
-      const float w = s_D[a + HWIN] - s_D[a];
+      const float w = D[a + HWIN] - D[a];
       const unsigned long long key =
           (unsigned long long)__float_as_uint(w) << 32 | (unsigned long long)(uint32_t)a;
       best = key > best ? key : best;
@@ -982,7 +993,7 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
       const unsigned long long o = __shfl_xor(best, d);
       best = o > best ? o : best;
     }
-    if ((t & (WAVE - 1)) == 0 && best) atomicMax(&s_best, best);
+    if ((t & (WAVE - 1)) == 0 && best) atomicMax(&s_best[sp], best);
   }
   __syncthreads();
 
@@ -1000,7 +1011,9 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
     nx.step = cur.step + (MODE == MODE_STEP ? 1u : 0u);
     nx.popmode = pm;
     nx.dshift = next_dsh;
-    nx.anchor = (int)(uint32_t)s_best;  // 0 where the gap fits one window
+    // 0 where the gap fits one window
+    nx.anchor[0] = (int)(uint32_t)s_best[0];
+    nx.anchor[1] = (int)(uint32_t)s_best[1];
     if (C.split) C.maxw[inst] = 0u;
     C.st[sn * C.n_inst + inst] = nx;
     if (MODE == MODE_STEP) {
@@ -1010,8 +1023,8 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
       row.n_e = n[0];
       row.n_i = n[1];
       row.n_in = nin;
-      row.w_e = tot4[1] * unit * wj;
-      row.w_i = tot4[2] * unit * wj;
+      row.w_e = tot5[1] * unit * wj;
+      row.w_i = tot5[2] * unit * wj;
       row.w_j = wj;
       for (int q = 0; q < NEV; ++q) row.ev[q] = (int64_t)s_ev[q];
       row.err = err0 | s_err;
@@ -1027,23 +1040,26 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
 
 // ---------------------------------------------------------------- deposit
 // A workgroup accumulates its markers' fixed-point weights in an LDS window
-// of HWIN nodes per species (the whole grid when it fits), and adds the
-// window to global memory once per instance it worked on, into one of NSLOT
-// copies of each node picked by the workgroup index: the tail kernel sums
-// the copies.  Nodes outside the window go to global memory directly.
+// of HWIN nodes (the whole grid when it fits) for the (instance, species) of
+// its tiles, and adds the window to global memory each time it moves on to
+// another (instance, species), into one of NSLOT copies of each node picked
+// by the workgroup index: the tail kernel sums the copies.  Nodes outside
+// the window, and the few products of the other species (ions from
+// ionization in electron tiles, secondary electrons in ion tiles), go to
+// global memory directly.
 struct DepWin {
-  int inst, anchor;
+  int inst, sp, anchor;
 };
 
 __device__ __forceinline__ void dep_add(const unsigned long long* acc_base, unsigned long long* acc,
-                                        unsigned long long (*hist)[HWIN], const DepWin& w,
+                                        unsigned long long* hist, const DepWin& w,
                                         int sp, int node0, int total_nodes, int cell,
                                         unsigned long long lo, unsigned long long hi) {
   (void)acc_base;
   const int r = cell - w.anchor;
-  if (r >= 0 && r + 1 < HWIN) {
-    if (lo) atomicAdd(&hist[sp][r], lo);
-    if (hi) atomicAdd(&hist[sp][r + 1], hi);
+  if (sp == w.sp && r >= 0 && r + 1 < HWIN) {
+    if (lo) atomicAdd(&hist[r], lo);
+    if (hi) atomicAdd(&hist[r + 1], hi);
   } else {
     const int slot = blockIdx.x % NSLOT;
     unsigned long long* a = acc + ((size_t)sp * NSLOT + slot) * total_nodes + node0 + cell;
@@ -1055,7 +1071,7 @@ __device__ __forceinline__ void dep_add(const unsigned long long* acc_base, unsi
 // Adds the window and the event counts gathered since the last flush (one
 // LDS row per wave) to global memory.  Called by all threads.
 template <typename R>
-__device__ __forceinline__ void dep_flush(const Ctx<R>& C, unsigned long long (*hist)[HWIN], const DepWin& w,
+__device__ __forceinline__ void dep_flush(const Ctx<R>& C, unsigned long long* hist, const DepWin& w,
                           uint32_t (*evw)[NEV]) {
   __syncthreads();
   const int slot = blockIdx.x % NSLOT;
@@ -1071,35 +1087,42 @@ __device__ __forceinline__ void dep_flush(const Ctx<R>& C, unsigned long long (*
   }
   IP& P = param(C.ip, w.inst);
   const int nn = min(HWIN, P.cells + 1 - w.anchor);
-  for (int sp = 0; sp < 2; ++sp) {
-    unsigned long long* dst = C.acc + ((size_t)sp * NSLOT + slot) * C.total_nodes + P.node + w.anchor;
-    for (int i = threadIdx.x; i < nn; i += BLOCK) {
-      const unsigned long long v = hist[sp][i];
-      if (v) {
-        atomicAdd(dst + i, v);
-        hist[sp][i] = 0ull;
-      }
+  unsigned long long* dst = C.acc + ((size_t)w.sp * NSLOT + slot) * C.total_nodes + P.node + w.anchor;
+  for (int i = threadIdx.x; i < nn; i += BLOCK) {
+    const unsigned long long v = hist[i];
+    if (v) {
+      atomicAdd(dst + i, v);
+      hist[i] = 0ull;
     }
   }
   __syncthreads();
 }
 
-// Tile space of generation g: electrons of instance 0, ions of instance 0,
-// electrons of instance 1, ...; an (instance, species) with P partitions
-// gets P * T tiles, T = max_p ceil(n_p / BLOCK), and tile j reads chunk
-// j mod T of partition j / T (partitions in order, so that the tiles of a
-// cell-sorted (instance, species) follow its cells).  Fills s_prefix[k] with
-// the first tile of pair k = 2 instance + species (k = 0 .. 2 n_inst).
+// Tile space of generation g: the electrons of instance 0, 1, ..., then the
+// ions of instance 0, 1, ... (a workgroup's run of tiles then changes
+// species at most once per step, and its deposit window with it); an
+// (instance, species) with P partitions gets P * T tiles, T = max_p
+// ceil(n_p / BLOCK), and tile j reads chunk j mod T of partition j / T
+// (partitions in order, so that the tiles of a cell-sorted (instance,
+// species) follow its cells).  Fills s_prefix[q] with the first tile of
+// position q (q = 0 .. 2 n_inst; pair_at gives its instance and species).
 // Called by all threads; ends with a barrier.
+__device__ __forceinline__ void pair_at(int q, int n_inst, int& inst, int& sp) {
+  sp = q >= n_inst ? 1 : 0;
+  inst = q - sp * n_inst;
+}
+
 template <typename R>
 __device__ void tile_prefix(const Ctx<R>& C, uint32_t g, uint32_t* s_prefix, double* s_scan) {
   const int tid = threadIdx.x, nk = 2 * C.n_inst;
   // per (instance, species): its tile count, set with the partition counts
-  // (by the tail kernel, the cell sort or the host)
+  // (by the tail kernel, the cell sort or the host) at 2 instance + species
   const int per = (nk + BLOCK - 1) / BLOCK;
   uint32_t loc = 0;
   for (int k = tid * per; k < min(nk, (tid + 1) * per); ++k) {
-    const uint32_t tl = C.tiles[(size_t)(g % 3u) * nk + k];
+    int inst, sp;
+    pair_at(k, C.n_inst, inst, sp);
+    const uint32_t tl = C.tiles[(size_t)(g % 3u) * nk + 2 * inst + sp];
     s_prefix[k + 1] = tl;
     loc += tl;
   }
@@ -1231,7 +1254,7 @@ __device__ __forceinline__ void next_output(Work& W, IP& P) {
 // and are stored with them.
 template <typename R, int MODE, bool QUEUE, bool WS>
 __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWin& win,
-                                     unsigned long long (*hist)[HWIN], const LaneOut<R, WS>& o,
+                                     unsigned long long* hist, const LaneOut<R, WS>& o,
                                      uint32_t ev, uint32_t err, uint32_t g, uint32_t bsel,
                                      uint32_t* evw) {
   constexpr int NE = LaneOut<R, WS>::NE, NI = LaneOut<R, WS>::NI;
@@ -1700,7 +1723,7 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
   (void)C_arg;
   const Ctx<R>& C = *reinterpret_cast<const Ctx<R>*>(kernarg_base());
   extern __shared__ uint32_t s_prefix[];  // 2 n_inst + 1 tile offsets (dynamic)
-  __shared__ unsigned long long s_hist[2][HWIN];
+  __shared__ unsigned long long s_hist[HWIN];
   __shared__ uint32_t s_gen;
   __shared__ uint32_t s_run[2];
   __shared__ uint32_t s_claim[7];  // pool, its tiles left and when, the claim's offset and
@@ -1725,7 +1748,7 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
     if (blockIdx.x == 0) C.g->tail_gen = gg;
   }
   if (tid < NWAVE * NEV) s_evw[tid / NEV][tid % NEV] = 0u;
-  for (int i = tid; i < 2 * HWIN; i += BLOCK) s_hist[i / HWIN][i % HWIN] = 0ull;
+  for (int i = tid; i < HWIN; i += BLOCK) s_hist[i] = 0ull;
   __syncthreads();
   const uint32_t g = s_gen;
 
@@ -1848,7 +1871,7 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
       }
     }
   };
-  DepWin win{-1, 0};
+  DepWin win{-1, 0, 0};
   Work W{-1, -1, 0, 0u, POP_NONE, 0, 0, 0u};
   uint32_t q_head = 0, q_count = 0;  // uniform over the wave
   uint32_t* evw = s_evw[wv];          // event counts of this wave since the last flush
@@ -1904,7 +1927,8 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
   for (uint32_t t = run_b; t < run_e; ++t) {
     if (tid == 0 && t + 1u == run_e) claim();
     cur.locate(s_prefix, nk, t);
-    const int k = cur.kc, inst = k >> 1, sp = k & 1;
+    int inst, sp;
+    pair_at(cur.kc, C.n_inst, inst, sp);
     IP& P = param(C.ip, inst);
     int part;
     uint32_t first;
@@ -1919,14 +1943,14 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
       // only while this kernel runs (scalar loads)
       using CS = const __attribute__((address_space(4))) InstState;
       CS& S0 = ((CS*)C.st)[(g % 2u) * C.n_inst + inst];
-      if (inst != win.inst) {
+      {
         // flush the old deposit window and anchor the new one: for
         // cell-sorted markers a quarter window below the tile's first
         // marker (a run's markers follow the cells); otherwise where the
-        // instance deposited most in the step before (the tail kernel's
+        // species deposited most in the step before (the tail kernel's
         // choice), which a marker of any tile is likely to hit
         if (win.inst >= 0) dep_flush(C, s_hist, win, s_evw);
-        int anchor = S0.anchor;
+        int anchor = S0.anchor[sp];
         if (C.sorted) {
           const int c0 = first < n ? gbuf(C, bsel, sp).cell(pb + first) : 0;
           anchor = c0 - HWIN / 4;
@@ -1935,6 +1959,7 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
         anchor = anchor > top ? top : anchor;
         win.anchor = anchor < 0 ? 0 : anchor;
         win.inst = inst;
+        win.sp = sp;
       }
       W.inst = inst;
       W.sp = sp;
@@ -2029,8 +2054,10 @@ __global__ void __launch_bounds__(BLOCK) k_sort_count(Ctx<R> C) {
   int k_open = -1;
   auto flush = [&]() {
     __syncthreads();
-    IP& P = param(C.ip, k_open >> 1);
-    uint32_t* dst = C.sort_hist + (size_t)(k_open & 1) * C.total_nodes + P.node;
+    int oi, os;
+    pair_at(k_open, C.n_inst, oi, os);
+    IP& P = param(C.ip, oi);
+    uint32_t* dst = C.sort_hist + (size_t)os * C.total_nodes + P.node;
     for (int c = tid; c < P.cells; c += BLOCK) {
       const uint32_t v = s_hist[c];
       if (v) {
@@ -2046,7 +2073,8 @@ __global__ void __launch_bounds__(BLOCK) k_sort_count(Ctx<R> C) {
       if (k_open >= 0) flush();
       k_open = cur.kc;
     }
-    const int inst = cur.kc >> 1, sp = cur.kc & 1;
+    int inst, sp;
+    pair_at(cur.kc, C.n_inst, inst, sp);
     IP& P = param(C.ip, inst);
     int part;
     uint32_t first;
@@ -2105,7 +2133,8 @@ __global__ void __launch_bounds__(BLOCK) k_sort_scatter(Ctx<R> C) {
   while (t < t_end) {
     TileCursor cur;
     cur.locate(s_prefix, nk, t);
-    const int k = cur.kc, inst = k >> 1, sp = k & 1;
+    int inst, sp;
+    pair_at(cur.kc, C.n_inst, inst, sp);
     const uint32_t run_end = min(t_end, cur.kend);
     IP& P = param(C.ip, inst);
     const Soa<R> in = gbuf(C, bsel, sp), out = gbuf(C, 1u - bsel, sp);

@@ -5,7 +5,9 @@ the Poisson solve shape the field (Eq. (7) deposit with density weight
 w_p = beta w_j, Sec. III).
 
 This exercises the paths small gaps never reach: deposits outside a
-workgroup's 928-node LDS window, the window re-anchored per instance, the
+workgroup's 1856-node LDS window (of the species its tiles hold; products of
+the other species always go outside), the window re-anchored per (instance,
+species), the
 tail kernel's scans with several nodes per thread (N + 1 > 1024) and its
 second accumulator round (N + 1 > 5120), 8 and 16 output partitions per
 (instance, species), population control at that size, and (with
