@@ -25,6 +25,7 @@ constexpr int NPOOL = 8;          // claim counters of the particle kernel's
 constexpr int MAX_DEVICES = 64;   // devices a process can hold a static workspace on
 constexpr int HWIN = 1856;        // nodes in a workgroup's LDS deposit window
                                   // (of the species its tile holds)
+constexpr uint32_t ANCHOR_PERIOD = 16;  // steps between choices of the windows
                                   // (under 30 KB of LDS per workgroup in all,
                                   // with room for the tile offsets of 256
                                   // instances: five workgroups per CU)

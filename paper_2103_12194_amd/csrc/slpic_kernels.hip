@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "slpic_internal.hpp"
 
@@ -930,31 +931,56 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
   const int chunk = (N + 1 + TBLOCK - 1) / TBLOCK;
   const int i0 = t * chunk, i1 = min(i0 + chunk, N + 1);
   const double rho0 = s_S[0], rhoN = s_S[N];
-  double loc = 0.0, dle = 0.0, dli = 0.0;
-  for (int i = i0; i < i1; ++i) {
-    if (i >= 1 && i <= N - 1) loc += s_S[i];
-    dle += (double)s_D[i];
-    dli += (double)s_D[DS + i];
-  }
-  double v5[5] = {loc, se, si, dle, dli}, ex5[5], tot5[5];
-  block_scan<5, TBLOCK / WAVE>(v5, ex5, tot5, sh);
-  double run = ex5[0], usum = 0.0, drun_e = ex5[3], drun_i = ex5[4];
-  for (int i = i0; i < i1; ++i) {
-    if (i >= 1 && i <= N - 1) run += s_S[i];
-    const double sv = (i == 0) ? 0.0 : (i <= N - 1 ? run : 0.0);
-    s_S[i] = sv;
-    if (i <= N - 1) usum += sv;
-    // deposit of the nodes before i (rounding keeps the sums ordered)
-    const double de = (double)s_D[i], di = (double)s_D[DS + i];
-    s_D[i] = (float)drun_e;
-    s_D[DS + i] = (float)drun_i;
-    drun_e += de;
-    drun_i += di;
-  }
-  if (t == 0) {
-    s_D[N + 1] = (float)tot5[3];
-    s_D[DS + N + 1] = (float)tot5[4];
-  }
+  // the deposit windows of the next step are chosen every ANCHOR_PERIOD
+  // steps (the dense regions move slowly) and carried over in between
+  const bool choose = MODE == MODE_REFRESH || cur.step % ANCHOR_PERIOD == 0u;
+  double wtot[2];  // species totals (fixed point)
+  double usum = 0.0;
+  // the pass, with (D) or without the deposit's prefix sums
+  auto s_pass = [&](auto with_d) {
+    constexpr bool D = decltype(with_d)::value;
+    constexpr int NV = D ? 5 : 3;
+    double v[NV], ex[NV], tot[NV];
+    double loc = 0.0, dle = 0.0, dli = 0.0;
+    for (int i = i0; i < i1; ++i) {
+      if (i >= 1 && i <= N - 1) loc += s_S[i];
+      if (D) {
+        dle += (double)s_D[i];
+        dli += (double)s_D[DS + i];
+      }
+    }
+    v[0] = loc;
+    v[1] = se;
+    v[2] = si;
+    if (D) {
+      v[NV - 2] = dle;
+      v[NV - 1] = dli;
+    }
+    block_scan<NV, TBLOCK / WAVE>(v, ex, tot, sh);
+    double run = ex[0], drun_e = D ? ex[NV - 2] : 0.0, drun_i = D ? ex[NV - 1] : 0.0;
+    for (int i = i0; i < i1; ++i) {
+      if (i >= 1 && i <= N - 1) run += s_S[i];
+      const double sv = (i == 0) ? 0.0 : (i <= N - 1 ? run : 0.0);
+      s_S[i] = sv;
+      if (i <= N - 1) usum += sv;
+      if (D) {
+        // deposit of the nodes before i (rounding keeps the sums ordered)
+        const double de = (double)s_D[i], di = (double)s_D[DS + i];
+        s_D[i] = (float)drun_e;
+        s_D[DS + i] = (float)drun_i;
+        drun_e += de;
+        drun_i += di;
+      }
+    }
+    if (D && t == 0) {
+      s_D[N + 1] = (float)tot[NV - 2];
+      s_D[DS + N + 1] = (float)tot[NV - 1];
+    }
+    wtot[0] = tot[1];
+    wtot[1] = tot[2];
+  };
+  if (choose) s_pass(std::true_type{});
+  else s_pass(std::false_type{});
   double v1[1] = {usum}, ex1[1], tot1[1];
   block_scan<1, TBLOCK / WAVE>(v1, ex1, tot1, sh);  // its barriers also publish s_S and s_D
   const double T = tot1[0];
@@ -974,6 +1000,7 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
     ER[i] = (R)e;
     if (i <= N - 1) U += s_S[i];
   }
+  if (choose) {
 #pragma unroll
   for (int sp = 0; sp < 2; ++sp) {
     // the next step's deposit window of each species: of the HWIN-node
@@ -996,6 +1023,7 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
     if ((t & (WAVE - 1)) == 0 && best) atomicMax(&s_best[sp], best);
   }
   __syncthreads();
+  }
 
   if (t == 0) {
     const int64_t n[2] = {(int64_t)s_cnt[1][0], (int64_t)s_cnt[1][1]};
@@ -1012,8 +1040,8 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
     nx.popmode = pm;
     nx.dshift = next_dsh;
     // 0 where the gap fits one window
-    nx.anchor[0] = (int)(uint32_t)s_best[0];
-    nx.anchor[1] = (int)(uint32_t)s_best[1];
+    nx.anchor[0] = choose ? (int)(uint32_t)s_best[0] : cur.anchor[0];
+    nx.anchor[1] = choose ? (int)(uint32_t)s_best[1] : cur.anchor[1];
     if (C.split) C.maxw[inst] = 0u;
     C.st[sn * C.n_inst + inst] = nx;
     if (MODE == MODE_STEP) {
@@ -1023,8 +1051,8 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
       row.n_e = n[0];
       row.n_i = n[1];
       row.n_in = nin;
-      row.w_e = tot5[1] * unit * wj;
-      row.w_i = tot5[2] * unit * wj;
+      row.w_e = wtot[0] * unit * wj;
+      row.w_i = wtot[1] * unit * wj;
       row.w_j = wj;
       for (int q = 0; q < NEV; ++q) row.ev[q] = (int64_t)s_ev[q];
       row.err = err0 | s_err;
