@@ -174,7 +174,10 @@ size_t slpic_workspace_bytes(const slpic_config* cfg, const slpic_instance* inst
  * copied.  dev_workspace (device, >= slpic_workspace_bytes, 256-byte
  * aligned) and hip_stream (a hipStream_t, NULL = default stream) are
  * borrowed until slpic_destroy.  Seeds each instance, solves its initial
- * field and synchronizes the stream.  On failure *out is NULL. */
+ * field and synchronizes the stream.  On failure *out is NULL.
+ * SLPIC_INVALID_ARG if the device's shared memory per block cannot hold
+ * 16 bytes per node of the largest instance (the per-instance field solve;
+ * about 10,000 cells on a 160 KB device). */
 int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
                  const slpic_xs* xs, void* dev_workspace, size_t ws_bytes,
                  void* hip_stream, slpic_t** out);
