@@ -177,7 +177,9 @@ size_t slpic_workspace_bytes(const slpic_config* cfg, const slpic_instance* inst
  * field and synchronizes the stream.  On failure *out is NULL.
  * SLPIC_INVALID_ARG if the device's shared memory per block cannot hold
  * 16 bytes per node of the largest instance (the per-instance field solve;
- * about 10,000 cells on a 160 KB device). */
+ * about 10,000 cells on a 160 KB device), or if a marker partition would
+ * take 2 GiB or more (capacity above about 1.2e9 markers per instance in
+ * FP32, 7.8e8 in FP64, at 16 partitions). */
 int slpic_create(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
                  const slpic_xs* xs, void* dev_workspace, size_t ws_bytes,
                  void* hip_stream, slpic_t** out);

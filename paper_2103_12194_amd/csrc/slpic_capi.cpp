@@ -117,6 +117,8 @@ bool make_layout(const slpic_config* cfg, const slpic_instance* inst, int n_inst
     // partitions start on marker-chunk boundaries
     int64_t cp = (inst[i].capacity + P - 1) / P + (P > 1 ? BLOCK : 0);
     cp = (cp + CH - 1) / CH * CH;
+    // the kernels address a partition's slots by 32-bit byte offsets
+    if (cp / CH * (int64_t)(CH * (4 + 4 * rs + 8)) > 0x7fffffffll) return false;
     L.parts[i] = P;
     L.cap_p[i] = cp;
     L.seg[i] = cap;
@@ -758,7 +760,7 @@ int create_impl(const slpic_config* cfg, const slpic_instance* inst, int n_inst,
   h->n_inst = n_inst;
   if (!make_layout(cfg, inst, n_inst, xs, h->L)) {
     delete h;
-    return fail(nullptr, SLPIC_INVALID_ARG, "too many tiles");
+    return fail(nullptr, SLPIC_INVALID_ARG, "too many tiles, or a partition of 2 GiB or more");
   }
   if (!dev_workspace || ws_bytes < h->L.total || ((uintptr_t)dev_workspace & 255)) {
     delete h;
@@ -904,7 +906,8 @@ int slpic_create_static(const slpic_config* cfg, const slpic_instance* inst, int
   const std::string v = validate(cfg, inst, n_inst, xs);
   if (!v.empty()) return fail(nullptr, SLPIC_INVALID_ARG, v);
   Layout L;
-  if (!make_layout(cfg, inst, n_inst, xs, L)) return fail(nullptr, SLPIC_INVALID_ARG, "too many tiles");
+  if (!make_layout(cfg, inst, n_inst, xs, L))
+    return fail(nullptr, SLPIC_INVALID_ARG, "too many tiles, or a partition of 2 GiB or more");
   if (L.total > SLPIC_STATIC_WORKSPACE_BYTES)
     return fail(nullptr, SLPIC_WORKSPACE_TOO_SMALL,
                 "the setup needs " + std::to_string(L.total) +

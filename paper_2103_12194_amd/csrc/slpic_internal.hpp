@@ -127,6 +127,35 @@ struct Soa {
   __host__ __device__ uint64_t& id(int64_t s) const { return *(uint64_t*)(chunk(s) + kId + lane(s) * 8); }
 };
 
+// Slot j of one partition as byte offsets from the partition's first chunk.
+// Partitions start on chunk boundaries and the host keeps a partition's
+// bytes under 2^31, so the offsets fit 32 bits and the chunk base can stay
+// in scalar registers (one wave works on one partition at a time).
+template <typename R>
+struct SlotOff {
+  uint32_t o4;  // a 4-byte field's offset: chunk * kChunk + lane * 4
+  uint32_t o8;  // an 8-byte field's: o4 + lane * 4
+  __host__ __device__ explicit SlotOff(uint32_t j) {
+    const uint32_t l4 = (j << 2) & (uint32_t)(4 * CH - 4);
+    // a partition under 2^31 bytes has fewer than 2^24 chunks: a 24-bit
+    // multiply-add
+    o4 = ((j >> 6) & 0xffffffu) * (uint32_t)Soa<R>::kChunk + l4;
+    o8 = o4 + l4;
+  }
+  __host__ __device__ uint32_t oR() const { return sizeof(R) == 4 ? o4 : o8; }
+};
+
+template <typename R>
+struct Part {
+  char* b;  // the partition's first chunk
+  __host__ __device__ int32_t& cell(const SlotOff<R>& q) const { return *(int32_t*)(b + q.o4); }
+  __host__ __device__ R& off(const SlotOff<R>& q) const { return *(R*)(b + Soa<R>::kOff + q.oR()); }
+  __host__ __device__ R& vx(const SlotOff<R>& q) const { return *(R*)(b + Soa<R>::kVx + q.oR()); }
+  __host__ __device__ R& vy(const SlotOff<R>& q) const { return *(R*)(b + Soa<R>::kVy + q.oR()); }
+  __host__ __device__ R& vz(const SlotOff<R>& q) const { return *(R*)(b + Soa<R>::kVz + q.oR()); }
+  __host__ __device__ uint64_t& id(const SlotOff<R>& q) const { return *(uint64_t*)(b + Soa<R>::kId + q.o8); }
+};
+
 // identical layout to the public slpic_stats
 struct StatsRow {
   int64_t step, n_e, n_i, n_in;

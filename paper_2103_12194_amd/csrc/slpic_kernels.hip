@@ -614,6 +614,19 @@ __device__ __forceinline__ Soa<R> gbuf(const Ctx<R>& C, uint32_t b, int sp) {
   return Soa<R>{(char*)(GC*)C.buf[b][sp].p};
 }
 
+// The partition of buffer S that starts at slot first (a multiple of CH),
+// seen from one wave: its first chunk, the same for every lane, goes to
+// scalar registers, so that slot accesses are a scalar base plus a 32-bit
+// lane offset.
+template <typename R>
+__device__ __forceinline__ Part<R> part_of(const Soa<R>& S, int64_t first) {
+  using GC = __attribute__((address_space(1))) char;
+  const uint64_t a = (uint64_t)S.chunk(first);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  return Part<R>{(char*)(GC*)(((uint64_t)hi << 32) | lo)};
+}
+
 // Marker count of an input partition of generation g.  Nothing writes the
 // input slot of the count ring while the particle kernel runs (reservations
 // go to slot g + 1), so it is read through the constant address space, with
@@ -1426,7 +1439,7 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
     for (int d = 32; d >= 1; d >>= 1) mw = fmaxf(mw, __shfl_xor(mw, d));
     if (lane == 0 && mw > 0.0f) atomicMax(C.maxw + inst, __float_as_uint(mw));
   }
-  const Soa<R> oe = gbuf(C, 1 - bsel, 0), oi = gbuf(C, 1 - bsel, 1);
+  const Part<R> oe = part_of(gbuf(C, 1 - bsel, 0), W.pbase), oi = part_of(gbuf(C, 1 - bsel, 1), W.pbase);
   R* const we = WS ? C.wt[1 - bsel][0] : nullptr;
   R* const wi = WS ? C.wt[1 - bsel][1] : nullptr;
   uint32_t pe = __builtin_amdgcn_readfirstlane(base_e) + pre_e;
@@ -1439,14 +1452,14 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
     for (int rep = 0; rep < 2; ++rep) {
       if (rep == 1 && !clone_e[j]) continue;
       if (pe < (uint32_t)P.cap_p) {
-        const int64_t s = W.pbase + pe;
-        oe.cell(s) = o.e[j].cell;
-        oe.off(s) = o.e[j].off;
-        oe.vx(s) = o.e[j].vx;
-        oe.vy(s) = o.e[j].vy;
-        oe.vz(s) = o.e[j].vz;
-        oe.id(s) = rep ? clone_e[j] : o.e[j].id;
-        if (WS) we[s] = o.e[j].w;
+        const SlotOff<R> q(pe);
+        oe.cell(q) = o.e[j].cell;
+        oe.off(q) = o.e[j].off;
+        oe.vx(q) = o.e[j].vx;
+        oe.vy(q) = o.e[j].vy;
+        oe.vz(q) = o.e[j].vz;
+        oe.id(q) = rep ? clone_e[j] : o.e[j].id;
+        if (WS) we[W.pbase + pe] = o.e[j].w;
       } else {
         werr |= ERR_CAPACITY;
       }
@@ -1460,14 +1473,14 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
     for (int rep = 0; rep < 2; ++rep) {
       if (rep == 1 && !clone_i[j]) continue;
       if (pi < (uint32_t)P.cap_p) {
-        const int64_t s = W.pbase + pi;
-        oi.cell(s) = o.i[j].cell;
-        oi.off(s) = o.i[j].off;
-        oi.vx(s) = o.i[j].vx;
-        oi.vy(s) = o.i[j].vy;
-        oi.vz(s) = o.i[j].vz;
-        oi.id(s) = rep ? clone_i[j] : o.i[j].id;
-        if (WS) wi[s] = o.i[j].w;
+        const SlotOff<R> q(pi);
+        oi.cell(q) = o.i[j].cell;
+        oi.off(q) = o.i[j].off;
+        oi.vx(q) = o.i[j].vx;
+        oi.vy(q) = o.i[j].vy;
+        oi.vz(q) = o.i[j].vz;
+        oi.id(q) = rep ? clone_i[j] : o.i[j].id;
+        if (WS) wi[W.pbase + pi] = o.i[j].w;
       } else {
         werr |= ERR_CAPACITY;
       }
@@ -1995,19 +2008,19 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
       W.pop = MODE == MODE_STEP ? S0.popmode : POP_NONE;
       if (WS) W.dshift = MODE == MODE_STEP ? S0.dshift : C.dep_shift;
     }
-    const Soa<R> in = gbuf(C, bsel, sp);
+    const Part<R> in = part_of(gbuf(C, bsel, sp), pb);
 
     // loads inside the partition need not wait for its count
     Mk<R> m;
     if (idx < (uint32_t)P.cap_p) {
-      const int64_t s = pb + idx;
-      m.cell = in.cell(s);
-      m.off = in.off(s);
-      m.vx = in.vx(s);
-      m.vy = in.vy(s);
-      m.vz = in.vz(s);
-      m.id = in.id(s);
-      m.w = WS ? C.wt[bsel][sp][s] : R(1);
+      const SlotOff<R> q(idx);
+      m.cell = in.cell(q);
+      m.off = in.off(q);
+      m.vx = in.vx(q);
+      m.vy = in.vy(q);
+      m.vz = in.vz(q);
+      m.id = in.id(q);
+      m.w = WS ? C.wt[bsel][sp][pb + idx] : R(1);
     }
     LaneOut<R, WS> o;
     o.me = o.mi = 0u;

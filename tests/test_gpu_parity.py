@@ -471,6 +471,27 @@ def test_fp64_flux_through_nodes_matches_oracle(xs_argon):
         slpic.Sim([inst], run, xs_argon).flux(0)
 
 
+
+def test_create_refuses_a_gap_beyond_the_field_solves_shared_memory(xs_argon):
+    """The per-instance field solve keeps 16 bytes per node in shared memory
+    (the charge and its sums in FP64, each species' deposit in FP32): a batch
+    whose largest gap needs more than the device's shared memory per block
+    (a 12,000-cell gap needs 192 KB; gfx950 has 160 KB) is refused at create
+    with INVALID_ARG, and a batch of 8192-cell gaps is accepted."""
+    run = configs.Run(precision=32)
+    small = configs.Instance(d=0.01, p_torr=1.0, V=300.0, cells=128, n_seed=100,
+                             capacity=4096)
+    big = configs.Instance(d=0.01, p_torr=1.0, V=300.0, cells=12000, n_seed=100,
+                           capacity=4096)
+    with pytest.raises(slpic.SlpicError) as ei:
+        slpic.Sim([small, big], run, xs_argon)
+    assert ei.value.code == -1
+    ok = configs.Instance(d=0.01, p_torr=1.0, V=300.0, cells=8192, n_seed=100,
+                          capacity=4096)
+    sim = slpic.Sim([small, ok], run, xs_argon)
+    sim.step(2)
+    assert sim.sync() == 0
+
 def test_bisection_round_of_256_instances_keeps_its_books():
     """The 256-instance bisection round (32 pd x 8 voltages, 64-8192 cells)
     at 1 % of its markers in one handle: every step of every instance keeps
