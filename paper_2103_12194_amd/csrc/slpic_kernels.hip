@@ -1102,8 +1102,11 @@ __device__ __forceinline__ void dep_add(const unsigned long long* acc_base, unsi
     if (lo) atomicAdd(&hist[r], lo);
     if (hi) atomicAdd(&hist[r + 1], hi);
   } else {
+    // the accumulators are global memory: global (not flat) atomics
+    using GU = __attribute__((address_space(1))) unsigned long long;
     const int slot = blockIdx.x % NSLOT;
-    unsigned long long* a = acc + ((size_t)sp * NSLOT + slot) * total_nodes + node0 + cell;
+    unsigned long long* a =
+        (unsigned long long*)((GU*)acc + ((size_t)sp * NSLOT + slot) * total_nodes + node0 + cell);
     if (lo) atomicAdd(a, lo);
     if (hi) atomicAdd(a + 1, hi);
   }
@@ -1128,7 +1131,9 @@ __device__ __forceinline__ void dep_flush(const Ctx<R>& C, unsigned long long* h
   }
   IP& P = param(C.ip, w.inst);
   const int nn = min(HWIN, P.cells + 1 - w.anchor);
-  unsigned long long* dst = C.acc + ((size_t)w.sp * NSLOT + slot) * C.total_nodes + P.node + w.anchor;
+  using GU = __attribute__((address_space(1))) unsigned long long;
+  unsigned long long* dst =
+      (unsigned long long*)((GU*)C.acc + ((size_t)w.sp * NSLOT + slot) * C.total_nodes + P.node + w.anchor);
   for (int i = threadIdx.x; i < nn; i += BLOCK) {
     const unsigned long long v = hist[i];
     if (v) {
