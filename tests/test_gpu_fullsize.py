@@ -161,3 +161,61 @@ def test_fp32_large_gaps_single_step_from_loaded_state(grid, xs_argon):
         rho_o, _, E_o = refs[k].fields()
         assert np.allclose(rho_g, rho_o, rtol=0, atol=1e-6 * np.abs(rho_o).max()), k
         assert np.allclose(E_g, E_o, rtol=0, atol=1e-6 * np.abs(E_o).max()), k
+
+
+# cells, electron cells [lo, hi), ion cells [lo, hi), electrons, ions
+DENSE = [(4096, (3300, 4090), (1000, 1500), 24000, 12000),
+         (2048, (900, 1100), (0, 2048), 20000, 8000),
+         (1024, (100, 300), (600, 900), 12000, 6000)]
+
+
+def test_dense_regions_away_from_the_cathode_match_independent_oracles():
+    """Each species' LDS deposit window sits where that species deposited
+    most (chosen on every field refresh and every 16 steps): here a 4096-cell
+    gap with its electrons packed against the anode (the window then starts
+    at its last possible node) and its ions in the middle, a 2048-cell gap
+    with electrons packed mid-gap, and a 1024-cell gap that fits one window,
+    in one FP64 batch against an oracle per gap for 40 steps (three window
+    choices).  A window reaching past its gap would add into the next gap's
+    nodes; every integer statistic must stay bit-exact every step, the
+    deposit and field within 1e-11, states within 1e-12."""
+    xs = synth.argon_like()
+    insts, pops = [], []
+    for k, (cells, (elo, ehi), (ilo, ihi), ne, ni) in enumerate(DENSE):
+        insts.append(configs.Instance(d=0.01, p_torr=4.7 * cells / 1024, V=300.0 + cells / 10,
+                                      cells=cells, gamma_se=0.2, seed_mode=configs.SEED_NONE,
+                                      capacity=8 * (ne + ni)))
+        e, i = synth.markers.mixed(300 + k, ne, ni, cells, cell_lo=elo, cell_hi=ehi, e_hi=60.0)
+        rng = np.random.default_rng([300 + k, 9])
+        i["cell"] = rng.integers(ilo, ihi, size=ni).astype(np.int32)
+        pops.append((e, i))
+    run = configs.Run(precision=64, w_j0=2e7)
+    print("dense regions away from the cathode", flush=True)
+    gpu = slpic.Sim(insts, run, xs)
+    refs = [oracle.Sim(x, run, xs, instance_index=k) for k, x in enumerate(insts)]
+    for k, (e, i) in enumerate(pops):
+        for sim, kw in ((gpu, {"inst": k}), (refs[k], {})):
+            sim.load(0, e, **kw)
+            sim.load(1, i, **kw)
+    for n in range(40):
+        gpu.step(1)
+        for r in refs:
+            r.step(1)
+        for k in range(len(insts)):
+            sg, so = gpu.stats(inst=k), refs[k].stats()
+            for key in STAT_INT:
+                assert sg[key] == so[key], (n, k, key, sg[key], so[key])
+            assert sg["w_e"] == pytest.approx(so["w_e"], rel=1e-9)
+            assert sg["w_i"] == pytest.approx(so["w_i"], rel=1e-9)
+        if n in (0, 17, 39):
+            for k in range(len(insts)):
+                rho_g, _, E_g = gpu.fields(inst=k)
+                rho_o, _, E_o = refs[k].fields()
+                assert np.allclose(rho_g, rho_o, rtol=0, atol=1e-11 * np.abs(rho_o).max()), (n, k)
+                assert np.allclose(E_g, E_o, rtol=0, atol=1e-11 * np.abs(E_o).max()), (n, k)
+    assert gpu.sync() == 0
+    for k, x in enumerate(insts):
+        v0 = gpu.scalars(k)["v0"]
+        for sp in (0, 1):
+            compare_populations(gpu.read(sp, k), refs[k].read(sp), 1e-12 * x.cells, 1e-12, v0,
+                                label=f"dense inst {k} sp {sp}")
