@@ -798,6 +798,29 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
   const int inst = blockIdx.x, t = threadIdx.x;
   IP& P = param(C.ip, inst);
   const int N = P.cells, node = P.node;
+  // The generation, and what this kernel reads at an index that depends on
+  // it: the state of both generations, both buffer selectors and this
+  // thread's partition count in all three ring slots.  The particle kernel
+  // has finished and nothing writes them before this kernel does, so they
+  // go out first, with the deposit's loads, and are picked once the
+  // generation is known.
+  const uint32_t g = C.g->tail_gen;
+  InstState st_a, st_b;
+  uint32_t bs_a = 0u, bs_b = 0u, err0 = 0u;
+  if (t == 0) {
+    st_a = C.st[inst];
+    st_b = C.st[C.n_inst + inst];
+    bs_a = C.g->bufsel[0];
+    bs_b = C.g->bufsel[1];
+    err0 = C.inst_err[inst];
+  }
+  const int csp = t / MAX_PART, cpart = t % MAX_PART;
+  const bool cown = t < 2 * MAX_PART && cpart < P.parts;
+  uint32_t cnt3[3] = {0u, 0u, 0u};
+  if (cown) {
+#pragma unroll
+    for (int s = 0; s < 3; ++s) cnt3[s] = C.counts[cidx(C.n_inst, (uint32_t)s, inst, csp, cpart)];
+  }
   if (t < NEV) s_ev[t] = 0ull;
   if (t < 4) s_cnt[t / 2][t % 2] = 0u;
   if (t < 2) s_mx[t] = 0u;
@@ -856,22 +879,27 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
     }
   }
   // the generation, then the state, buffer choice and partition counts
-  const uint32_t g = C.g->tail_gen;
   const uint32_t sn = (g + 1) % 2u;
-  uint32_t err0 = 0u;
   if (t == 0) {
-    s_cur = C.st[(g % 2u) * C.n_inst + inst];
-    s_bs = C.g->bufsel[g % 2u];
-    err0 = C.inst_err[inst];
+    // field by field (a select of whole records goes through memory)
+    const bool odd = (g & 1u) != 0u;
+    s_cur.w_j = odd ? st_b.w_j : st_a.w_j;
+    s_cur.step = odd ? st_b.step : st_a.step;
+    s_cur.popmode = odd ? st_b.popmode : st_a.popmode;
+    s_cur.dshift = odd ? st_b.dshift : st_a.dshift;
+    s_cur.anchor[0] = odd ? st_b.anchor[0] : st_a.anchor[0];
+    s_cur.anchor[1] = odd ? st_b.anchor[1] : st_a.anchor[1];
+    s_bs = odd ? bs_b : bs_a;
   }
-  if (t < 2 * MAX_PART) {
-    const int sp = t / MAX_PART, p = t % MAX_PART;
-    if (p < P.parts) {
-      uint32_t* ci = C.counts + cidx(C.n_inst, g % 3u, inst, sp, p);
+  if (cown) {
+    const int sp = csp, p = cpart;
+    {
+      const uint32_t g3 = g % 3u;
       uint32_t* co = C.counts + cidx(C.n_inst, (g + 1) % 3u, inst, sp, p);
       uint32_t* cf = C.counts + cidx(C.n_inst, (g + 2) % 3u, inst, sp, p);
-      const uint32_t cin = *ci;
-      uint32_t c = MODE == MODE_STEP ? *co : cin;
+      const uint32_t cin = g3 == 0u ? cnt3[0] : (g3 == 1u ? cnt3[1] : cnt3[2]);
+      const uint32_t cout = g3 == 0u ? cnt3[1] : (g3 == 1u ? cnt3[2] : cnt3[0]);
+      uint32_t c = MODE == MODE_STEP ? cout : cin;
       if (c > (uint32_t)P.cap_p) {
         atomicOr(C.inst_err + inst, (uint32_t)ERR_CAPACITY);
         atomicOr(&s_err, (uint32_t)ERR_CAPACITY);
@@ -1158,19 +1186,23 @@ __device__ __forceinline__ void pair_at(int q, int n_inst, int& inst, int& sp) {
   inst = q - sp * n_inst;
 }
 
-template <typename R>
-__device__ void tile_prefix(const Ctx<R>& C, uint32_t g, uint32_t* s_prefix, double* s_scan) {
+// Thread t owns positions t * per + j, j < per = ceil(2 n_inst / BLOCK) <=
+// MAXPER; count_of(j, k) gives the tile count of its j-th position k.
+constexpr int MAXPER = (2 * MAX_INST + BLOCK - 1) / BLOCK;
+
+template <typename R, typename F>
+__device__ void tile_prefix_of(const Ctx<R>& C, uint32_t* s_prefix, double* s_scan, F count_of) {
   const int tid = threadIdx.x, nk = 2 * C.n_inst;
-  // per (instance, species): its tile count, set with the partition counts
-  // (by the tail kernel, the cell sort or the host) at 2 instance + species
   const int per = (nk + BLOCK - 1) / BLOCK;
   uint32_t loc = 0;
-  for (int k = tid * per; k < min(nk, (tid + 1) * per); ++k) {
-    int inst, sp;
-    pair_at(k, C.n_inst, inst, sp);
-    const uint32_t tl = C.tiles[(size_t)(g % 3u) * nk + 2 * inst + sp];
-    s_prefix[k + 1] = tl;
-    loc += tl;
+#pragma unroll
+  for (int j = 0; j < MAXPER; ++j) {
+    const int k = tid * per + j;
+    if (j < per && k < nk) {
+      const uint32_t tl = count_of(j, k);
+      s_prefix[k + 1] = tl;
+      loc += tl;
+    }
   }
   double v1[1] = {(double)loc}, ex1[1], tot1[1];
   block_scan<1>(v1, ex1, tot1, s_scan);
@@ -1182,6 +1214,21 @@ __device__ void tile_prefix(const Ctx<R>& C, uint32_t g, uint32_t* s_prefix, dou
     s_prefix[k + 1] = run;
   }
   __syncthreads();
+}
+
+// per (instance, species): its tile count, set with the partition counts
+// (by the tail kernel, the cell sort or the host) at 2 instance + species
+// of ring slot g mod 3
+template <typename R>
+__device__ __forceinline__ const uint32_t* tile_counts(const Ctx<R>& C, uint32_t slot, int k) {
+  int inst, sp;
+  pair_at(k, C.n_inst, inst, sp);
+  return C.tiles + (size_t)slot * 2 * C.n_inst + 2 * inst + sp;
+}
+
+template <typename R>
+__device__ void tile_prefix(const Ctx<R>& C, uint32_t g, uint32_t* s_prefix, double* s_scan) {
+  tile_prefix_of(C, s_prefix, s_scan, [&](int, int k) { return *tile_counts(C, g % 3u, k); });
 }
 
 // Position of tiles in the tile space: a cursor that finds its first tile by
@@ -1785,6 +1832,23 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
   __shared__ R q_w[WS ? NWAVE : 1][WS ? QW : 1];  // flux weights (weight splitting)
 
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+  const int nk = 2 * C.n_inst;
+  // The tile counts of this thread's positions in all three ring slots (for
+  // up to PREPER positions a thread, 256 instances), and both buffer
+  // selectors: nothing writes them while this kernel runs, so they go out
+  // with the generation's load and are picked once it is known (one memory
+  // round trip instead of three before the first claim).
+  constexpr int PREPER = 2;
+  const int per = (nk + BLOCK - 1) / BLOCK;
+  uint32_t pre[3][PREPER];
+#pragma unroll
+  for (int j = 0; j < PREPER; ++j) {
+    const int k = tid * per + j;
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+      pre[s][j] = per <= PREPER && j < per && k < nk ? *tile_counts(C, (uint32_t)s, k) : 0u;
+  }
+  const uint32_t bs0 = C.g->bufsel[0], bs1 = C.g->bufsel[1];
   // the generation to advance from: set by the previous tail kernel, and
   // handed to the next one through tail_gen (tail workgroups cannot read
   // cur_gen, which the first of them to finish moves on)
@@ -1798,10 +1862,13 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
   __syncthreads();
   const uint32_t g = s_gen;
 
-  const int nk = 2 * C.n_inst;
-  tile_prefix(C, g, s_prefix, s_scan);
+  const uint32_t g3 = g % 3u;
+  tile_prefix_of(C, s_prefix, s_scan, [&](int j, int k) {
+    if (j < PREPER && per <= PREPER) return g3 == 0u ? pre[0][j] : (g3 == 1u ? pre[1][j] : pre[2][j]);
+    return *tile_counts(C, g3, k);
+  });
   const uint32_t n_tiles = s_prefix[nk];
-  const uint32_t bsel = C.g->bufsel[g % 2u];
+  const uint32_t bsel = g % 2u ? bs1 : bs0;
 
   // Work distribution.  Tile costs differ widely (electron tiles against ion
   // tiles, collision rates from instance to instance), so equal shares of
