@@ -98,6 +98,9 @@ def parse():
                     help="also compare SLPIC with plain PIC on one gap")
     ap.add_argument("--all-configs", action="store_true",
                     help="also time the single-gap and bisection-round workloads")
+    ap.add_argument("--evolve", type=int, default=None,
+                    help="untimed steps before the warmup (default: max(0, %d - warmup)); "
+                         "e.g. 20000 times the sweep with its glow developed" % EVOLVE)
     return ap.parse_args()
 
 
@@ -386,7 +389,7 @@ def main():
     default_shape = sim.launch_shape() + (sim.work_distribution(),)
     apply_shape(sim, shape)
     # untimed steps that let the seeds spread over their gaps, then the warmup
-    evolve = max(0, EVOLVE - args.warmup)
+    evolve = max(0, EVOLVE - args.warmup) if args.evolve is None else max(0, args.evolve)
     sim.step(evolve)
     sim.step(args.warmup)
     sim.sync()
