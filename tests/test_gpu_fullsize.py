@@ -15,6 +15,8 @@ resort_period 4) the cell sort, each against an independent oracle run per
 instance.
 """
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -63,13 +65,27 @@ def test_large_gaps_with_claimed_runs_match_independent_oracles(resort_period, x
     _large_gaps(resort_period, xs_argon, grid=32, claimed=1)
 
 
-def _large_gaps(resort_period, xs_argon, grid=None, claimed=None):
+def test_large_gaps_with_weight_splitting_match_independent_oracles(xs_argon):
+    """Weight splitting (Sec. III, split fraction 0.3) on the same four gaps:
+    every collision keeps the uncollided part and adds a marker carrying the
+    collided part's flux weight, so each marker deposits its own weight,
+    inside and outside the workgroups' LDS windows.  Capacities at 16 times
+    the loaded markers (the populations grow about tenfold); 8 steps against
+    an oracle per gap, flux weights within 1e-12."""
+    _large_gaps(0, xs_argon, split=0.3, steps=8, cap_factor=16)
+
+
+def _large_gaps(resort_period, xs_argon, grid=None, claimed=None, split=0.0, steps=STEPS,
+                cap_factor=None):
     insts, pops = _setup()
+    if cap_factor is not None:
+        insts = [dataclasses.replace(x, capacity=cap_factor * (len(e["id"]) + len(i["id"])))
+                 for x, (e, i) in zip(insts, pops)]
     # a flux weight at which the markers' space charge moves the field by
     # 0.1-3 % of V/d: about 1e8 times the field tolerance below
-    run = configs.Run(precision=64, w_j0=2e7, resort_period=resort_period)
-    print(f"full-size parity, resort_period={resort_period}, grid={grid}, claimed={claimed}",
-          flush=True)
+    run = configs.Run(precision=64, w_j0=2e7, resort_period=resort_period, split_frac=split)
+    print(f"full-size parity, resort_period={resort_period}, grid={grid}, claimed={claimed}, "
+          f"split={split}", flush=True)
     gpu = slpic.Sim(insts, run, xs_argon)
     if grid is not None:
         gpu.set_launch_shape(grid, 0)
@@ -82,7 +98,8 @@ def _large_gaps(resort_period, xs_argon, grid=None, claimed=None):
             sim.load(0, e, **kw)
             sim.load(1, i, **kw)
     parts = [gpu.partitions(0, k)[0].size for k in range(len(insts))]
-    assert parts == [16, 8, 16, 8], parts
+    if cap_factor is None:
+        assert parts == [16, 8, 16, 8], parts
     for k, x in enumerate(insts):
         E_g, E_o = gpu.fields(inst=k)[2], refs[k].fields()[2]
         vac = x.V / x.d
@@ -90,7 +107,7 @@ def _large_gaps(resort_period, xs_argon, grid=None, claimed=None):
         assert np.abs(E_o + vac).max() > 1e-3 * vac, k
         assert np.allclose(E_g, E_o, rtol=0, atol=1e-11 * np.abs(E_o).max()), k
     roulette = 0
-    for n in range(STEPS):
+    for n in range(steps):
         gpu.step(1)
         for r in refs:
             r.step(1)
@@ -102,7 +119,7 @@ def _large_gaps(resort_period, xs_argon, grid=None, claimed=None):
             assert sg["w_e"] == pytest.approx(so["w_e"], rel=1e-9)
             assert sg["w_i"] == pytest.approx(so["w_i"], rel=1e-9)
             roulette += so["roulette"]
-        if n in (0, STEPS - 1):
+        if n in (0, steps - 1):
             for k in range(len(insts)):
                 rho_g, _, E_g = gpu.fields(inst=k)
                 rho_o, _, E_o = refs[k].fields()
@@ -114,8 +131,9 @@ def _large_gaps(resort_period, xs_argon, grid=None, claimed=None):
         v0 = gpu.scalars(k)["v0"]
         for sp in (0, 1):
             w = compare_populations(gpu.read(sp, k), refs[k].read(sp), 1e-12 * x.cells,
-                                    1e-12, v0, label=f"inst {k} sp {sp}")
-            print("full size", resort_period, k, sp, w)
+                                    1e-12, v0, label=f"inst {k} sp {sp}",
+                                    tol_w=1e-12 if split > 0.0 else None)
+            print("full size", resort_period, split, k, sp, w)
 
 
 @pytest.mark.parametrize("grid", [None, 32])
