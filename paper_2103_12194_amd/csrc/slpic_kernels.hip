@@ -794,7 +794,8 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
   __shared__ uint32_t s_pc[MAX_PART];      // electron output partition counts
   __shared__ InstState s_cur;
   __shared__ uint32_t s_bs;
-  __shared__ unsigned long long s_best[2];  // next deposit windows: (float bits of the deposit) << 32 | first node
+  // the next step's deposit windows: (float bits of the deposit) << 32 | first node
+  __shared__ unsigned long long s_best[2];
   const int inst = blockIdx.x, t = threadIdx.x;
   IP& P = param(C.ip, inst);
   const int N = P.cells, node = P.node;
@@ -1043,27 +1044,27 @@ __global__ void __launch_bounds__(TBLOCK) k_tail(Ctx<R> C) {
   }
   if (choose) {
 #pragma unroll
-  for (int sp = 0; sp < 2; ++sp) {
-    // the next step's deposit window of each species: of the HWIN-node
-    // windows inside the gap, the one that took the species' largest
-    // deposit in this step (nonnegative floats order as their bit patterns)
-    const float* D = s_D + sp * DS;
-    unsigned long long best = 0ull;
-    const int top = min(i1 - 1, N + 1 - HWIN);
-    for (int a = i0; a <= top; ++a) {
-      const float w = D[a + HWIN] - D[a];
-      const unsigned long long key =
-          (unsigned long long)__float_as_uint(w) << 32 | (unsigned long long)(uint32_t)a;
-      best = key > best ? key : best;
-    }
+    for (int sp = 0; sp < 2; ++sp) {
+      // the next step's deposit window of each species: of the HWIN-node
+      // windows inside the gap, the one that took the species' largest
+      // deposit in this step (nonnegative floats order as their bit patterns)
+      const float* D = s_D + sp * DS;
+      unsigned long long best = 0ull;
+      const int top = min(i1 - 1, N + 1 - HWIN);
+      for (int a = i0; a <= top; ++a) {
+        const float w = D[a + HWIN] - D[a];
+        const unsigned long long key =
+            (unsigned long long)__float_as_uint(w) << 32 | (unsigned long long)(uint32_t)a;
+        best = key > best ? key : best;
+      }
 #pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-      const unsigned long long o = __shfl_xor(best, d);
-      best = o > best ? o : best;
+      for (int d = 1; d < WAVE; d <<= 1) {
+        const unsigned long long o = __shfl_xor(best, d);
+        best = o > best ? o : best;
+      }
+      if ((t & (WAVE - 1)) == 0 && best) atomicMax(&s_best[sp], best);
     }
-    if ((t & (WAVE - 1)) == 0 && best) atomicMax(&s_best[sp], best);
-  }
-  __syncthreads();
+    __syncthreads();
   }
 
   if (t == 0) {
@@ -1120,11 +1121,9 @@ struct DepWin {
   int inst, sp, anchor;
 };
 
-__device__ __forceinline__ void dep_add(const unsigned long long* acc_base, unsigned long long* acc,
-                                        unsigned long long* hist, const DepWin& w,
-                                        int sp, int node0, int total_nodes, int cell,
-                                        unsigned long long lo, unsigned long long hi) {
-  (void)acc_base;
+__device__ __forceinline__ void dep_add(unsigned long long* acc, unsigned long long* hist,
+                                        const DepWin& w, int sp, int node0, int total_nodes,
+                                        int cell, unsigned long long lo, unsigned long long hi) {
   const int r = cell - w.anchor;
   if (sp == w.sp && r >= 0 && r + 1 < HWIN) {
     if (lo) atomicAdd(&hist[r], lo);
@@ -1143,8 +1142,8 @@ __device__ __forceinline__ void dep_add(const unsigned long long* acc_base, unsi
 // Adds the window and the event counts gathered since the last flush (one
 // LDS row per wave) to global memory.  Called by all threads.
 template <typename R>
-__device__ __forceinline__ void dep_flush(const Ctx<R>& C, unsigned long long* hist, const DepWin& w,
-                          uint32_t (*evw)[NEV]) {
+__device__ __forceinline__ void dep_flush(const Ctx<R>& C, unsigned long long* hist,
+                                          const DepWin& w, uint32_t (*evw)[NEV]) {
   __syncthreads();
   const int slot = blockIdx.x % NSLOT;
   if (threadIdx.x < NEV) {
@@ -1160,8 +1159,9 @@ __device__ __forceinline__ void dep_flush(const Ctx<R>& C, unsigned long long* h
   IP& P = param(C.ip, w.inst);
   const int nn = min(HWIN, P.cells + 1 - w.anchor);
   using GU = __attribute__((address_space(1))) unsigned long long;
-  unsigned long long* dst =
-      (unsigned long long*)((GU*)C.acc + ((size_t)w.sp * NSLOT + slot) * C.total_nodes + P.node + w.anchor);
+  unsigned long long* dst = (unsigned long long*)((GU*)C.acc +
+                                                  ((size_t)w.sp * NSLOT + slot) * C.total_nodes +
+                                                  P.node + w.anchor);
   for (int i = threadIdx.x; i < nn; i += BLOCK) {
     const unsigned long long v = hist[i];
     if (v) {
@@ -1435,7 +1435,7 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
       R b = beta_fast(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
       if (WS) b *= e.w;
       const uint32_t dbl = clone_e[q] ? 1u : 0u;
-      dep_add(C.acc, C.acc, hist, win, 0, P.node, C.total_nodes, e.cell,
+      dep_add(C.acc, hist, win, 0, P.node, C.total_nodes, e.cell,
               fixed_pt<R>(b * (R(1) - e.off), shift) << dbl, fixed_pt<R>(b * e.off, shift) << dbl);
     }
 #pragma unroll
@@ -1445,7 +1445,7 @@ __device__ __forceinline__ void emit(const Ctx<R>& C, const Work& W, const DepWi
       R b = beta_fast(e.vx * e.vx + e.vy * e.vy + e.vz * e.vz, v0, limited);
       if (WS) b *= e.w;
       const uint32_t dbl = clone_i[q] ? 1u : 0u;
-      dep_add(C.acc, C.acc, hist, win, 1, P.node, C.total_nodes, e.cell,
+      dep_add(C.acc, hist, win, 1, P.node, C.total_nodes, e.cell,
               fixed_pt<R>(b * (R(1) - e.off), shift) << dbl, fixed_pt<R>(b * e.off, shift) << dbl);
     }
   }
