@@ -1995,6 +1995,8 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
     LaneOut<R, WS> o;
     o.me = o.mi = 0u;
     uint32_t ev = 0, err = 0;
+    // the batch's output partition, ahead of the collisions (see the tile's)
+    next_output(W, param(C.ip, W.inst));
     // the appends of other lanes land before these reads (one wave: LDS
     // operations complete in order; the fence keeps the compiler's order)
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -2015,7 +2017,6 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // reads before reuse
     q_head = ring(q_head, n);
     q_count -= n;
-    next_output(W, param(C.ip, W.inst));
     emit<R, MODE, true, WS>(C, W, win, s_hist, o, ev, err, g, bsel, evw);
   };
   // append marker m to the queue at offset off (< QW) past its head
@@ -2094,6 +2095,9 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
       m.id = in.id(q);
       m.w = WS ? C.wt[bsel][sp][pb + idx] : R(1);
     }
+    // this tile's output partition: its hash runs while the loads are in
+    // flight rather than between the flight and the reservation
+    next_output(W, P);
     LaneOut<R, WS> o;
     o.me = o.mi = 0u;
     uint32_t ev = 0, err = 0;
@@ -2105,7 +2109,6 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
       if (cand) q_put(m, q_count + (uint32_t)__popcll(b & lt));
       q_count += (uint32_t)__popcll(b);
     }
-    next_output(W, P);
     emit<R, MODE, false, WS>(C, W, win, s_hist, o, ev, err, g, bsel, evw);
     while (MODE == MODE_STEP && q_count >= (uint32_t)WAVE) run_queue((uint32_t)WAVE);
   }
