@@ -249,6 +249,36 @@ def test_batched_instances_match_independent_oracles(xs_argon):
             assert sg[key] == so[key], (k, key)
 
 
+
+def test_batch_of_more_than_256_instances_matches_independent_oracles(xs_argon):
+    """300 gaps in one FP64 batch: the particle kernel's prologue then holds
+    three or more (instance, species) positions a thread, past what it
+    fetches together with the generation, and loads the rest once the
+    generation is known.  Every tenth gap (different sizes, seeds and
+    population targets) against its own oracle for 12 steps: populations
+    and integer statistics bit-exact."""
+    insts = []
+    for k in range(300):
+        insts.append(_c1_small(n_seed=40 + (k % 7) * 20, n_target=0 if k % 3 else 80,
+                               V=300.0 + (k % 5) * 25.0, capacity=4096))
+    run = configs.Run(precision=64)
+    print("300-instance batch", flush=True)
+    gpu = slpic.Sim(insts, run, xs_argon)
+    picked = list(range(0, 300, 10)) + [299]
+    refs = {k: oracle.Sim(insts[k], run, xs_argon, instance_index=k) for k in picked}
+    gpu.step(12)
+    for r in refs.values():
+        r.step(12)
+    assert gpu.sync() == 0
+    for k, r in refs.items():
+        v0 = gpu.scalars(k)["v0"]
+        for sp in (0, 1):
+            compare_populations(gpu.read(sp, k), r.read(sp), 1e-12 * insts[k].cells, 1e-12, v0,
+                                label=f"inst {k} sp {sp}")
+        sg, so = gpu.stats(inst=k), r.stats()
+        for key in STAT_INT:
+            assert sg[key] == so[key], (k, key)
+
 def test_capacity_overflow_is_reported(xs_argon):
     inst = _c1_small(n_seed=1000, n_target=0, capacity=1000)
     gpu = slpic.Sim([inst], configs.Run(precision=32), xs_argon)
