@@ -175,7 +175,7 @@ struct InstState {
   int32_t anchor[2];  // first node of each species' deposit window for
                       // markers not in cell order: of the windows inside
                       // the gap, the one that took the species' largest
-                      // deposit in the step before
+                      // deposit in the last step the tail kernel chose on
 };
 
 // Handle-wide device words.  Per-step state is buffered by generation: a

@@ -8,7 +8,8 @@
 // markers, and the linear charge deposit in fixed point.  k_tail, one
 // workgroup per instance, then turns the deposit into the charge density,
 // solves the instance's Poisson problem in FP64, writes its statistics row,
-// decides the next step's population control, injects the cathode source
+// decides the next step's population control, injects the cathode source,
+// picks the deposit windows of the next steps (every ANCHOR_PERIOD steps)
 // and advances the generation.
 //
 // Memory layout: markers (int32 cell, R offset in the cell, R v_x, v_y, v_z,
@@ -776,8 +777,9 @@ __device__ double inject(const Ctx<R>& C, IP& P, int inst, const InstState& cur,
 
 // One workgroup of TBLOCK threads per instance, launched after the particle
 // kernel: charge density from the fixed-point deposit, Poisson solve,
-// statistics row, population-control decision for the next step and the
-// generation switch.  Every global load is issued up front; the prefix sums
+// statistics row, population-control decision for the next step, the next
+// deposit windows (every ANCHOR_PERIOD steps) and the generation switch.
+// Every global load is issued up front; the prefix sums
 // run in LDS (dynamic shared memory: max_cells + 1 doubles, then two rows
 // of max_cells + 2 floats).
 template <typename R, int MODE>
@@ -2060,9 +2062,10 @@ __global__ void __launch_bounds__(BLOCK, sizeof(R) == 4 ? OCC : 1) k_gen(Ctx<R> 
       {
         // flush the old deposit window and anchor the new one: for
         // cell-sorted markers a quarter window below the tile's first
-        // marker (a run's markers follow the cells); otherwise where the
-        // species deposited most in the step before (the tail kernel's
-        // choice), which a marker of any tile is likely to hit
+        // marker (a run's markers follow the cells); otherwise the tail
+        // kernel's choice, where the species deposited most in the last
+        // step it chose on (every ANCHOR_PERIOD steps), which a marker of
+        // any tile is likely to hit
         if (win.inst >= 0) dep_flush(C, s_hist, win, s_evw);
         int anchor = S0.anchor[sp];
         if (C.sorted) {
