@@ -132,3 +132,17 @@ def test_split_fraction_is_validated(built, xs_argon):
     n0 = _ws(built, w.instances, r0, xs_argon)
     n1 = _ws(built, w.instances, r1, xs_argon)
     assert n1 > n0
+
+
+def test_partitions_of_2_gib_or_more_are_refused(built, xs_argon):
+    """The kernels address a partition's marker slots by 32-bit byte offsets,
+    so a setup whose partitions would reach 2 GiB is refused (size 0): at
+    16 partitions that is a capacity of about 1.23e9 markers in FP32 (28
+    bytes a slot) and 7.8e8 in FP64 (44 bytes).  Nothing is allocated."""
+    w = configs.c1()
+    for prec, ok, bad in ((32, 1.20e9, 1.26e9), (64, 7.7e8, 8.0e8)):
+        run = configs.Run(precision=prec)
+        good = configs.replace(w.instances[0], capacity=int(ok))
+        over = configs.replace(w.instances[0], capacity=int(bad))
+        assert _ws(built, [good], run, xs_argon) > int(ok) * 4 * (28 if prec == 32 else 44), prec
+        assert _ws(built, [over], run, xs_argon) == 0, prec
